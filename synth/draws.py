@@ -1,0 +1,129 @@
+"""Seeded draws for keys, ciphertexts, tables and request traces.
+
+Every function here returns plain numpy arrays sampled from a numpy
+``Generator`` keyed by ``(seed, stream tag)``.  Nothing here combines the
+draws: the phase, the gadget, the key layout and the test vector are built by
+the two implementations separately.
+
+Distributions
+-------------
+* uniform residues in [0, M) for key masks and encryption masks;
+* binary secrets s in {0,1}^n and z in {0,1}^N (the secret distribution of the
+  single-key CMux with d_- = 0, Sec. 2 item (15));
+* the discrete Gaussian on Z with P(x) proportional to exp(-x^2 / (2 sigma^2)),
+  tail-cut at 12 sigma, for every error term (sigma = 0 gives the noise-free
+  mode used for end-to-end correctness at large t);
+* look-up tables: f(m) uniform on [0, t') for m < t/2 and extended by
+  f(m + t/2) = -f(m) mod t', so that f is nega-cyclic (Sec. 2 item (7),
+  Definition 1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+# 2^31 - 2^17 + 1: prime, = 1 mod 2^17, so it carries negacyclic NTTs of every
+# power-of-two degree up to 2^16.
+Q_DEFAULT = 2147352577
+
+_TAGS = {
+    "s": 1, "z": 2, "bsk_a": 3, "bsk_e": 4, "ksk_a": 5, "ksk_e": 6,
+    "enc_a": 7, "enc_e": 8, "msg": 9, "table": 10, "mix": 11, "arrivals": 12,
+}
+
+
+def _rng(seed: int, tag: str) -> np.random.Generator:
+    return np.random.default_rng([int(seed) & 0xFFFFFFFFFFFFFFFF, _TAGS[tag]])
+
+
+@dataclass(frozen=True)
+class Params:
+    """Ring and gadget parameters shared by every table of one key set."""
+
+    n: int            # LWE dimension
+    N: int            # ring degree (power of two)
+    Q: int = Q_DEFAULT
+    log2_B: int = 7   # blind-rotation gadget base 2^log2_B
+    l: int = 4        # blind-rotation gadget length
+    log2_Bks: int = 4  # key-switch base 2^log2_Bks
+    l_ks: int = 8     # key-switch length (ceil(31 / log2_Bks) makes it exact)
+    sigma: float = 3.2
+    sigma_ks: float = 3.2
+
+    @property
+    def B_ks(self) -> int:
+        return 1 << self.log2_Bks
+
+    def noise_free(self) -> "Params":
+        return replace(self, sigma=0.0, sigma_ks=0.0)
+
+
+# Named workloads.  "tiny": n=64, N=256, k=2, t=16, base 2^8 x 3.
+# "paper_shaped": n=630, N=1024, k=4, t=2^12, base 2^7 x 4, key switch 2^4 x 8.
+PRESETS = {
+    "tiny": dict(params=Params(n=64, N=256, log2_B=8, l=3), t=16, t_out=16, r=2),
+    "paper_shaped": dict(params=Params(n=630, N=1024, log2_B=7, l=4), t=4096, t_out=4096, r=4),
+}
+
+# (t, r) classes of the uneven batch and of the serving trace: q = 2Nr each.
+CLASS_MIX = ((256, 1), (1024, 2), (4096, 4), (16384, 8))
+
+
+def discrete_gaussian(rng: np.random.Generator, sigma: float, size) -> np.ndarray:
+    """Discrete Gaussian on Z (tail-cut at 12 sigma) as int32."""
+    if sigma == 0:
+        return np.zeros(size, dtype=np.int32)
+    tail = int(np.ceil(12 * sigma))
+    support = np.arange(-tail, tail + 1, dtype=np.int64)
+    w = np.exp(-(support.astype(np.float64) ** 2) / (2.0 * sigma * sigma))
+    idx = rng.choice(support.size, size=size, p=w / w.sum())
+    return support[idx].astype(np.int32)
+
+
+def key_draws(p: Params, seed: int) -> dict:
+    """All random material of one key set.
+
+    Shapes: s (n,), z (N,), bsk_a (n, 2l, N), bsk_e (n, 2l, N),
+    ksk_a (N, l_ks, B_ks, n), ksk_e (N, l_ks, B_ks).
+    """
+    n, N, l, Q = p.n, p.N, p.l, p.Q
+    out = {
+        "s": _rng(seed, "s").integers(0, 2, size=n, dtype=np.uint32),
+        "z": _rng(seed, "z").integers(0, 2, size=N, dtype=np.uint32),
+        "bsk_a": _rng(seed, "bsk_a").integers(0, Q, size=(n, 2 * l, N), dtype=np.uint32),
+        "bsk_e": discrete_gaussian(_rng(seed, "bsk_e"), p.sigma, (n, 2 * l, N)),
+        "ksk_a": _rng(seed, "ksk_a").integers(0, Q, size=(N, p.l_ks, p.B_ks, n), dtype=np.uint32),
+        "ksk_e": discrete_gaussian(_rng(seed, "ksk_e"), p.sigma_ks, (N, p.l_ks, p.B_ks)),
+    }
+    return out
+
+
+def enc_draws(n: int, q: int, count: int, seed: int, sigma: float = 3.2) -> dict:
+    """Masks a (count, n) uniform in [0, q) and errors e (count,)."""
+    return {
+        "a": _rng(seed, "enc_a").integers(0, q, size=(count, n), dtype=np.uint32),
+        "e": discrete_gaussian(_rng(seed, "enc_e"), sigma, (count,)),
+    }
+
+
+def messages(t: int, count: int, seed: int) -> np.ndarray:
+    return _rng(seed, "msg").integers(0, t, size=count, dtype=np.uint32)
+
+
+def negacyclic_table(t: int, t_out: int, seed: int) -> np.ndarray:
+    """Random f: Z_t -> Z_t' with f(m + t/2) = -f(m) mod t'."""
+    half = _rng(seed, "table").integers(0, t_out, size=t // 2, dtype=np.int64)
+    f = np.concatenate([half, (-half) % t_out])
+    return f.astype(np.uint32)
+
+
+def class_mix(count: int, seed: int, classes=CLASS_MIX) -> np.ndarray:
+    """Index into ``classes`` drawn uniformly per ciphertext."""
+    return _rng(seed, "mix").integers(0, len(classes), size=count, dtype=np.int32)
+
+
+def poisson_arrivals(rate_per_s: float, count: int, seed: int) -> np.ndarray:
+    """Arrival offsets in nanoseconds of a Poisson process (exponential gaps)."""
+    gaps = _rng(seed, "arrivals").exponential(1.0 / rate_per_s, size=count)
+    return np.cumsum(gaps * 1e9).astype(np.int64)
