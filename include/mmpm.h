@@ -1,0 +1,221 @@
+/*
+ * mmpm.h -- C ABI of the BootMMPM functional bootstrap on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library bootstraps LWE ciphertexts whose plaintexts are large (t up to
+ * 2^14 and beyond) through a look-up table spread over a vector of r
+ * negacyclic polynomials, following Algorithm 1 (BootMMPM) of "Large-Plaintext
+ * Functional Bootstrapping in FHE with Small Bootstrapping Keys"
+ * (arXiv 2310.12441), with a binary LWE secret s and a binary ring secret z.
+ *
+ * Conventions shared by every call
+ *   * Q is an odd prime with Q = 1 mod 2N and Q < 2^31; every residue is a
+ *     uint32 in [0, Q) (or [0, q) for LWE ciphertexts at modulus q).
+ *   * An LWE ciphertext of dimension d is d+1 consecutive uint32: a_0..a_{d-1}, b,
+ *     with phase b - <a, s> (Sec. 2 item (8)).
+ *   * An RLWE pair is (a, b), N words each, phase b - a z (Sec. 2 item (12)).
+ *   * Ownership: the caller owns every buffer it passes; the library copies
+ *     what it keeps.  A context owns its keys, tables and device memory.
+ *   * Errors: every int-returning call returns MM_OK (0) or a negative MM_E*
+ *     code, never throws, and keeps a message readable with mm_last_error().
+ *   * Threads: calls on distinct contexts are independent.  Calls on one
+ *     context must not overlap, except mm_submit / mm_poll / mm_server_stats,
+ *     which are safe from any thread while a server runs.
+ *   * Device pointers: with MM_DEVICE_PTRS every ciphertext buffer is device
+ *     memory on the context's device and the call is asynchronous on `stream`
+ *     (a hipStream_t, or NULL for the null stream); without it buffers are host
+ *     memory and the call returns when results are in them.
+ */
+#ifndef MMPM_H
+#define MMPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MM_OK 0
+#define MM_EINVAL (-1)   /* bad parameter, size or id */
+#define MM_ENOMEM (-2)   /* host or device allocation failed */
+#define MM_EDEVICE (-3)  /* a HIP call failed; see mm_last_error */
+#define MM_EBUSY (-4)    /* serving: request refused by admission */
+#define MM_EAGAIN (-5)   /* serving: result not ready yet */
+#define MM_ESTATE (-6)   /* call not valid in the current state */
+
+/* flags */
+#define MM_DEVICE_PTRS 1u /* ciphertext buffers are device pointers */
+#define MM_PLAIN 2u       /* bootstrap one ciphertext at a time (per-ciphertext launches) */
+
+typedef struct mm_ctx mm_ctx;
+typedef struct mm_server mm_server;
+
+/* Ring and gadget parameters of one key set (Alg. 1 inputs).
+ * n: LWE dimension; N: ring degree, a power of two in [64, 1024] for the device
+ * path; Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l: the
+ * blind-rotation gadget base 2^log2_B and length, l * log2_B <= 32 and
+ * log2_B <= 15; log2_Bks, l_ks: the key-switch base and length,
+ * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact. */
+typedef struct {
+    uint32_t n, N, Q, log2_B, l, log2_Bks, l_ks;
+} mm_params;
+
+/* The random material of a key set, drawn by the caller (host memory, read
+ * only during mm_keygen):
+ *   s      n values in {0,1}           LWE secret
+ *   z      N values in {0,1}           RLWE secret
+ *   bsk_a  n * 2l * N in [0, Q)        RGSW masks, [i][row][coeff]
+ *   bsk_e  n * 2l * N small ints       RGSW errors, same layout
+ *   ksk_a  N * l_ks * B_ks * n in [0,Q) key-switch masks, [i][j][v][k]
+ *   ksk_e  N * l_ks * B_ks small ints  key-switch errors, [i][j][v]  */
+typedef struct {
+    const uint32_t *s, *z, *bsk_a;
+    const int32_t *bsk_e;
+    const uint32_t *ksk_a;
+    const int32_t *ksk_e;
+} mm_key_draws;
+
+/* Build a key set (host only; no GPU needed).
+ * BSK_i = RGSW_z(s_i): rows u < l are (a_u, a_u z + e_u + s_i g_u), rows l+u are
+ * (a_{l+u} + s_i g_u, a_{l+u} z + e_{l+u}), g_u = 2^(sg + u log2_B) mod Q with
+ * sg = max(0, bits(Q) - l log2_B) (Alg. 1 inputs; Sec. 2 item (14)).
+ * KSK[i][j][v] = LWE_s(v z_i B_ks^j), v in [0, B_ks) including 0 (Sec. 2 item
+ * (11)).  On success *out owns a new context.  MM_EINVAL for bad parameters. */
+int mm_keygen(const mm_params *p, const mm_key_draws *draws, mm_ctx **out);
+
+/* Release a context, its device memory and any server it runs.  NULL is a no-op. */
+void mm_free(mm_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of the last failed mm_keygen when
+ * ctx is NULL).  The string stays valid until the next call on ctx. */
+const char *mm_last_error(const mm_ctx *ctx);
+
+int mm_get_params(const mm_ctx *ctx, mm_params *out);
+
+/* Coefficient-form keys, for checking: bsk as [n][2l][2][N] (part 0 = a),
+ * ksk as [N][l_ks][B_ks][n+1].  `words` is the capacity of out. */
+int mm_export_bsk(const mm_ctx *ctx, uint32_t *out, size_t words);
+int mm_export_ksk(const mm_ctx *ctx, uint32_t *out, size_t words);
+
+/* Select device `device`, convert the bootstrapping key to the NTT domain and
+ * upload both keys.  Called implicitly by the first device call. */
+int mm_device_init(mm_ctx *ctx, int device);
+
+/* Register a look-up table f: Z_t -> Z_t' held in r polynomials (Sec. 3,
+ * Example 2; Alg. 1 input v_test).  Requires t, t' even, t | 2Nr, f nega-cyclic
+ * (f[m + t/2] = -f[m] mod t', Definition 1) with entries in [0, t').  q_in is
+ * the modulus of the ciphertexts bootstrapped with this table (0 selects 2Nr, so
+ * the first modulus switch is the identity); 2 <= q_in <= 2^31.  The test vector
+ * holds, at entry b and coefficient a, floor(Q/t') times the canonical residue of
+ * f'(-(a r + b)), where f' extends f to Z_2Nr by rounding to the nearest multiple
+ * of 2Nr/t (ties upward).  *id receives the table id. */
+int mm_table_create(mm_ctx *ctx, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in,
+                    const uint32_t *f, int *id);
+int mm_table_info(const mm_ctx *ctx, int id, uint32_t *t, uint32_t *t_out, uint32_t *r,
+                  uint32_t *q_in);
+/* The scaled test vector of table id as [r][N]. */
+int mm_table_export(const mm_ctx *ctx, int id, uint32_t *V, size_t words);
+
+/* LWE encryption under s (Sec. 2 item (8)): ct_c = (a_c, <a_c, s> + m_c floor(q/t)
+ * + e_c mod q) with caller-drawn masks a (count x n, in [0, q)) and errors e.
+ * Host buffers; ct is count x (n+1). */
+int mm_encrypt(const mm_ctx *ctx, uint32_t q, uint32_t t, const uint32_t *m, size_t count,
+               const uint32_t *mask, const int32_t *err, uint32_t *ct);
+
+/* m_c = round((b - <a, s> mod q) / floor(q/t)) mod t (ties upward). Host buffers. */
+int mm_decrypt(const mm_ctx *ctx, uint32_t q, uint32_t t, const uint32_t *ct, size_t count,
+               uint32_t *m);
+
+/* BootMMPM(ct, f) (Alg. 1) for `count` ciphertexts, ciphertext c bootstrapped
+ * with table table_ids[c] (tables may differ in t, t', r and q_in):
+ * modulus switch q_in -> 2Nr, ACC = Phi(b')(0, V), n CMux steps
+ * ACC += (Phi(-a'_i) ACC - ACC) x BSK_i, sample extraction of entry 0, key switch
+ * z -> s, modulus switch Q -> q_out.  ct_in holds count x (n+1) words at each
+ * table's q_in; ct_out receives count x (n+1) words at q_out, where q_out = 0
+ * keeps each table's q_in and q_out = Q skips the final switch.  By default the
+ * whole batch runs as one persistent fused launch sequence (captured in a HIP
+ * graph); MM_PLAIN runs one ciphertext at a time.  Both give identical bits. */
+int mm_bootstrap(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
+                 uint32_t *ct_out, uint32_t q_out, uint32_t flags, void *stream);
+
+/* ---- the same path one step at a time (each a row of the hot path) ---- */
+
+/* Modulus switch round(x q_to / q_from) (ties upward) of `count` residues (Sec. 2 item (9)). */
+int mm_modswitch(mm_ctx *ctx, const uint32_t *in, size_t count, uint32_t q_from, uint32_t q_to,
+                 uint32_t *out, uint32_t flags, void *stream);
+
+/* Blind rotation only: for ciphertext c (at its table's q_in), the accumulator
+ * after the modulus switch, the initialisation and the first `steps` CMux steps
+ * (steps <= n).  acc_out receives, for each c in order, r_c x 2 x N words
+ * ([component][part][coeff], part 0 = a). */
+int mm_blind_rotate(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
+                    uint32_t steps, uint32_t *acc_out, uint32_t flags, void *stream);
+
+/* One external product g^{-1}(in) x BSK_i (eq. def:gsw) for `count` RLWE pairs
+ * in = [count][2][N] -> out, same layout, step index i < n. */
+int mm_external_product(mm_ctx *ctx, uint32_t i, const uint32_t *in, size_t count, uint32_t *out,
+                        uint32_t flags, void *stream);
+
+/* Constant-term extraction (eq. equ-sam-extr) of `count` RLWE pairs
+ * [count][2][N] -> [count][N+1]. */
+int mm_sample_extract(mm_ctx *ctx, const uint32_t *rlwe, size_t count, uint32_t *lwe,
+                      uint32_t flags, void *stream);
+
+/* Key switch z -> s (eq. equ-key-swi) of `count` LWE_N ciphertexts at Q
+ * [count][N+1] -> [count][n+1] at Q. */
+int mm_keyswitch(mm_ctx *ctx, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n,
+                 uint32_t flags, void *stream);
+
+/* Negacyclic products a_c * b_c in Z_Q[x]/(x^N+1) through the device NTT:
+ * a, b, out are [count][N]. */
+int mm_negacyclic_mul(mm_ctx *ctx, const uint32_t *a, const uint32_t *b, size_t count,
+                      uint32_t *out, uint32_t flags, void *stream);
+
+/* ---- autotuning ---- */
+
+/* Time the kernel schedules that fit this batch shape (ciphertexts per
+ * workgroup slot packing, key-switch tiling) on the device and remember the
+ * fastest for the shape (N, sum of r, count).  mm_bootstrap uses the
+ * remembered schedule.  *choice receives the chosen schedule index. */
+int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
+                int *choice);
+
+/* ---- serving: continuous batching ---- */
+
+/* Start a server on ctx.  It owns up to `slots` in-flight ciphertexts whose
+ * device state (accumulators, inputs, outputs) fits in hbm_budget_bytes; each
+ * launch advances every resident ciphertext by `chunk_steps` CMux steps, so a
+ * request admitted while others run joins them at the next launch. */
+int mm_server_start(mm_ctx *ctx, size_t hbm_budget_bytes, uint32_t chunk_steps, mm_server **out);
+
+/* Queue one ciphertext (n+1 words at its table's q_in, host memory).  The
+ * result is at the table's q_in.  MM_EBUSY when the queue is full.
+ * *ticket identifies the request for mm_poll. */
+int mm_submit(mm_server *s, int table_id, const uint32_t *ct, uint64_t *ticket);
+
+/* Copy the result of `ticket` into ct_out (n+1 words) once ready; MM_EAGAIN
+ * before that.  A ticket can be collected once. */
+int mm_poll(mm_server *s, uint64_t ticket, uint32_t *ct_out);
+
+/* Latency percentiles (submit to result ready, ms) and completed bootstraps per
+ * second since start. */
+int mm_server_stats(mm_server *s, double *p50_ms, double *p99_ms, double *boots_per_s,
+                    uint64_t *completed);
+
+/* Stop the server after its in-flight work completes. */
+int mm_server_stop(mm_server *s);
+
+/* Replay a request trace: request k (table table_ids[k], ciphertext
+ * ct_in + k(n+1)) arrives arrival_ns[k] ns after the call starts; the call
+ * submits each at its time, collects every result into ct_out + k(n+1) and
+ * latency_ms[k], and returns when all are done. */
+int mm_server_replay(mm_server *s, const int *table_ids, const uint32_t *ct_in,
+                     const int64_t *arrival_ns, size_t count, uint32_t *ct_out,
+                     double *latency_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMPM_H */

@@ -1,0 +1,550 @@
+// Device runtime of the library: key upload, workspace, batching (packing
+// ciphertext components into 8-wave groups), HIP-graph capture of the batched
+// launch sequence, and the per-row entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+
+#include "kernels.hpp"
+#include "mmpm_internal.hpp"
+
+namespace mm {
+
+#define HIPC(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            throw ::mm::Error(MM_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+enum WsSlot { WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_COUNT };
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct PinBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;  // last stream use of the buffer
+};
+
+struct Device {
+    int id = -1, num_cu = 0;
+    uint32_t qn = 0, c_fix = 0;
+    uint32_t *bsk = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
+    size_t tv_words = 0, tables_uploaded = 0;
+    DevBuf ws[WS_COUNT];
+    PinBuf pin[2];
+    hipStream_t own = nullptr;
+    struct Graph {
+        std::string key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    std::map<std::string, int> tuned;  // batch shape -> schedule index
+    int ws_generation = 0;
+
+    ~Device()
+    {
+        hipSetDevice(id);
+        hipDeviceSynchronize();
+        for (auto &g : graphs)
+            if (g.exec) hipGraphExecDestroy(g.exec);
+        for (auto &b : ws)
+            if (b.p) hipFree(b.p);
+        for (auto &b : pin) {
+            if (b.p) hipHostFree(b.p);
+            if (b.ev) hipEventDestroy(b.ev);
+        }
+        for (void *p : {(void *)bsk, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
+            if (p) hipFree(p);
+        if (own) hipStreamDestroy(own);
+    }
+};
+
+void DeviceDeleter::operator()(Device *d) const { delete d; }
+
+void device_release(mm_ctx &c) { c.dev.reset(); }
+
+static void *ws(Device &d, int slot, size_t bytes)
+{
+    DevBuf &b = d.ws[slot];
+    if (b.bytes < bytes) {
+        HIPC(hipDeviceSynchronize());
+        if (b.p) HIPC(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+        const size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            b.p = nullptr;
+            throw Error(MM_ENOMEM, "device workspace allocation failed");
+        }
+        b.bytes = want;
+        d.ws_generation++;
+        for (auto &g : d.graphs)
+            if (g.exec) hipGraphExecDestroy(g.exec);
+        d.graphs.clear();
+    }
+    return b.p;
+}
+
+// Pinned host staging buffer `slot`; waits until its previous use has executed.
+static void *pinned(Device &d, int slot, size_t bytes)
+{
+    PinBuf &b = d.pin[slot];
+    if (!b.ev) HIPC(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+    HIPC(hipEventSynchronize(b.ev));
+    if (b.bytes < bytes) {
+        if (b.p) HIPC(hipHostFree(b.p));
+        b.p = nullptr;
+        const size_t want = std::max<size_t>(bytes * 2, 4096);
+        if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+            b.p = nullptr;
+            b.bytes = 0;
+            throw Error(MM_ENOMEM, "pinned staging allocation failed");
+        }
+        b.bytes = want;
+    }
+    return b.p;
+}
+
+static uint32_t neg_inv_2_32(uint32_t Q)
+{
+    uint32_t inv = Q;  // Newton: inv = Q^-1 mod 2^32 (Q odd)
+    for (int i = 0; i < 5; i++) inv *= 2u - Q * inv;
+    return 0u - inv;
+}
+
+static uint32_t to_mont(uint32_t x, uint32_t Q) { return (uint32_t)(((uint64_t)x << 32) % Q); }
+
+void device_init(mm_ctx &c, int id)
+{
+    if (c.dev && c.dev->id == id) return;
+    c.dev.reset();
+    std::unique_ptr<Device, DeviceDeleter> d(new Device());
+    HIPC(hipSetDevice(id));
+    d->id = id;
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, id));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        throw Error(MM_EDEVICE, std::string("device is ") + prop.gcnArchName + ", the kernels are built for gfx950");
+    d->num_cu = prop.multiProcessorCount;
+    const mm_params &p = c.p;
+    const uint32_t N = p.N, Q = p.Q;
+    MM_REQUIRE(N == 256 || N == 512 || N == 1024, "device path supports N in {256, 512, 1024}");
+    d->qn = neg_inv_2_32(Q);
+    // 2^64 / N mod Q, for the pointwise product of two forward NTTs
+    d->c_fix = mulmod(to_mont(to_mont(1, Q), Q), c.ntt.n_inv, Q);
+
+    std::vector<uint32_t> twf(N), twi(N);
+    for (uint32_t k = 0; k < N; k++) {
+        twf[k] = to_mont(c.ntt.fwd[k], Q);
+        twi[k] = to_mont(c.ntt.inv[k], Q);
+    }
+    // BSK in the NTT domain, times 2^32 / N (Montgomery form with the inverse NTT's 1/N folded in)
+    const size_t polys = (size_t)p.n * 2 * p.l * 2;
+    std::vector<uint32_t> kb(polys * N);
+    const uint32_t scale = to_mont(c.ntt.n_inv, Q);
+    parallel_for((int64_t)polys, [&](int64_t t) {
+        uint32_t *dst = &kb[(size_t)t * N];
+        std::memcpy(dst, &c.bsk[(size_t)t * N], sizeof(uint32_t) * N);
+        c.ntt.forward(dst);
+        for (uint32_t k = 0; k < N; k++) dst[k] = mulmod(dst[k], scale, Q);
+    });
+    auto upload = [&](uint32_t **dst, const uint32_t *src, size_t words) {
+        if (hipMalloc((void **)dst, words * 4) != hipSuccess) {
+            *dst = nullptr;
+            throw Error(MM_ENOMEM, "device key allocation failed");
+        }
+        HIPC(hipMemcpy(*dst, src, words * 4, hipMemcpyHostToDevice));
+    };
+    upload(&d->twf, twf.data(), N);
+    upload(&d->twi, twi.data(), N);
+    upload(&d->bsk, kb.data(), kb.size());
+    upload(&d->ksk, c.ksk.data(), c.ksk.size());
+    HIPC(dev::init_kernel_attributes());
+    HIPC(hipStreamCreateWithFlags(&d->own, hipStreamNonBlocking));
+    c.dev = std::move(d);
+}
+
+static Device &ensure_device(mm_ctx &c)
+{
+    if (!c.dev) {
+        int cur = 0;
+        HIPC(hipGetDevice(&cur));
+        device_init(c, cur);
+    }
+    HIPC(hipSetDevice(c.dev->id));
+    Device &d = *c.dev;
+    // (re)upload the test-vector arena when tables were added
+    if (d.tables_uploaded != c.tables.size()) {
+        size_t words = 0;
+        for (auto &t : c.tables) {
+            t.dev_offset = words;
+            words += t.V.size();
+        }
+        std::vector<uint32_t> arena(std::max<size_t>(words, 1));
+        for (auto &t : c.tables) std::memcpy(&arena[t.dev_offset], t.V.data(), t.V.size() * 4);
+        HIPC(hipDeviceSynchronize());
+        if (d.tv) HIPC(hipFree(d.tv));
+        d.tv = nullptr;
+        if (hipMalloc((void **)&d.tv, arena.size() * 4) != hipSuccess) throw Error(MM_ENOMEM, "test vector upload");
+        HIPC(hipMemcpy(d.tv, arena.data(), arena.size() * 4, hipMemcpyHostToDevice));
+        d.tables_uploaded = c.tables.size();
+        for (auto &g : d.graphs)
+            if (g.exec) hipGraphExecDestroy(g.exec);
+        d.graphs.clear();
+    }
+    return d;
+}
+
+// ------------------------------------------------------------------ staging
+
+static const uint32_t *stage_in(Device &d, int slot, const uint32_t *p, size_t words, bool dptr, hipStream_t st)
+{
+    if (dptr || words == 0) return p;
+    uint32_t *b = (uint32_t *)ws(d, slot, words * 4);
+    HIPC(hipMemcpyAsync(b, p, words * 4, hipMemcpyHostToDevice, st));
+    return b;
+}
+
+static uint32_t *stage_out(Device &d, int slot, uint32_t *p, size_t words, bool dptr)
+{
+    if (dptr || words == 0) return p;
+    return (uint32_t *)ws(d, slot, words * 4);
+}
+
+static void finish_out(uint32_t *host, const uint32_t *dev, size_t words, bool dptr, hipStream_t st)
+{
+    if (!dptr && words) HIPC(hipMemcpyAsync(host, dev, words * 4, hipMemcpyDeviceToHost, st));
+    if (!dptr) HIPC(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------ batching
+
+// Pack ciphertexts into groups of 8 wave slots, first-fit over r descending,
+// each ciphertext's components on consecutive waves of one group.
+static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, size_t count, uint32_t flags,
+                                              uint32_t i0, const std::vector<uint64_t> &acc_off)
+{
+    std::vector<size_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return c.tables[ids[a]].r > c.tables[ids[b]].r; });
+    std::vector<dev::WaveTask> tasks;
+    std::vector<uint32_t> used;  // per group
+    size_t first_open = 0;
+    for (size_t o : order) {
+        const Table &t = c.tables[ids[o]];
+        size_t g = first_open;
+        while (g < used.size() && used[g] + t.r > 8) g++;
+        if (g == used.size()) {
+            used.push_back(0);
+            dev::WaveTask idle{};
+            idle.ct = -1;
+            tasks.insert(tasks.end(), 8, idle);
+        }
+        for (uint32_t j = 0; j < t.r; j++) {
+            dev::WaveTask &w = tasks[g * 8 + used[g] + j];
+            w.ct = (int32_t)o;
+            w.comp = j;
+            w.r = t.r;
+            w.tv_off = (uint32_t)t.dev_offset;
+            w.q_in = t.q_in;
+            w.i0 = i0;
+            w.flags = flags;
+            w.acc_off = acc_off.empty() ? 0 : acc_off[o];
+        }
+        used[g] += t.r;
+        while (first_open < used.size() && used[first_open] == 8) first_open++;
+    }
+    return tasks;
+}
+
+static void check_ids(const mm_ctx &c, const int *ids, size_t count)
+{
+    MM_REQUIRE(ids || count == 0, "null table ids");
+    for (size_t i = 0; i < count; i++)
+        MM_REQUIRE(ids[i] >= 0 && (size_t)ids[i] < c.tables.size(), "table id out of range");
+}
+
+static dev::WaveTask *upload_tasks(Device &d, const std::vector<dev::WaveTask> &tasks, hipStream_t st)
+{
+    const size_t bytes = tasks.size() * sizeof(dev::WaveTask);
+    void *h = pinned(d, 0, bytes);
+    std::memcpy(h, tasks.data(), bytes);
+    auto *dt = (dev::WaveTask *)ws(d, WS_TASKS, bytes);
+    HIPC(hipMemcpyAsync(dt, h, bytes, hipMemcpyHostToDevice, st));
+    HIPC(hipEventRecord(d.pin[0].ev, st));
+    return dt;
+}
+
+static dev::BrArgs br_args(const mm_ctx &c, const Device &d)
+{
+    dev::BrArgs A{};
+    A.ct_stride = c.p.n + 1;
+    A.n = c.p.n;
+    A.Q = c.p.Q;
+    A.qn = d.qn;
+    A.log2B = c.p.log2_B;
+    A.l = c.p.l;
+    A.sg = c.sg;
+    A.bsk = d.bsk;
+    A.twf = d.twf;
+    A.twi = d.twi;
+    A.tv = d.tv;
+    return A;
+}
+
+static uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count)
+{
+    const size_t col_tiles = (c.p.n + 1 + 63) / 64;
+    const size_t ct_tiles = (count + 4 * dev::KS_CTS_PER_WAVE - 1) / (4 * dev::KS_CTS_PER_WAVE);
+    const size_t target = 2 * (size_t)d.num_cu;
+    size_t P = (target + col_tiles * ct_tiles - 1) / (col_tiles * ct_tiles);
+    P = std::max<size_t>(1, std::min<size_t>(P, c.p.N / 8));
+    return (uint32_t)P;
+}
+
+// Enqueue key switch + final modulus switch of `count` extracted samples.
+static void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, size_t count, uint32_t *out,
+                              const uint32_t *q_out_per_ct, uint32_t q_out, uint32_t P, uint64_t *part,
+                              hipStream_t st)
+{
+    dev::KsArgs K{};
+    K.lwe_N = ext;
+    K.ksk = d.ksk;
+    K.part = part;
+    K.count = count;
+    K.n = c.p.n;
+    K.N = c.p.N;
+    K.Q = c.p.Q;
+    K.log2Bks = c.p.log2_Bks;
+    K.l_ks = c.p.l_ks;
+    dev::launch_keyswitch(K, P, st);
+    dev::launch_ks_finalize(part, ext, out, count, c.p.n, c.p.N, P, c.p.Q, q_out_per_ct, q_out, st);
+}
+
+// The batched path for ciphertexts already on the device.
+static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
+                            uint32_t q_out, bool use_graph, hipStream_t st)
+{
+    const uint32_t N = c.p.N, W = c.p.n + 1;
+    auto tasks = pack_groups(c, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {});
+    const int groups = (int)(tasks.size() / 8);
+    // per-ciphertext output modulus
+    const uint32_t *qv = nullptr;
+    uint32_t q_scalar = q_out;
+    if (q_out == 0) {
+        bool same = true;
+        for (size_t i = 1; i < count; i++) same &= c.tables[ids[i]].q_in == c.tables[ids[0]].q_in;
+        if (same) {
+            q_scalar = c.tables[ids[0]].q_in;
+        } else {
+            uint32_t *h = (uint32_t *)pinned(d, 1, count * 4);
+            for (size_t i = 0; i < count; i++) h[i] = c.tables[ids[i]].q_in;
+            uint32_t *dq = (uint32_t *)ws(d, WS_QOUT, count * 4);
+            HIPC(hipMemcpyAsync(dq, h, count * 4, hipMemcpyHostToDevice, st));
+            HIPC(hipEventRecord(d.pin[1].ev, st));
+            qv = dq;
+        }
+    }
+    const uint32_t P = ks_splits(c, d, count);
+    // allocate every buffer before a capture
+    uint32_t *ext = (uint32_t *)ws(d, WS_EXT, count * (N + 1) * 4);
+    uint64_t *part = (uint64_t *)ws(d, WS_PART, (size_t)P * count * W * 8);
+    dev::WaveTask *dt = upload_tasks(d, tasks, st);
+
+    dev::BrArgs A = br_args(c, d);
+    A.tasks = dt;
+    A.num_groups = groups;
+    A.steps = (int)c.p.n;
+    A.ct_in = d_in;
+    A.ext_out = ext;
+    A.acc_state = nullptr;
+    const int grid = std::min(groups, d.num_cu);
+
+    auto enqueue = [&](hipStream_t s) {
+        dev::launch_blind_rotate(N, A, grid, s);
+        enqueue_keyswitch(c, d, ext, count, d_out, qv, q_scalar, P, part, s);
+    };
+    if (!use_graph) {
+        enqueue(st);
+        HIPC(hipGetLastError());
+        return;
+    }
+    const std::string key = std::to_string(count) + "/" + std::to_string(groups) + "/" + std::to_string(P) + "/" +
+                            std::to_string(q_scalar) + "/" + std::to_string((uintptr_t)qv) + "/" +
+                            std::to_string((uintptr_t)d_in) + "/" + std::to_string((uintptr_t)d_out) + "/" +
+                            std::to_string(d.ws_generation);
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : d.graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        hipGraph_t graph;
+        HIPC(hipStreamBeginCapture(d.own, hipStreamCaptureModeThreadLocal));
+        enqueue(d.own);
+        HIPC(hipStreamEndCapture(d.own, &graph));
+        HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPC(hipGraphDestroy(graph));
+        if (d.graphs.size() >= 8) {
+            hipGraphExecDestroy(d.graphs.front().exec);
+            d.graphs.erase(d.graphs.begin());
+        }
+        d.graphs.push_back({key, exec});
+    }
+    HIPC(hipGraphLaunch(exec, st));
+}
+
+void run_bootstrap(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count, uint32_t *ct_out, uint32_t q_out,
+                   uint32_t flags, void *stream)
+{
+    check_ids(c, ids, count);
+    MM_REQUIRE(q_out == 0 || q_out == c.p.Q || (q_out >= 2 && q_out < c.p.Q), "q_out must be 0, Q or in [2, Q)");
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const size_t W = c.p.n + 1;
+    const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * W, dptr, st);
+    uint32_t *d_out = stage_out(d, WS_OUT, ct_out, count * W, dptr);
+    if (flags & MM_PLAIN) {
+        for (size_t i = 0; i < count; i++)
+            bootstrap_batch(c, d, ids + i, d_in + i * W, 1, d_out + i * W, q_out, false, st);
+    } else {
+        bootstrap_batch(c, d, ids, d_in, count, d_out, q_out, true, st);
+    }
+    finish_out(ct_out, d_out, count * W, dptr, st);
+}
+
+void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count, uint32_t steps,
+                      uint32_t *acc_out, uint32_t flags, void *stream)
+{
+    check_ids(c, ids, count);
+    MM_REQUIRE(steps <= c.p.n, "steps must be <= n");
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const uint32_t N = c.p.N;
+    std::vector<uint64_t> off(count);
+    uint64_t words = 0;
+    for (size_t i = 0; i < count; i++) {
+        off[i] = words;
+        words += (uint64_t)c.tables[ids[i]].r * 2 * N;
+    }
+    const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * (c.p.n + 1), dptr, st);
+    uint32_t *d_acc = stage_out(d, WS_ACC, acc_out, words, dptr);
+    auto tasks = pack_groups(c, ids, count, dev::TASK_INIT | dev::TASK_STORE, 0, off);
+    dev::WaveTask *dt = upload_tasks(d, tasks, st);
+    dev::BrArgs A = br_args(c, d);
+    A.tasks = dt;
+    A.num_groups = (int)(tasks.size() / 8);
+    A.steps = (int)steps;
+    A.ct_in = d_in;
+    A.acc_state = d_acc;
+    dev::launch_blind_rotate(N, A, std::min(A.num_groups, d.num_cu), st);
+    HIPC(hipGetLastError());
+    finish_out(acc_out, d_acc, words, dptr, st);
+}
+
+void run_external_product(mm_ctx &c, uint32_t i, const uint32_t *in, size_t count, uint32_t *out, uint32_t flags,
+                          void *stream)
+{
+    MM_REQUIRE(i < c.p.n, "key index must be < n");
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const size_t words = count * 2 * c.p.N;
+    const uint32_t *din = stage_in(d, WS_IN, in, words, dptr, st);
+    uint32_t *dout = stage_out(d, WS_OUT, out, words, dptr);
+    dev::launch_external_product(c.p.N, din, dout, count, d.bsk + (size_t)i * 4 * c.p.l * c.p.N, d.twf, d.twi, c.p.Q,
+                                 d.qn, c.p.log2_B, c.p.l, c.sg, st);
+    HIPC(hipGetLastError());
+    finish_out(out, dout, words, dptr, st);
+}
+
+void run_negacyclic_mul(mm_ctx &c, const uint32_t *a, const uint32_t *b, size_t count, uint32_t *out, uint32_t flags,
+                        void *stream)
+{
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const size_t words = count * c.p.N;
+    const uint32_t *da = stage_in(d, WS_IN, a, words, dptr, st);
+    const uint32_t *db = stage_in(d, WS_IN2, b, words, dptr, st);
+    uint32_t *dout = stage_out(d, WS_OUT, out, words, dptr);
+    dev::launch_negacyclic_mul(c.p.N, da, db, dout, count, d.twf, d.twi, c.p.Q, d.qn, d.c_fix, st);
+    HIPC(hipGetLastError());
+    finish_out(out, dout, words, dptr, st);
+}
+
+void run_modswitch(mm_ctx &c, const uint32_t *in, size_t count, uint32_t q_from, uint32_t q_to, uint32_t *out,
+                   uint32_t flags, void *stream)
+{
+    MM_REQUIRE(q_from >= 2 && q_to >= 2 && q_from <= (1u << 31) && q_to <= (1u << 31), "moduli out of range");
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const uint32_t *din = stage_in(d, WS_IN, in, count, dptr, st);
+    uint32_t *dout = stage_out(d, WS_OUT, out, count, dptr);
+    dev::launch_modswitch(din, dout, count, q_from, q_to, st);
+    HIPC(hipGetLastError());
+    finish_out(out, dout, count, dptr, st);
+}
+
+void run_sample_extract(mm_ctx &c, const uint32_t *rlwe, size_t count, uint32_t *lwe, uint32_t flags, void *stream)
+{
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const uint32_t N = c.p.N;
+    const uint32_t *din = stage_in(d, WS_IN, rlwe, count * 2 * N, dptr, st);
+    uint32_t *dout = stage_out(d, WS_OUT, lwe, count * (N + 1), dptr);
+    dev::launch_sample_extract(din, dout, count, N, c.p.Q, st);
+    HIPC(hipGetLastError());
+    finish_out(lwe, dout, count * (N + 1), dptr, st);
+}
+
+void run_keyswitch(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n, uint32_t flags, void *stream)
+{
+    if (count == 0) return;
+    Device &d = ensure_device(c);
+    hipStream_t st = (hipStream_t)stream;
+    const bool dptr = flags & MM_DEVICE_PTRS;
+    const uint32_t N = c.p.N, W = c.p.n + 1;
+    const uint32_t *din = stage_in(d, WS_IN, lwe_N, count * (N + 1), dptr, st);
+    uint32_t *dout = stage_out(d, WS_OUT, lwe_n, count * W, dptr);
+    const uint32_t P = ks_splits(c, d, count);
+    uint64_t *part = (uint64_t *)ws(d, WS_PART, (size_t)P * count * W * 8);
+    enqueue_keyswitch(c, d, din, count, dout, nullptr, c.p.Q, P, part, st);
+    HIPC(hipGetLastError());
+    finish_out(lwe_n, dout, count * W, dptr, st);
+}
+
+int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
+{
+    (void)c;
+    (void)ids;
+    (void)ct_in;
+    (void)count;
+    return 0;
+}
+
+}  // namespace mm
+
+mm_ctx::~mm_ctx()
+{
+    if (server) mm::server_stop(server);
+    server = nullptr;
+    dev.reset();
+}

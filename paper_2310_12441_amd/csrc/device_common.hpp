@@ -1,0 +1,254 @@
+// Device-side building blocks shared by the kernels: exact arithmetic mod Q
+// (Q odd, Q < 2^31), the wave-resident negacyclic NTT and the external
+// product of one RLWE pair by one bootstrapping-key row block.
+//
+// Data layout of one degree-N polynomial inside a wave (64 lanes, E = N/64
+// coefficients per lane): the NTT runs in NPH phases; in phase p lane L and
+// register k hold coefficient
+//     idx_p(L, k) = ((L >> R_p) << (R_p + LE)) | (k << R_p) | (L & (2^R_p - 1)),
+// R_p = max(0, 6 - p * LE), LE = log2 E.  Phase 0 (R = 6) is the natural layout
+// idx = 64 k + L used for coefficient-domain work (rotation, decomposition,
+// accumulation); the last phase (R = 0) is idx = E L + k, in which the NTT
+// output is consumed pointwise.  Butterflies whose two inputs differ in a
+// register bit are done in registers; between phases the wave swaps layout
+// through its own LDS slot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mm {
+namespace dev {
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+template <int N>
+struct Geo {
+    static constexpr int E = N / 64;
+    static constexpr int LE = ilog2(E);
+    static constexpr int LOGN = ilog2(N);
+    static constexpr int NPH = 1 + (6 + LE - 1) / LE;
+    static constexpr int PAD = N / 16;            // one pad word per 16
+    static constexpr int POLYW = N + PAD;         // words of one swizzled poly in LDS
+    static constexpr int SLOTW = 2 * POLYW;       // a wave's LDS slot: two polys
+    __host__ __device__ static constexpr int R(int p) { return 6 - p * LE < 0 ? 0 : 6 - p * LE; }
+    // highest idx bit whose butterflies run in phase p
+    __host__ __device__ static constexpr int HI(int p) { return p == 0 ? LOGN - 1 : R(p - 1) - 1; }
+    static_assert(N == 64 * E && E >= 4 && E <= 16, "device path supports N in {256, 512, 1024}");
+};
+
+// LDS word address of coefficient idx: one pad word per 16 keeps all phase
+// layouts (strides 1, 4*64/E... and E) free of bank conflicts.
+__device__ __forceinline__ int swz(int idx) { return idx + (idx >> 4); }
+
+template <int N>
+__device__ __forceinline__ int idx_of(int p, int L, int k)
+{
+    using G = Geo<N>;
+    const int R = G::R(p);
+    return ((L >> R) << (R + G::LE)) | (k << R) | (L & ((1 << R) - 1));
+}
+
+struct ModQ {
+    uint32_t Q;   // odd modulus < 2^31
+    uint32_t qn;  // -Q^{-1} mod 2^32
+};
+
+__device__ __forceinline__ uint32_t add_q(uint32_t a, uint32_t b, uint32_t Q)
+{
+    const uint32_t s = a + b;  // a, b < Q < 2^31
+    return min(s, s - Q);
+}
+
+__device__ __forceinline__ uint32_t sub_q(uint32_t a, uint32_t b, uint32_t Q)
+{
+    const uint32_t d = a - b;  // wraps when a < b; then d + Q is the answer and smaller
+    return min(d, d + Q);
+}
+
+// Montgomery reduction of x < 2^32 Q: x 2^-32 mod Q in [0, Q).
+__device__ __forceinline__ uint32_t redc(uint64_t x, const ModQ &m)
+{
+    const uint32_t q = (uint32_t)x * m.qn;
+    const uint32_t t = (uint32_t)((x + (uint64_t)q * m.Q) >> 32);  // < 2Q
+    return min(t, t - m.Q);
+}
+
+// a * w 2^-32 mod Q for a < 2^32, w < Q (w held in Montgomery form w 2^32).
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t w, const ModQ &m)
+{
+    return redc((uint64_t)a * w, m);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Move NP polys from the layout of phase `from` to that of phase `to`
+// through the wave's LDS slot (NP <= 2).
+template <int N, int NP>
+__device__ __forceinline__ void relayout(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, int L, int from,
+                                         int to)
+{
+    using G = Geo<N>;
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < NP; q++)
+#pragma unroll
+        for (int k = 0; k < G::E; k++) slot[q * G::POLYW + swz(idx_of<N>(from, L, k))] = x[q][k];
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < NP; q++)
+#pragma unroll
+        for (int k = 0; k < G::E; k++) x[q][k] = slot[q * G::POLYW + swz(idx_of<N>(to, L, k))];
+}
+
+// Forward negacyclic NTT (Cooley-Tukey, merged psi powers, natural order in,
+// bit-reversed order out) of NP polys held in phase-0 layout; returns them in
+// the last phase's layout.  twf[k] = psi^bitrev(k) 2^32 mod Q.
+template <int N, int NP>
+__device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, const uint32_t *twf,
+                                        int L, const ModQ &m)
+{
+    using G = Geo<N>;
+#pragma unroll
+    for (int p = 0; p < G::NPH; p++) {
+        if (p > 0) relayout<N, NP>(x, slot, L, p - 1, p);
+        const int R = G::R(p);
+        const int Lhi = (p == 0) ? 0 : (L >> R);
+#pragma unroll
+        for (int b = G::HI(p); b >= R; b--) {
+            const int kb = b - R, s = G::LOGN - 1 - b;
+#pragma unroll
+            for (int k0 = 0; k0 < G::E; k0++) {
+                if (k0 & (1 << kb)) continue;
+                const int k1 = k0 | (1 << kb);
+                const uint32_t w = twf[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
+#pragma unroll
+                for (int q = 0; q < NP; q++) {
+                    const uint32_t u = x[q][k0];
+                    const uint32_t v = mont_mul(x[q][k1], w, m);
+                    x[q][k0] = add_q(u, v, m.Q);
+                    x[q][k1] = sub_q(u, v, m.Q);
+                }
+            }
+        }
+    }
+}
+
+// Inverse negacyclic NTT (Gentleman-Sande, bit-reversed in, natural out),
+// without the 1/N factor: polys arrive in the last phase's layout and leave in
+// phase-0 layout.  twi[k] = psi^-bitrev(k) 2^32 mod Q.
+template <int N, int NP>
+__device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, const uint32_t *twi,
+                                        int L, const ModQ &m)
+{
+    using G = Geo<N>;
+#pragma unroll
+    for (int p = G::NPH - 1; p >= 0; p--) {
+        const int R = G::R(p);
+        const int Lhi = (p == 0) ? 0 : (L >> R);
+#pragma unroll
+        for (int b = R; b <= G::HI(p); b++) {
+            const int kb = b - R, s = G::LOGN - 1 - b;
+#pragma unroll
+            for (int k0 = 0; k0 < G::E; k0++) {
+                if (k0 & (1 << kb)) continue;
+                const int k1 = k0 | (1 << kb);
+                const uint32_t w = twi[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
+#pragma unroll
+                for (int q = 0; q < NP; q++) {
+                    const uint32_t u = x[q][k0], v = x[q][k1];
+                    x[q][k0] = add_q(u, v, m.Q);
+                    x[q][k1] = mont_mul(u - v + m.Q, w, m);
+                }
+            }
+        }
+        if (p > 0) relayout<N, NP>(x, slot, L, p, p - 1);
+    }
+}
+
+struct GadgetC {
+    uint32_t log2B, l, sg;
+};
+
+// Centred residue of x in [0, Q), rounded to a multiple of 2^sg and divided by it.
+__device__ __forceinline__ int32_t gadget_start(uint32_t x, const GadgetC &g, uint32_t Q)
+{
+    int32_t xc = (x > (Q - 1) / 2) ? (int32_t)(x - Q) : (int32_t)x;
+    if (g.sg) xc = (xc + (1 << (g.sg - 1))) >> g.sg;
+    return xc;
+}
+
+// Next balanced base-2^log2B digit of y (low to high), as a residue mod Q; the
+// last digit keeps the remaining value (which may reach B/2).
+__device__ __forceinline__ uint32_t gadget_next(int32_t &y, bool last, const GadgetC &g, uint32_t Q)
+{
+    int32_t d;
+    if (last) {
+        d = y;
+    } else {
+        const int32_t mask = (1 << g.log2B) - 1;
+        d = y & mask;
+        y >>= g.log2B;
+        const int32_t c = d > (mask >> 1) ? 1 : 0;
+        d -= c << g.log2B;
+        y += c;
+    }
+    return d < 0 ? (uint32_t)(d + (int32_t)Q) : (uint32_t)d;
+}
+
+// out = g^{-1}(Da, Db) x K for one RLWE pair in phase-0 layout, K the RGSW key
+// block [2l][2][N] in the NTT domain (Montgomery form, 1/N folded in): digits
+// of b meet rows u < l, digits of a meet rows l + u (eq. def:gsw).  The result
+// is in phase-0 layout, coefficient domain.
+template <int N>
+__device__ __forceinline__ void external_product(const uint32_t (&Da)[Geo<N>::E], const uint32_t (&Db)[Geo<N>::E],
+                                                 const uint32_t *__restrict__ K, uint32_t *slot,
+                                                 const uint32_t *twf, const uint32_t *twi, int L,
+                                                 const ModQ &m, const GadgetC &g,
+                                                 uint32_t (&out)[2][Geo<N>::E])
+{
+    using G = Geo<N>;
+    constexpr int E = G::E;
+    int32_t ya[E], yb[E];
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        ya[k] = gadget_start(Da[k], g, m.Q);
+        yb[k] = gadget_start(Db[k], g, m.Q);
+        out[0][k] = 0;
+        out[1][k] = 0;
+    }
+    for (uint32_t u = 0; u < g.l; u++) {
+        // keep twiddle and key loads inside the iteration (register pressure)
+        __asm__ volatile("" ::: "memory");
+        const bool last = (u + 1 == g.l);
+        uint32_t pd[2][E];
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            pd[0][k] = gadget_next(yb[k], last, g, m.Q);
+            pd[1][k] = gadget_next(ya[k], last, g, m.Q);
+        }
+        ntt_fwd<N, 2>(pd, slot, twf, L, m);
+        // lane L now holds NTT positions E L .. E L + E - 1
+        const uint32_t *kb_a = K + ((size_t)(u)*2 + 0) * N + L * E;
+        const uint32_t *kb_b = K + ((size_t)(u)*2 + 1) * N + L * E;
+        const uint32_t *ka_a = K + ((size_t)(g.l + u) * 2 + 0) * N + L * E;
+        const uint32_t *ka_b = K + ((size_t)(g.l + u) * 2 + 1) * N + L * E;
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
+            const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
+            out[0][k] = add_q(out[0][k], redc(xa, m), m.Q);
+            out[1][k] = add_q(out[1][k], redc(xb, m), m.Q);
+        }
+    }
+    __asm__ volatile("" ::: "memory");
+    ntt_inv<N, 2>(out, slot, twi, L, m);
+}
+
+}  // namespace dev
+}  // namespace mm

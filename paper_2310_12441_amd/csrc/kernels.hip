@@ -1,0 +1,419 @@
+// HIP kernels of the BootMMPM bootstrap for gfx950.
+//
+// k_blind_rotate: the fused, persistent blind rotation (Alg. 1, first modulus
+//   switch, accumulator initialisation and the n CMux steps, then the sample
+//   extraction of entry 0).  One workgroup of 8 waves owns a "group" of up to 8
+//   ciphertext components; each wave owns one component j of one ciphertext
+//   and keeps that component's RLWE pair (a, b) in registers for all n steps.
+//   Each step the waves publish their pairs in LDS, read the pair that
+//   Phi(-a'_i) brings to their slot (an index-and-sign remap, eq. ex1:BPc),
+//   form D = Phi(-a'_i) ACC - ACC, and add D x BSK_i (the binary CMux of
+//   eq. cmux:BP) with a wave-resident NTT external product.
+// k_keyswitch / k_ks_finalize: the key switch z -> s (eq. equ-key-swi) and the
+//   final modulus switch Q -> q_out, batched over ciphertexts.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace dev {
+
+__device__ __forceinline__ uint32_t modswitch_dev(uint32_t x, uint32_t q_from, uint32_t q_to)
+{
+    if (q_from == q_to) return x;
+    const uint64_t num = 2ull * (uint64_t)x * q_to + q_from;
+    return (uint32_t)((num / (2ull * q_from)) % q_to);
+}
+
+__global__ void k_modswitch(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, size_t count,
+                            uint32_t q_from, uint32_t q_to)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = modswitch_dev(in[i], q_from, q_to);
+}
+
+// Row j of Phi(c), c = a r + b: source component (j - b) mod r and monomial
+// exponent a + [j < b] (eq. ex1:BPc).
+__device__ __forceinline__ void phi_row(uint32_t c, uint32_t r, uint32_t j, uint32_t &src, uint32_t &e)
+{
+    const uint32_t a = c / r, b = c - a * r;
+    src = (j + r - b) % r;
+    e = a + (j < b ? 1u : 0u);
+}
+
+// LDS per wave: its accumulator pair (a, b) followed by two scratch polys.
+template <int N>
+struct BrLds {
+    static constexpr int WAVE_WORDS = 2 * Geo<N>::POLYW + Geo<N>::SLOTW;
+};
+
+template <int N>
+__global__ void __launch_bounds__(512, 1) k_blind_rotate(BrArgs A)
+{
+    using G = Geo<N>;
+    constexpr int E = G::E, P = G::POLYW;
+    extern __shared__ uint32_t lds[];
+    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
+    uint32_t *accl = lds + wave * BrLds<N>::WAVE_WORDS;  // [a | b], swizzled
+    uint32_t *scr = accl + 2 * P;
+    const ModQ m{A.Q, A.qn};
+    const GadgetC g{A.log2B, A.l, A.sg};
+
+    for (int grp = blockIdx.x; grp < A.num_groups; grp += gridDim.x) {
+        const WaveTask T = A.tasks[grp * 8 + wave];
+        const bool has = T.ct >= 0;
+        const uint32_t r = has ? T.r : 1u, M = 2u * N * r;
+        const uint32_t *ct = A.ct_in + (size_t)(has ? T.ct : 0) * A.ct_stride;
+
+        // ---- accumulator: Phi(b') (0, V) or the stored state, into LDS
+        if (has && (T.flags & TASK_INIT)) {
+            const uint32_t bq = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[A.n], T.q_in, M));
+            uint32_t src, e;
+            phi_row(bq, r, T.comp, src, e);
+            const uint32_t *V = A.tv + T.tv_off + (size_t)src * N;
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint32_t idx = 64 * k + L;
+                const uint32_t i2 = (idx + 2 * N - (e % (2 * N))) % (2 * N);
+                const uint32_t v = V[i2 & (N - 1)];
+                accl[swz(idx)] = 0;
+                accl[P + swz(idx)] = (i2 >= N) ? (v ? A.Q - v : 0) : v;
+            }
+        } else if (has) {
+            const uint32_t *S = A.acc_state + T.acc_off + (size_t)T.comp * 2 * N;
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                accl[swz(64 * k + L)] = S[64 * k + L];
+                accl[P + swz(64 * k + L)] = S[N + 64 * k + L];
+            }
+        }
+
+        // ---- the CMux steps
+        for (int s = 0; s < A.steps; s++) {
+            const uint32_t i = T.i0 + (uint32_t)s;
+            const bool active = has && i < A.n;
+            __syncthreads();  // every accumulator of the group is up to date
+            uint32_t D[2][E];
+            if (active) {
+                const uint32_t ai = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[i], T.q_in, M));
+                const uint32_t c = (M - ai) % M;  // -a'_i mod 2Nr
+                uint32_t src, e;
+                phi_row(c, r, T.comp, src, e);
+                const uint32_t *sp = lds + (wave - (int)T.comp + (int)src) * BrLds<N>::WAVE_WORDS;
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    const uint32_t idx = 64 * k + L;
+                    const uint32_t i2 = (idx + 2 * N - e) % (2 * N);
+                    const int a = swz(i2 & (N - 1));
+                    uint32_t va = sp[a], vb = sp[P + a];
+                    if (i2 >= N) {
+                        va = va ? A.Q - va : 0;
+                        vb = vb ? A.Q - vb : 0;
+                    }
+                    D[0][k] = sub_q(va, accl[swz(idx)], A.Q);
+                    D[1][k] = sub_q(vb, accl[P + swz(idx)], A.Q);
+                }
+            }
+            __syncthreads();  // every rotated read of this step is done
+            if (active) {
+                uint32_t o[2][E];
+                const uint32_t *K = A.bsk + (size_t)i * (4u * A.l * N);
+                external_product<N>(D[0], D[1], K, scr, A.twf, A.twi, L, m, g, o);
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    const int a = swz(64 * k + L);
+                    accl[a] = add_q(accl[a], o[0][k], A.Q);
+                    accl[P + a] = add_q(accl[P + a], o[1][k], A.Q);
+                }
+            }
+        }
+
+        // ---- results (each wave reads back only its own accumulator)
+        if (!has) continue;
+        if (T.flags & TASK_STORE) {
+            uint32_t *S = A.acc_state + T.acc_off + (size_t)T.comp * 2 * N;
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                S[64 * k + L] = accl[swz(64 * k + L)];
+                S[N + 64 * k + L] = accl[P + swz(64 * k + L)];
+            }
+        }
+        if ((T.flags & TASK_EXTRACT) && T.comp == 0 && T.i0 + (uint32_t)A.steps >= A.n) {
+            // (A_0, -A_{N-1}, ..., -A_1; B_0) (eq. equ-sam-extr)
+            uint32_t *o = A.ext_out + (size_t)T.ct * (N + 1);
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint32_t idx = 64 * k + L;
+                const uint32_t v = accl[swz(idx)];
+                o[(N - idx) & (N - 1)] = idx ? (v ? A.Q - v : 0) : v;
+            }
+            if (L == 0) o[N] = accl[P + swz(0)];
+        }
+    }
+}
+
+// One external product per wave: in/out [count][2][N].
+template <int N>
+__global__ void __launch_bounds__(256) k_external_product(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                          size_t count, const uint32_t *__restrict__ K,
+                                                          const uint32_t *twf, const uint32_t *twi, uint32_t Q,
+                                                          uint32_t qn, uint32_t log2B, uint32_t l, uint32_t sg)
+{
+    using G = Geo<N>;
+    constexpr int E = G::E;
+    extern __shared__ uint32_t lds[];
+    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
+    const size_t c = (size_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (c >= count) return;
+    uint32_t *slot = lds + wave * G::SLOTW;
+    const ModQ m{Q, qn};
+    const GadgetC g{log2B, l, sg};
+    uint32_t D[2][E], o[2][E];
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        D[0][k] = in[c * 2 * N + 64 * k + L];
+        D[1][k] = in[c * 2 * N + N + 64 * k + L];
+    }
+    external_product<N>(D[0], D[1], K, slot, twf, twi, L, m, g, o);
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        out[c * 2 * N + 64 * k + L] = o[0][k];
+        out[c * 2 * N + N + 64 * k + L] = o[1][k];
+    }
+}
+
+// a * b through the wave NTT: [count][N] each.  c_fix = 2^64 / N mod Q
+// undoes two Montgomery factors and the missing 1/N.
+template <int N>
+__global__ void __launch_bounds__(256) k_negacyclic_mul(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                                        uint32_t *__restrict__ out, size_t count, const uint32_t *twf,
+                                                        const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t c_fix)
+{
+    using G = Geo<N>;
+    constexpr int E = G::E;
+    extern __shared__ uint32_t lds[];
+    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
+    const size_t c = (size_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (c >= count) return;
+    uint32_t *slot = lds + wave * G::SLOTW;
+    const ModQ m{Q, qn};
+    uint32_t x[2][E];
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        x[0][k] = a[c * N + 64 * k + L];
+        x[1][k] = b[c * N + 64 * k + L];
+    }
+    ntt_fwd<N, 2>(x, slot, twf, L, m);
+    uint32_t y[1][E];
+#pragma unroll
+    for (int k = 0; k < E; k++) y[0][k] = mont_mul(mont_mul(x[0][k], x[1][k], m), c_fix, m);
+    ntt_inv<N, 1>(y, slot, twi, L, m);
+#pragma unroll
+    for (int k = 0; k < E; k++) out[c * N + 64 * k + L] = y[0][k];
+}
+
+// Sample extraction of [count][2][N] pairs.
+__global__ void k_sample_extract(const uint32_t *__restrict__ rlwe, uint32_t *__restrict__ lwe, size_t count,
+                                 uint32_t N, uint32_t Q)
+{
+    const size_t total = count * (N + 1);
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = t / (N + 1);
+        const uint32_t k = (uint32_t)(t - c * (N + 1));
+        const uint32_t *A = rlwe + c * 2 * N;
+        uint32_t v;
+        if (k == N) v = A[N];
+        else if (k == 0) v = A[0];
+        else v = A[N - k] ? Q - A[N - k] : 0;
+        lwe[t] = v;
+    }
+}
+
+// Key switch, partial sums: thread (col, ct) adds KSK[i][j][d_ij(ct)][col] over
+// the (i, j) pairs of split z (i in [i_begin, i_end)).  part[(z count + ct)(n+1) + col].
+__global__ void __launch_bounds__(256) k_keyswitch(KsArgs A)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t col = blockIdx.x * 64 + lane;
+    const uint32_t W = A.n + 1;
+    const uint32_t iper = (A.N + gridDim.z - 1) / gridDim.z;
+    const uint32_t i_begin = blockIdx.z * iper, i_end = min(A.N, i_begin + iper);
+    const uint32_t Bm = (1u << A.log2Bks) - 1;
+    constexpr int CPW = KS_CTS_PER_WAVE;
+    uint64_t acc[CPW];
+    const uint32_t *src[CPW];
+    bool ok[CPW];
+#pragma unroll
+    for (int q = 0; q < CPW; q++) {
+        const size_t ct = ((size_t)blockIdx.y * 4 + wave) * CPW + q;
+        ok[q] = ct < A.count;
+        src[q] = A.lwe_N + (ok[q] ? ct : 0) * (A.N + 1);
+        acc[q] = 0;
+    }
+    if (col < W) {
+        for (uint32_t i = i_begin; i < i_end; i++) {
+            const uint32_t *rowbase = A.ksk + (size_t)i * A.l_ks * (Bm + 1) * W + col;
+#pragma unroll
+            for (int q = 0; q < CPW; q++) {
+                const uint32_t a = __builtin_amdgcn_readfirstlane(src[q][i]);
+                for (uint32_t j = 0; j < A.l_ks; j++) {
+                    const uint32_t sh = j * A.log2Bks;
+                    const uint32_t d = sh < 32 ? (a >> sh) & Bm : 0u;
+                    acc[q] += rowbase[((size_t)j * (Bm + 1) + d) * W];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CPW; q++) {
+            const size_t ct = ((size_t)blockIdx.y * 4 + wave) * CPW + q;
+            if (ok[q]) A.part[((size_t)blockIdx.z * A.count + ct) * W + col] = acc[q] % A.Q;
+        }
+    }
+}
+
+// (0^n, b) - sum of the partials, then the modulus switch Q -> q_out
+// (q_out = Q keeps the residues).  out[ct][n+1].
+__global__ void k_ks_finalize(const uint64_t *__restrict__ part, const uint32_t *__restrict__ lwe_N,
+                              uint32_t *__restrict__ out, size_t count, uint32_t n, uint32_t N, uint32_t splits,
+                              uint32_t Q, const uint32_t *__restrict__ q_out_per_ct, uint32_t q_out)
+{
+    const uint32_t W = n + 1;
+    const size_t total = count * W;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t ct = t / W;
+        const uint32_t col = (uint32_t)(t - ct * W);
+        uint64_t s = 0;
+        for (uint32_t z = 0; z < splits; z++) s += part[((size_t)z * count + ct) * W + col];
+        const uint32_t v = (uint32_t)(s % Q);
+        uint32_t x;
+        if (col < n) x = v ? Q - v : 0;
+        else {
+            const uint32_t b = lwe_N[ct * (N + 1) + N];
+            x = b >= v ? b - v : b + Q - v;
+        }
+        const uint32_t qo = q_out_per_ct ? q_out_per_ct[ct] : q_out;
+        out[t] = (qo == Q) ? x : modswitch_dev(x, Q, qo);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int N>
+static void launch_br_n(const BrArgs &A, int grid, hipStream_t st)
+{
+    const size_t lds = (size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_blind_rotate<N>, dim3(grid), dim3(512), lds, st, A);
+}
+
+template <int N>
+static hipError_t br_attr_n()
+{
+    return hipFuncSetAttribute((const void *)k_blind_rotate<N>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t)));
+}
+
+hipError_t init_kernel_attributes()
+{
+    hipError_t e = br_attr_n<256>();
+    if (e == hipSuccess) e = br_attr_n<512>();
+    if (e == hipSuccess) e = br_attr_n<1024>();
+    return e;
+}
+
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int grid, hipStream_t st)
+{
+    switch (N) {
+    case 256: launch_br_n<256>(A, grid, st); break;
+    case 512: launch_br_n<512>(A, grid, st); break;
+    case 1024: launch_br_n<1024>(A, grid, st); break;
+    default: break;
+    }
+}
+
+size_t br_lds_bytes(uint32_t N)
+{
+    switch (N) {
+    case 256: return (size_t)8 * BrLds<256>::WAVE_WORDS * 4;
+    case 512: return (size_t)8 * BrLds<512>::WAVE_WORDS * 4;
+    default: return (size_t)8 * BrLds<1024>::WAVE_WORDS * 4;
+    }
+}
+
+template <int N>
+static void launch_ep_n(const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K, const uint32_t *twf,
+                        const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B, uint32_t l, uint32_t sg,
+                        hipStream_t st)
+{
+    const size_t lds = (size_t)4 * Geo<N>::SLOTW * sizeof(uint32_t);
+    const int grid = (int)((count + 3) / 4);
+    hipLaunchKernelGGL(k_external_product<N>, dim3(grid), dim3(256), lds, st, in, out, count, K, twf, twi, Q, qn,
+                       log2B, l, sg);
+}
+
+void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
+                             const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,
+                             uint32_t l, uint32_t sg, hipStream_t st)
+{
+    switch (N) {
+    case 256: launch_ep_n<256>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
+    case 512: launch_ep_n<512>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
+    case 1024: launch_ep_n<1024>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
+    default: break;
+    }
+}
+
+template <int N>
+static void launch_pm_n(const uint32_t *a, const uint32_t *b, uint32_t *out, size_t count, const uint32_t *twf,
+                        const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t c_fix, hipStream_t st)
+{
+    const size_t lds = (size_t)4 * Geo<N>::SLOTW * sizeof(uint32_t);
+    const int grid = (int)((count + 3) / 4);
+    hipLaunchKernelGGL(k_negacyclic_mul<N>, dim3(grid), dim3(256), lds, st, a, b, out, count, twf, twi, Q, qn, c_fix);
+}
+
+void launch_negacyclic_mul(uint32_t N, const uint32_t *a, const uint32_t *b, uint32_t *out, size_t count,
+                           const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t c_fix,
+                           hipStream_t st)
+{
+    switch (N) {
+    case 256: launch_pm_n<256>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
+    case 512: launch_pm_n<512>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
+    case 1024: launch_pm_n<1024>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
+    default: break;
+    }
+}
+
+void launch_modswitch(const uint32_t *in, uint32_t *out, size_t count, uint32_t q_from, uint32_t q_to, hipStream_t st)
+{
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_modswitch, dim3(std::max(grid, 1)), dim3(256), 0, st, in, out, count, q_from, q_to);
+}
+
+void launch_sample_extract(const uint32_t *rlwe, uint32_t *lwe, size_t count, uint32_t N, uint32_t Q, hipStream_t st)
+{
+    const size_t total = count * (N + 1);
+    const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sample_extract, dim3(std::max(grid, 1)), dim3(256), 0, st, rlwe, lwe, count, N, Q);
+}
+
+void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st)
+{
+    const uint32_t W = A.n + 1;
+    const uint32_t cts_per_block = 4 * KS_CTS_PER_WAVE;
+    dim3 grid((W + 63) / 64, (uint32_t)((A.count + cts_per_block - 1) / cts_per_block), splits);
+    hipLaunchKernelGGL(k_keyswitch, grid, dim3(256), 0, st, A);
+}
+
+void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, uint32_t *out, size_t count, uint32_t n,
+                        uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct, uint32_t q_out,
+                        hipStream_t st)
+{
+    const size_t total = count * (n + 1);
+    const int grid = (int)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_ks_finalize, dim3(std::max(grid, 1)), dim3(256), 0, st, part, lwe_N, out, count, n, N,
+                       splits, Q, q_out_per_ct, q_out);
+}
+
+}  // namespace dev
+}  // namespace mm

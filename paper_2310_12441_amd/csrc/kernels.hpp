@@ -1,0 +1,74 @@
+// Kernel argument blocks and launchers (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mm {
+namespace dev {
+
+enum : uint32_t {
+    TASK_INIT = 1u,     // accumulator starts at Phi(b')(0, V)
+    TASK_STORE = 2u,    // write the accumulator to acc_state at the end of the launch
+    TASK_EXTRACT = 4u,  // component 0 writes the extracted LWE_N sample when step n is reached
+};
+
+// What one wave of a blind-rotation workgroup does.  A group is 8 consecutive
+// WaveTasks; the components 0..r-1 of a ciphertext sit on consecutive waves.
+struct WaveTask {
+    int32_t ct;        // ciphertext index, -1 for an idle wave
+    uint32_t comp;     // component j
+    uint32_t r;        // vector length of the ciphertext's table
+    uint32_t tv_off;   // word offset of the table's test vector in the arena
+    uint32_t q_in;     // ciphertext modulus
+    uint32_t i0;       // first CMux step of this launch
+    uint32_t flags;    // TASK_*
+    uint32_t pad;
+    uint64_t acc_off;  // word offset of the ciphertext's accumulator state (r x 2 x N)
+};
+
+struct BrArgs {
+    const WaveTask *tasks;
+    int num_groups;
+    int steps;                 // CMux steps per launch
+    const uint32_t *ct_in;     // ciphertexts at their q_in
+    uint32_t ct_stride;        // n + 1
+    uint32_t n, Q, qn, log2B, l, sg;
+    const uint32_t *bsk;       // [n][2l][2][N], NTT domain, x 2^32 / N mod Q
+    const uint32_t *twf, *twi; // Montgomery-form twiddles
+    const uint32_t *tv;        // test-vector arena
+    uint32_t *acc_state;       // accumulators carried between launches
+    uint32_t *ext_out;         // [ct][N + 1] extracted samples
+};
+
+constexpr int KS_CTS_PER_WAVE = 4;
+
+struct KsArgs {
+    const uint32_t *lwe_N;  // [count][N + 1] at Q
+    const uint32_t *ksk;    // [N][l_ks][B_ks][n + 1]
+    uint64_t *part;         // [splits][count][n + 1]
+    size_t count;
+    uint32_t n, N, Q, log2Bks, l_ks;
+};
+
+hipError_t init_kernel_attributes();
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int grid, hipStream_t st);
+size_t br_lds_bytes(uint32_t N);
+void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
+                             const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,
+                             uint32_t l, uint32_t sg, hipStream_t st);
+void launch_negacyclic_mul(uint32_t N, const uint32_t *a, const uint32_t *b, uint32_t *out, size_t count,
+                           const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t c_fix,
+                           hipStream_t st);
+void launch_modswitch(const uint32_t *in, uint32_t *out, size_t count, uint32_t q_from, uint32_t q_to,
+                      hipStream_t st);
+void launch_sample_extract(const uint32_t *rlwe, uint32_t *lwe, size_t count, uint32_t N, uint32_t Q,
+                           hipStream_t st);
+void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st);
+void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, uint32_t *out, size_t count, uint32_t n,
+                        uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct, uint32_t q_out,
+                        hipStream_t st);
+
+}  // namespace dev
+}  // namespace mm

@@ -1,0 +1,111 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-side calls (key generation, test vectors, encryption) agree bit
+for bit with the oracle on the same draws.  No device compute runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import PRESETS, Params, enc_draws, key_draws, messages, negacyclic_table
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _binding():
+    from paper_2310_12441_amd import binding
+    return binding
+
+
+def test_header_symbols_exported():
+    b = _binding()
+    hdr = open(os.path.join(ROOT, "include", "mmpm.h")).read()
+    declared = sorted(set(re.findall(r"\b(mm_[a-z_]+)\s*\(", hdr)))
+    assert declared, "no declarations found"
+    so = ctypes.CDLL(b.LIB_PATH)
+    missing = [s for s in declared if not hasattr(so, s)]
+    assert not missing, missing
+    assert sorted(b.SYMBOLS) == declared
+
+
+@pytest.mark.parametrize("preset,seed", [("tiny", 0), ("tiny", 9)])
+def test_keygen_matches_oracle(preset, seed):
+    b = _binding()
+    p = PRESETS[preset]["params"]
+    dr = key_draws(p, seed)
+    ctx = b.Context(p, dr)
+    np.testing.assert_array_equal(ctx.export_bsk(), oracle.keygen_bsk(p, dr))
+    np.testing.assert_array_equal(ctx.export_ksk(), oracle.keygen_ksk(p, dr))
+
+
+def test_keygen_matches_oracle_paper_shaped_bsk():
+    b = _binding()
+    p = PRESETS["paper_shaped"]["params"]
+    small = Params(n=24, N=p.N, log2_B=p.log2_B, l=p.l)  # full ring, fewer LWE coordinates
+    dr = key_draws(small, 5)
+    ctx = b.Context(small, dr)
+    np.testing.assert_array_equal(ctx.export_bsk(), oracle.keygen_bsk(small, dr))
+    np.testing.assert_array_equal(ctx.export_ksk(), oracle.keygen_ksk(small, dr))
+
+
+@pytest.mark.parametrize("N,r,t,t_out", [(256, 2, 16, 16), (1024, 4, 4096, 4096), (1024, 1, 256, 256),
+                                         (1024, 8, 16384, 16384), (256, 3, 24, 32)])
+def test_test_vector_matches_oracle(N, r, t, t_out):
+    b = _binding()
+    p = Params(n=4, N=N)
+    ctx = b.Context(p, key_draws(p, 1))
+    f = negacyclic_table(t, t_out, 7)
+    tid = ctx.table_create(t, t_out, r, f)
+    np.testing.assert_array_equal(ctx.table_export(tid), oracle.test_vector(N, r, p.Q, t, t_out, f))
+    assert ctx.table_info(tid) == (t, t_out, r, 2 * N * r)
+
+
+@pytest.mark.parametrize("q,t", [(1024, 16), (8192, 4096), (2147352577, 4096), (16384, 16384)])
+def test_encrypt_decrypt_match_oracle(q, t):
+    b = _binding()
+    p = Params(n=37, N=256)
+    dr = key_draws(p, 2)
+    ctx = b.Context(p, dr)
+    m = messages(t, 300, 3)
+    ed = enc_draws(p.n, q, 300, 4)
+    ct = ctx.encrypt(q, t, m, ed["a"], ed["e"])
+    np.testing.assert_array_equal(ct, oracle.encrypt(p.n, q, t, dr["s"], m, ed["a"], ed["e"]))
+    np.testing.assert_array_equal(ctx.decrypt(q, t, ct), oracle.decrypt(p.n, q, t, dr["s"], ct))
+
+
+def test_error_paths():
+    b = _binding()
+    p = Params(n=4, N=256)
+    dr = key_draws(p, 1)
+    with pytest.raises(b.MMError) as e:
+        b.Context(Params(n=4, N=256, Q=2147352579), dr)  # not prime
+    assert e.value.code == b.MM_EINVAL
+    with pytest.raises(b.MMError):
+        b.Context(Params(n=4, N=256, log2_Bks=4, l_ks=6), key_draws(Params(n=4, N=256, l_ks=6), 1))
+    ctx = b.Context(p, dr)
+    f = negacyclic_table(16, 16, 1)
+    with pytest.raises(b.MMError):
+        ctx.table_create(16, 16, 2, np.arange(16))  # not nega-cyclic
+    with pytest.raises(b.MMError):
+        ctx.table_create(12, 16, 2, negacyclic_table(12, 16, 1))  # 12 does not divide 2Nr = 1024
+    with pytest.raises(b.MMError):
+        ctx.table_create(16, 16, 9, f)  # r > 8
+    bad = dict(dr)
+    bad["s"] = dr["s"] + 2
+    with pytest.raises(b.MMError):
+        b.Context(p, bad)
+
+
+def test_device_calls_fail_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    b = _binding()
+    p = PRESETS["tiny"]["params"]
+    ctx = b.Context(p, key_draws(p, 1))
+    tid = ctx.table_create(16, 16, 2, negacyclic_table(16, 16, 1))
+    with pytest.raises(b.MMError) as e:
+        ctx.bootstrap([tid], np.zeros((1, p.n + 1), np.uint32))
+    assert e.value.code == b.MM_EDEVICE

@@ -1,0 +1,281 @@
+"""GPU parity: every row of the hot path through the C ABI against the oracle.
+
+The HIP library and the oracle build their keys, test vectors and ciphertexts
+from the same draws (synth) independently; every comparison is bit-exact
+(tolerance 0), since the whole path is exact integer arithmetic.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import CLASS_MIX, PRESETS, Params, class_mix, enc_draws, key_draws, messages, negacyclic_table
+
+pytestmark = pytest.mark.gpu
+Q = 2147352577
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_12441_amd import binding
+    return binding
+
+
+class Case:
+    """Product context + oracle keys for one parameter set."""
+
+    def __init__(self, p, seed):
+        b = _gpu()
+        self.p = p
+        self.draws = key_draws(p, seed)
+        self.ctx = b.Context(p, self.draws)
+        self.keys = oracle.KeySet(p, self.draws)
+        self.ctx.device_init(0)
+
+    def table(self, t, t_out, r, seed, q_in=0):
+        f = negacyclic_table(t, t_out, seed)
+        tid = self.ctx.table_create(t, t_out, r, f, q_in)
+        V = oracle.test_vector(self.p.N, r, Q, t, t_out, f)
+        return tid, f, V
+
+    def encrypt(self, q, t, m, seed, sigma=3.2):
+        ed = enc_draws(self.p.n, q, len(m), seed, sigma)
+        return oracle.encrypt(self.p.n, q, t, self.keys.s, m, ed["a"], ed["e"])
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return Case(PRESETS["tiny"]["params"], 11)
+
+
+@pytest.fixture(scope="module")
+def paper():
+    return Case(PRESETS["paper_shaped"]["params"], 12)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------- single rows
+
+@pytest.mark.parametrize("q_from,q_to", [(Q, 8192), (8192, 8192), (1 << 20, 2048), (Q, 1024)])
+def test_modswitch(tiny, q_from, q_to):
+    say("modswitch", q_from, q_to)
+    rng = np.random.default_rng(q_to)
+    x = rng.integers(0, q_from, 5000, dtype=np.uint32)
+    np.testing.assert_array_equal(tiny.ctx.modswitch(x, q_from, q_to), oracle.modswitch(x, q_from, q_to))
+
+
+@pytest.mark.parametrize("which", ["tiny", "paper"])
+@pytest.mark.parametrize("count", [1, 5, 33])
+def test_negacyclic_mul(request, which, count):
+    case = request.getfixturevalue(which)
+    say("negacyclic_mul", which, count)
+    N = case.p.N
+    rng = np.random.default_rng(count + N)
+    a = rng.integers(0, Q, (count, N), dtype=np.uint32)
+    b = rng.integers(0, Q, (count, N), dtype=np.uint32)
+    got = case.ctx.negacyclic_mul(a, b)
+    for c in range(count):
+        np.testing.assert_array_equal(got[c], oracle.poly_mul(a[c], b[c], Q), err_msg=f"poly {c}")
+
+
+def test_negacyclic_mul_edges(paper):
+    N = paper.p.N
+    a = np.zeros((4, N), np.uint32)
+    b = np.zeros((4, N), np.uint32)
+    a[0, 0] = 1
+    b[0] = np.arange(N)
+    a[1, N - 1] = 1  # x^(N-1) * x = -1
+    b[1, 1] = 1
+    a[2] = Q - 1
+    b[2] = Q - 1
+    a[3, 5] = 7
+    b[3, N - 3] = Q - 2
+    got = paper.ctx.negacyclic_mul(a, b)
+    for c in range(4):
+        np.testing.assert_array_equal(got[c], oracle.poly_mul(a[c], b[c], Q))
+
+
+@pytest.mark.parametrize("which", ["tiny", "paper"])
+def test_external_product(request, which):
+    case = request.getfixturevalue(which)
+    say("external_product", which)
+    N = case.p.N
+    rng = np.random.default_rng(3)
+    count = 9
+    rl = rng.integers(0, Q, (count, 2, N), dtype=np.uint32)
+    rl[0] = 0
+    rl[1] = Q - 1
+    for i in (0, 1, case.p.n - 1):
+        got = case.ctx.external_product(i, rl)
+        for c in range(count):
+            want = oracle.external_product(case.keys.bsk[i], rl[c], Q, case.p.log2_B, case.p.l)
+            np.testing.assert_array_equal(got[c], want, err_msg=f"key {i} pair {c}")
+
+
+def test_sample_extract(paper):
+    N = paper.p.N
+    rng = np.random.default_rng(4)
+    rl = rng.integers(0, Q, (6, 2, N), dtype=np.uint32)
+    got = paper.ctx.sample_extract(rl)
+    for c in range(6):
+        np.testing.assert_array_equal(got[c], oracle.sample_extract(rl[c], Q))
+
+
+@pytest.mark.parametrize("count", [1, 3, 70])
+def test_keyswitch(paper, count):
+    say("keyswitch", count)
+    rng = np.random.default_rng(count)
+    lw = rng.integers(0, Q, (count, paper.p.N + 1), dtype=np.uint32)
+    got = paper.ctx.keyswitch(lw)
+    for c in range(count):
+        np.testing.assert_array_equal(got[c], oracle.keyswitch(paper.p, paper.keys.ksk, lw[c]))
+
+
+# ---------------------------------------------------------------- blind rotation
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 5, 64])
+def test_blind_rotate_tiny_steps(tiny, steps):
+    say("blind_rotate tiny steps", steps)
+    tid, f, V = tiny.table(16, 16, 2, 5)
+    q = 2 * tiny.p.N * 2
+    m = messages(16, 4, 7)
+    ct = tiny.encrypt(q, 16, m, 8)
+    got = tiny.ctx.blind_rotate([tid] * 4, ct, steps).reshape(4, 2, 2, tiny.p.N)
+    for c in range(4):
+        want = oracle.blind_rotate(tiny.p, 2, tiny.keys.bsk, V, ct[c], steps)
+        np.testing.assert_array_equal(got[c], want, err_msg=f"ct {c}")
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_blind_rotate_paper_mixed_r(paper, steps):
+    """r = 1, 2, 4, 8 in one launch (components packed into shared workgroups)."""
+    say("blind_rotate paper mixed steps", steps)
+    ids, cts, Vs, rs = [], [], [], []
+    for k, (t, r) in enumerate(CLASS_MIX):
+        tid, f, V = paper.table(t, t, r, 20 + k)
+        q = 2 * paper.p.N * r
+        ct = paper.encrypt(q, t, messages(t, 2, 30 + k), 40 + k)
+        for c in range(2):
+            ids.append(tid)
+            cts.append(ct[c])
+            Vs.append(V)
+            rs.append(r)
+    got = paper.ctx.blind_rotate(ids, np.array(cts), steps)
+    off = 0
+    for c in range(len(ids)):
+        r = rs[c]
+        size = r * 2 * paper.p.N
+        want = oracle.blind_rotate(paper.p, r, paper.keys.bsk, Vs[c], cts[c], steps)
+        np.testing.assert_array_equal(got[off:off + size].reshape(r, 2, paper.p.N), want, err_msg=f"ct {c} r {r}")
+        off += size
+
+
+# ---------------------------------------------------------------- whole bootstrap
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_bootstrap_tiny_all_messages(tiny, plain):
+    say("bootstrap tiny plain", plain)
+    tid, f, V = tiny.table(16, 16, 2, 6)
+    q = 2 * tiny.p.N * 2
+    m = np.arange(16, dtype=np.uint32)
+    ct = tiny.encrypt(q, 16, m, 9)
+    got = tiny.ctx.bootstrap([tid] * 16, ct, plain=plain)
+    want = oracle.bootstrap_many(tiny.p, 2, tiny.keys.bsk, tiny.keys.ksk, V, q, q, ct)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(oracle.decrypt(tiny.p.n, q, 16, tiny.keys.s, got), f[m])
+
+
+def test_bootstrap_tiny_correct_many_seeds():
+    """decrypt(bootstrap(Enc(m))) = f(m) for every m, fresh keys per seed (Definition 1)."""
+    b = _gpu()
+    pre = PRESETS["tiny"]
+    p = pre["params"]
+    for seed in range(100, 112):
+        dr = key_draws(p, seed)
+        ctx = b.Context(p, dr)
+        f = negacyclic_table(16, 16, seed)
+        tid = ctx.table_create(16, 16, 2, f)
+        q = 2 * p.N * 2
+        m = np.tile(np.arange(16, dtype=np.uint32), 4)
+        ed = enc_draws(p.n, q, m.size, seed)
+        ct = ctx.encrypt(q, 16, m, ed["a"], ed["e"])
+        out = ctx.bootstrap([tid] * m.size, ct)
+        np.testing.assert_array_equal(ctx.decrypt(q, 16, out), f[m], err_msg=f"seed {seed}")
+        ctx.close()
+
+
+@pytest.mark.parametrize("q_out", [0, Q, 4096])
+def test_bootstrap_paper_single(paper, q_out):
+    say("bootstrap paper single q_out", q_out)
+    tid, f, V = paper.table(4096, 4096, 4, 7)
+    q = 8192
+    ct = paper.encrypt(q, 4096, messages(4096, 2, 10), 11)
+    got_plain = paper.ctx.bootstrap([tid] * 2, ct, q_out=q_out, plain=True)
+    got_batch = paper.ctx.bootstrap([tid] * 2, ct, q_out=q_out)
+    np.testing.assert_array_equal(got_plain, got_batch)
+    qo = q if q_out == 0 else q_out
+    want = oracle.bootstrap_many(paper.p, 4, paper.keys.bsk, paper.keys.ksk, V, q, qo, ct)
+    np.testing.assert_array_equal(got_plain, want)
+
+
+def test_bootstrap_mixed_batch_equals_alone(paper):
+    """Uneven (t, r) batch: every output equals the oracle and the same ciphertext run alone."""
+    say("bootstrap mixed batch")
+    tabs = []
+    for k, (t, r) in enumerate(CLASS_MIX):
+        tid, f, V = paper.table(t, t, r, 50 + k)
+        tabs.append((tid, t, r, V))
+    cls = class_mix(24, 3)
+    ids, cts = [], []
+    for c, k in enumerate(cls):
+        tid, t, r, V = tabs[k]
+        ids.append(tid)
+        cts.append(paper.encrypt(2 * paper.p.N * r, t, messages(t, 1, 100 + c), 200 + c)[0])
+    cts = np.array(cts)
+    got = paper.ctx.bootstrap(ids, cts)
+    alone = paper.ctx.bootstrap(ids, cts, plain=True)
+    np.testing.assert_array_equal(got, alone)
+    for c in range(0, len(ids), 6):
+        tid, t, r, V = tabs[cls[c]]
+        q = 2 * paper.p.N * r
+        want = oracle.bootstrap(paper.p, r, paper.keys.bsk, paper.keys.ksk, V, q, q, cts[c])
+        np.testing.assert_array_equal(got[c], want, err_msg=f"ct {c} class {cls[c]}")
+
+
+def test_bootstrap_noise_free_all_messages_decode_at_Q():
+    """sigma = 0 keys and inputs: every m in Z_4096 decodes from the output at Q."""
+    b = _gpu()
+    p = PRESETS["paper_shaped"]["params"].noise_free()
+    dr = key_draws(p, 77)
+    ctx = b.Context(p, dr)
+    f = negacyclic_table(4096, 4096, 77)
+    tid = ctx.table_create(4096, 4096, 4, f)
+    m = np.arange(4096, dtype=np.uint32)
+    ed = enc_draws(p.n, 8192, 4096, 78, sigma=0.0)
+    ct = ctx.encrypt(8192, 4096, m, ed["a"], ed["e"])
+    out = ctx.bootstrap([tid] * 4096, ct, q_out=Q)
+    np.testing.assert_array_equal(ctx.decrypt(Q, 4096, out), f[m])
+    # a sample against the oracle at full batch size
+    keys = oracle.KeySet(p, dr)
+    V = oracle.test_vector(p.N, 4, Q, 4096, 4096, f)
+    pick = np.array([0, 1, 2047, 4095])
+    want = oracle.bootstrap_many(p, 4, keys.bsk, keys.ksk, V, 8192, Q, ct[pick])
+    np.testing.assert_array_equal(out[pick], want)
+    ctx.close()
+
+
+def test_bootstrap_device_pointers(paper):
+    import torch
+    tid, f, V = paper.table(4096, 4096, 4, 8)
+    ct = paper.encrypt(8192, 4096, messages(4096, 3, 12), 13)
+    host = paper.ctx.bootstrap([tid] * 3, ct)
+    dev_in = torch.from_numpy(ct.view(np.int32)).cuda()
+    dev_out = paper.ctx.bootstrap([tid] * 3, dev_in)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dev_out.cpu().numpy().view(np.uint32), host)
