@@ -1,0 +1,227 @@
+"""Benchmark: batched BootMMPM bootstraps per second at t = 2^12 on one MI355X.
+
+One step = one call of the whole hot path (modulus switch, accumulator
+initialisation, 630 CMux steps, sample extraction, key switch, final modulus
+switch) over a batch of 4096 ciphertexts with n = 630, N = 1024, k = r = 4,
+t = t' = 2^12, gadget 2^7 x 4, key switch 2^4 x 8, Q = 2^31 - 2^17 + 1, inputs
+resident in device memory.  Alongside: the plain per-ciphertext path on the same
+GPU, the blind-rotation kernel's roofline, and the CPU oracle on the host cores.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BATCH = 4096
+# MI355X vector issue: the published fp32 vector rate 157.3 TFLOP/s is 256 CUs x
+# 128 FMA lanes/clock x 2 flops x 2.4 GHz, i.e. 78.6 T lane-instructions/s; a
+# 32-bit integer VALU instruction takes the same issue slot.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
+PEAK_HBM = 8.0e12
+KERNEL_SOURCES = ("paper_2310_12441_amd/csrc/kernels.hip", "paper_2310_12441_amd/csrc/device_common.hpp")
+COUNTERS = os.path.join(ROOT, "profiles", "k_blind_rotate_paper_shaped_4096_counters.txt")
+
+
+def ops_per_bootstrap(n, N, l, r):
+    """Algorithmic 32-bit VALU instructions (lane-ops) of one blind rotation.
+
+    Op model, one lane-op per instruction of the shortest sequence in the
+    representation used (residues in [0, Q), Q < 2^31, Montgomery twiddles):
+    Cooley-Tukey butterfly 11 = Montgomery product 5 (64-bit product, low-word
+    multiply, multiply-add, subtract, min) + modular add 3 + modular subtract 3;
+    Gentleman-Sande butterfly 10 = modular add 3 + lazy subtract 2 + Montgomery
+    product 5; NTT-domain multiply-accumulate 10 per pair of key products = two
+    64-bit multiply-adds + Montgomery reduction 5 + modular add 3.  Per step and
+    ring component: 2l forward and 2 inverse NTTs of (N/2) log2 N butterflies and
+    2 N l product pairs.  Decomposition, rotation, data movement and address
+    arithmetic are not counted.
+    """
+    logN = int(np.log2(N))
+    bfly = (N // 2) * logN
+    per_comp = 2 * l * bfly * 11 + 2 * bfly * 10 + 2 * N * l * 10
+    return n * r * per_comp
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the blind-rotation kernel from the committed
+    counter summary, or None when it is missing or the kernel changed since."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != source_hash():
+        return None
+    try:
+        return int(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bsk_bytes(n, N, l):
+    return n * 2 * l * 2 * N * 4
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=BATCH)
+    ap.add_argument("--plain", type=int, default=8, help="ciphertexts timed on the plain path")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: one per host thread)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); ciphertexts are independent, "
+              "so more GPUs would each bootstrap their own share with a replica of the keys", flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2310_12441_amd import binding
+    from synth import PRESETS, enc_draws, key_draws, messages, negacyclic_table
+
+    pre = PRESETS["paper_shaped"]
+    p, t, r = pre["params"], pre["t"], pre["r"]
+    q = 2 * p.N * r
+    B = args.batch
+    seeds = {"keys": 1, "table": 2, "messages": 3, "encryption": 4}
+    draws = key_draws(p, seeds["keys"])
+    ctx = binding.Context(p, draws)
+    ctx.device_init(0)
+    f = negacyclic_table(t, t, seeds["table"])
+    tid = ctx.table_create(t, t, r, f)
+    m = messages(t, B, seeds["messages"])
+    ed = enc_draws(p.n, q, B, seeds["encryption"])
+    ct = ctx.encrypt(q, t, m, ed["a"], ed["e"])
+    ids = np.full(B, tid, dtype=np.int32)
+    dev_in = torch.from_numpy(ct.view(np.int32)).cuda()
+    dev_out = torch.empty_like(dev_in)
+
+    # ---- batched path (timed)
+    ctx.set_timing(True)
+    for _ in range(args.warmup):
+        ctx.bootstrap(ids, dev_in, out=dev_out)
+        ctx.last_timing()
+    torch.cuda.synchronize()
+    br_ms, ks_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.bootstrap(ids, dev_in, out=dev_out)
+        a, b = ctx.last_timing()
+        br_ms.append(a)
+        ks_ms.append(b)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = B * args.steps / wall
+    batched_out = dev_out.cpu().numpy().view(np.uint32).copy()
+
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(7)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # ---- plain path on the same GPU (one ciphertext at a time)
+    P = min(args.plain, B)
+    plain_rate, plain_same = None, None
+    if P > 0:
+        ctx.bootstrap(ids[:1], dev_in[:1], plain=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain_out = ctx.bootstrap(ids[:P], dev_in[:P], plain=True)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t1
+        plain_rate = P / plain_s
+        plain_same = bool(np.array_equal(plain_out.cpu().numpy().view(np.uint32), batched_out[:P]))
+
+    # ---- roofline of the blind-rotation kernel
+    br_avg = float(np.mean(br_ms)) * 1e-3
+    ops = ops_per_bootstrap(p.n, p.N, p.l, r) * B
+    achieved = ops / br_avg
+    hbm_alg = bsk_bytes(p.n, p.N, p.l) + B * (p.n + 1) * 4 + B * (p.N + 1) * 4
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved / 1e12, 3),
+        "peak": round(PEAK_LANE_OPS / 1e12, 3),
+        "unit": "TOP/s",
+        "frac": round(achieved / PEAK_LANE_OPS, 4),
+        "traffic": measured_traffic(),
+        "kernel": "k_blind_rotate<1024>",
+        "kernel_ms": round(br_avg * 1e3, 3),
+        "ops_per_launch": ops,
+        "hbm_algorithmic_bytes": hbm_alg,
+        "hbm_frac": round(hbm_alg / br_avg / PEAK_HBM, 6),
+        "kernel_source_sha256_16": source_hash(),
+    }
+
+    # ---- CPU oracle on the host cores, on a bounded sample of the same batch
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nthr = oracle.num_threads()
+        S = args.cpu_sample or max(8, 3 * nthr)
+        keys = oracle.KeySet(p, draws)
+        V = oracle.test_vector(p.N, r, p.Q, t, t, f)
+        idx = np.linspace(0, B - 1, S).astype(int)
+        t2 = time.perf_counter()
+        want = oracle.bootstrap_many(p, r, keys.bsk, keys.ksk, V, q, q, ct[idx])
+        cpu_s = time.perf_counter() - t2
+        cpu = {"value": round(S / cpu_s, 4), "unit": "bootstraps/s", "cores": nthr, "kind": "oracle",
+               "sample": f"{S} of the {B} ciphertexts (evenly spaced), one ciphertext per thread, schoolbook products",
+               "seconds": round(cpu_s, 2), "parity_with_gpu": bool(np.array_equal(want, batched_out[idx]))}
+
+    line = {
+        "metric": "bootstraps/sec at t=2^12 (batched vs plain, bit-exact); serving p50/p99 ms",
+        "value": round(value, 2),
+        "unit": "bootstraps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"batched {B} x BootMMPM (n=630, N=1024, k=4, t=2^12, B=2^7 l=4, Bks=2^4 lks=8)",
+                   "batch": B, "n": p.n, "N": p.N, "k": r, "t": t, "q": q, "Q": p.Q, "seeds": seeds},
+        "plain_bootstraps_per_s": round(plain_rate, 3) if plain_rate else None,
+        "plain_ms_per_bootstrap": round(1e3 / plain_rate, 3) if plain_rate else None,
+        "batched_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
+        "plain_equals_batched": plain_same,
+        "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

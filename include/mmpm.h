@@ -172,6 +172,15 @@ int mm_keyswitch(mm_ctx *ctx, const uint32_t *lwe_N, size_t count, uint32_t *lwe
 int mm_negacyclic_mul(mm_ctx *ctx, const uint32_t *a, const uint32_t *b, size_t count,
                       uint32_t *out, uint32_t flags, void *stream);
 
+/* ---- kernel timing ---- */
+
+/* With enable != 0, every batched mm_bootstrap on ctx records HIP events on
+ * its stream around the blind-rotation kernel and around the key-switch
+ * kernels (inside the captured graph).  mm_last_timing waits for the events
+ * of the last such call and returns both durations in milliseconds. */
+int mm_set_timing(mm_ctx *ctx, int enable);
+int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
+
 /* ---- autotuning ---- */
 
 /* Time the kernel schedules that fit this batch shape (ciphertexts per

@@ -23,7 +23,7 @@ SYMBOLS = [
     "mm_keygen", "mm_free", "mm_last_error", "mm_get_params", "mm_export_bsk", "mm_export_ksk",
     "mm_device_init", "mm_table_create", "mm_table_info", "mm_table_export", "mm_encrypt", "mm_decrypt",
     "mm_bootstrap", "mm_modswitch", "mm_blind_rotate", "mm_external_product", "mm_sample_extract",
-    "mm_keyswitch", "mm_negacyclic_mul", "mm_autotune", "mm_server_start", "mm_submit", "mm_poll",
+    "mm_keyswitch", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune", "mm_server_start", "mm_submit", "mm_poll",
     "mm_server_stats", "mm_server_stop", "mm_server_replay",
 ]
 
@@ -68,6 +68,8 @@ def _load():
         "mm_sample_extract": (i32, [vp, vp, sz, vp, u32, vp]),
         "mm_keyswitch": (i32, [vp, vp, sz, vp, u32, vp]),
         "mm_negacyclic_mul": (i32, [vp, vp, vp, sz, vp, u32, vp]),
+        "mm_set_timing": (i32, [vp, i32]),
+        "mm_last_timing": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "mm_autotune": (i32, [vp, vp, vp, sz, C.POINTER(i32)]),
         "mm_server_start": (i32, [vp, sz, u32, C.POINTER(vp)]),
         "mm_submit": (i32, [vp, i32, vp, C.POINTER(u64)]),
@@ -267,6 +269,15 @@ class Context:
         bb = Buf(b)
         self._check(lib.mm_negacyclic_mul(self.h, i.ptr, bb.ptr, cnt, o.ptr, flags, st))
         return o.arr
+
+    def set_timing(self, enable: bool):
+        self._check(lib.mm_set_timing(self.h, 1 if enable else 0))
+
+    def last_timing(self):
+        """(blind-rotation ms, key-switch ms) of the last batched bootstrap."""
+        a, b = C.c_float(), C.c_float()
+        self._check(lib.mm_last_timing(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def autotune(self, table_ids, ct) -> int:
         ids = _i32(np.atleast_1d(table_ids))

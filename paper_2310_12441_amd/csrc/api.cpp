@@ -183,6 +183,20 @@ int mm_negacyclic_mul(mm_ctx *ctx, const uint32_t *a, const uint32_t *b, size_t 
     return guard(ctx, [&] { mm::run_negacyclic_mul(*ctx, a, b, count, out, flags, stream); });
 }
 
+int mm_set_timing(mm_ctx *ctx, int enable)
+{
+    if (!ctx) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->lock);
+    return guard(ctx, [&] { mm::set_timing(*ctx, enable != 0); });
+}
+
+int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms)
+{
+    if (!ctx) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->lock);
+    return guard(ctx, [&] { mm::last_timing(*ctx, blind_rotate_ms, keyswitch_ms); });
+}
+
 int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count, int *choice)
 {
     if (!ctx || !choice || (count && (!ct_in || !table_ids))) return MM_EINVAL;

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <string>
 
@@ -48,6 +49,8 @@ struct Device {
     std::vector<Graph> graphs;
     std::map<std::string, int> tuned;  // batch shape -> schedule index
     int ws_generation = 0;
+    bool timing = false;
+    hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // before BR, after BR, after key switch
 
     ~Device()
     {
@@ -63,6 +66,8 @@ struct Device {
         }
         for (void *p : {(void *)bsk, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
             if (p) hipFree(p);
+        for (auto &e : tev)
+            if (e) hipEventDestroy(e);
         if (own) hipStreamDestroy(own);
     }
 };
@@ -369,12 +374,15 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
     A.acc_state = nullptr;
     const int grid = std::min(groups, d.num_cu);
 
-    auto enqueue = [&](hipStream_t s) {
-        dev::launch_blind_rotate(N, A, grid, s);
-        enqueue_keyswitch(c, d, ext, count, d_out, qv, q_scalar, P, part, s);
-    };
+    const bool timed = d.timing;
+    auto enqueue_br = [&](hipStream_t s) { dev::launch_blind_rotate(N, A, grid, s); };
+    auto enqueue_ks = [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, count, d_out, qv, q_scalar, P, part, s); };
     if (!use_graph) {
-        enqueue(st);
+        if (timed) HIPC(hipEventRecord(d.tev[0], st));
+        enqueue_br(st);
+        if (timed) HIPC(hipEventRecord(d.tev[1], st));
+        enqueue_ks(st);
+        if (timed) HIPC(hipEventRecord(d.tev[2], st));
         HIPC(hipGetLastError());
         return;
     }
@@ -382,23 +390,41 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
                             std::to_string(q_scalar) + "/" + std::to_string((uintptr_t)qv) + "/" +
                             std::to_string((uintptr_t)d_in) + "/" + std::to_string((uintptr_t)d_out) + "/" +
                             std::to_string(d.ws_generation);
-    hipGraphExec_t exec = nullptr;
-    for (auto &g : d.graphs)
-        if (g.key == key) exec = g.exec;
-    if (!exec) {
+    // One graph holds the whole launch sequence; with timing on, the blind
+    // rotation and the key switch are two graphs so that events can sit
+    // between them on the stream.
+    auto get_graph = [&](const std::string &k, const std::function<void(hipStream_t)> &body) {
+        for (auto &g : d.graphs)
+            if (g.key == k) return g.exec;
         hipGraph_t graph;
+        hipGraphExec_t exec = nullptr;
         HIPC(hipStreamBeginCapture(d.own, hipStreamCaptureModeThreadLocal));
-        enqueue(d.own);
+        body(d.own);
         HIPC(hipStreamEndCapture(d.own, &graph));
         HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         HIPC(hipGraphDestroy(graph));
-        if (d.graphs.size() >= 8) {
+        if (d.graphs.size() >= 12) {
             hipGraphExecDestroy(d.graphs.front().exec);
             d.graphs.erase(d.graphs.begin());
         }
-        d.graphs.push_back({key, exec});
+        d.graphs.push_back({k, exec});
+        return exec;
+    };
+    if (!timed) {
+        hipGraphExec_t g = get_graph(key + "/all", [&](hipStream_t s) {
+            enqueue_br(s);
+            enqueue_ks(s);
+        });
+        HIPC(hipGraphLaunch(g, st));
+    } else {
+        hipGraphExec_t g1 = get_graph(key + "/br", enqueue_br);
+        hipGraphExec_t g2 = get_graph(key + "/ks", enqueue_ks);
+        HIPC(hipEventRecord(d.tev[0], st));
+        HIPC(hipGraphLaunch(g1, st));
+        HIPC(hipEventRecord(d.tev[1], st));
+        HIPC(hipGraphLaunch(g2, st));
+        HIPC(hipEventRecord(d.tev[2], st));
     }
-    HIPC(hipGraphLaunch(exec, st));
 }
 
 void run_bootstrap(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count, uint32_t *ct_out, uint32_t q_out,
@@ -529,6 +555,26 @@ void run_keyswitch(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe
     enqueue_keyswitch(c, d, din, count, dout, nullptr, c.p.Q, P, part, st);
     HIPC(hipGetLastError());
     finish_out(lwe_n, dout, count * W, dptr, st);
+}
+
+void set_timing(mm_ctx &c, bool on)
+{
+    Device &d = ensure_device(c);
+    if (on && !d.tev[0])
+        for (auto &e : d.tev) HIPC(hipEventCreate(&e));
+    d.timing = on;
+}
+
+void last_timing(mm_ctx &c, float *br_ms, float *ks_ms)
+{
+    Device &d = ensure_device(c);
+    if (!d.timing || !d.tev[0]) throw Error(MM_ESTATE, "timing is not enabled");
+    HIPC(hipEventSynchronize(d.tev[2]));
+    float a = 0, b = 0;
+    HIPC(hipEventElapsedTime(&a, d.tev[0], d.tev[1]));
+    HIPC(hipEventElapsedTime(&b, d.tev[1], d.tev[2]));
+    if (br_ms) *br_ms = a;
+    if (ks_ms) *ks_ms = b;
 }
 
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
