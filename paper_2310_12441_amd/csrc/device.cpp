@@ -9,74 +9,15 @@
 #include <numeric>
 #include <string>
 
-#include "kernels.hpp"
-#include "mmpm_internal.hpp"
+#include "device_internal.hpp"
 
 namespace mm {
-
-#define HIPC(expr)                                                                                  \
-    do {                                                                                            \
-        hipError_t e_ = (expr);                                                                     \
-        if (e_ != hipSuccess)                                                                       \
-            throw ::mm::Error(MM_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
-    } while (0)
-
-enum WsSlot { WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_COUNT };
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct PinBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipEvent_t ev = nullptr;  // last stream use of the buffer
-};
-
-struct Device {
-    int id = -1, num_cu = 0;
-    uint32_t qn = 0, c_fix = 0;
-    uint32_t *bsk = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
-    size_t tv_words = 0, tables_uploaded = 0;
-    DevBuf ws[WS_COUNT];
-    PinBuf pin[2];
-    hipStream_t own = nullptr;
-    struct Graph {
-        std::string key;
-        hipGraphExec_t exec = nullptr;
-    };
-    std::vector<Graph> graphs;
-    std::map<std::string, int> tuned;  // batch shape -> schedule index
-    int ws_generation = 0;
-    bool timing = false;
-    hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // before BR, after BR, after key switch
-
-    ~Device()
-    {
-        hipSetDevice(id);
-        hipDeviceSynchronize();
-        for (auto &g : graphs)
-            if (g.exec) hipGraphExecDestroy(g.exec);
-        for (auto &b : ws)
-            if (b.p) hipFree(b.p);
-        for (auto &b : pin) {
-            if (b.p) hipHostFree(b.p);
-            if (b.ev) hipEventDestroy(b.ev);
-        }
-        for (void *p : {(void *)bsk, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
-            if (p) hipFree(p);
-        for (auto &e : tev)
-            if (e) hipEventDestroy(e);
-        if (own) hipStreamDestroy(own);
-    }
-};
 
 void DeviceDeleter::operator()(Device *d) const { delete d; }
 
 void device_release(mm_ctx &c) { c.dev.reset(); }
 
-static void *ws(Device &d, int slot, size_t bytes)
+void *ws(Device &d, int slot, size_t bytes)
 {
     DevBuf &b = d.ws[slot];
     if (b.bytes < bytes) {
@@ -99,7 +40,7 @@ static void *ws(Device &d, int slot, size_t bytes)
 }
 
 // Pinned host staging buffer `slot`; waits until its previous use has executed.
-static void *pinned(Device &d, int slot, size_t bytes)
+void *pinned(Device &d, int slot, size_t bytes)
 {
     PinBuf &b = d.pin[slot];
     if (!b.ev) HIPC(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
@@ -177,7 +118,7 @@ void device_init(mm_ctx &c, int id)
     c.dev = std::move(d);
 }
 
-static Device &ensure_device(mm_ctx &c)
+Device &ensure_device(mm_ctx &c)
 {
     if (!c.dev) {
         int cur = 0;
@@ -233,42 +174,54 @@ static void finish_out(uint32_t *host, const uint32_t *dev, size_t words, bool d
 // ------------------------------------------------------------------ batching
 
 // Pack ciphertexts into groups of 8 wave slots, first-fit over r descending,
-// each ciphertext's components on consecutive waves of one group.
-static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, size_t count, uint32_t flags,
-                                              uint32_t i0, const std::vector<uint64_t> &acc_off)
+// each ciphertext's components on consecutive waves of one group.  cts[k] is
+// the task of ciphertext k with comp = 0; the result holds 8 tasks per group.
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts)
 {
-    std::vector<size_t> order(count);
+    std::vector<size_t> order(cts.size());
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return c.tables[ids[a]].r > c.tables[ids[b]].r; });
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cts[a].r > cts[b].r; });
     std::vector<dev::WaveTask> tasks;
     std::vector<uint32_t> used;  // per group
     size_t first_open = 0;
     for (size_t o : order) {
-        const Table &t = c.tables[ids[o]];
+        const uint32_t r = cts[o].r;
         size_t g = first_open;
-        while (g < used.size() && used[g] + t.r > 8) g++;
+        while (g < used.size() && used[g] + r > 8) g++;
         if (g == used.size()) {
             used.push_back(0);
             dev::WaveTask idle{};
             idle.ct = -1;
             tasks.insert(tasks.end(), 8, idle);
         }
-        for (uint32_t j = 0; j < t.r; j++) {
-            dev::WaveTask &w = tasks[g * 8 + used[g] + j];
-            w.ct = (int32_t)o;
+        for (uint32_t j = 0; j < r; j++) {
+            dev::WaveTask w = cts[o];
             w.comp = j;
-            w.r = t.r;
-            w.tv_off = (uint32_t)t.dev_offset;
-            w.q_in = t.q_in;
-            w.i0 = i0;
-            w.flags = flags;
-            w.acc_off = acc_off.empty() ? 0 : acc_off[o];
+            tasks[g * 8 + used[g] + j] = w;
         }
-        used[g] += t.r;
+        used[g] += r;
         while (first_open < used.size() && used[first_open] == 8) first_open++;
     }
     return tasks;
+}
+
+static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, size_t count, uint32_t flags,
+                                              uint32_t i0, const std::vector<uint64_t> &acc_off)
+{
+    std::vector<dev::WaveTask> cts(count);
+    for (size_t k = 0; k < count; k++) {
+        const Table &t = c.tables[ids[k]];
+        dev::WaveTask &w = cts[k];
+        w.ct = (int32_t)k;
+        w.comp = 0;
+        w.r = t.r;
+        w.tv_off = (uint32_t)t.dev_offset;
+        w.q_in = t.q_in;
+        w.i0 = i0;
+        w.flags = flags;
+        w.acc_off = acc_off.empty() ? 0 : acc_off[k];
+    }
+    return pack_tasks(cts);
 }
 
 static void check_ids(const mm_ctx &c, const int *ids, size_t count)
@@ -289,7 +242,7 @@ static dev::WaveTask *upload_tasks(Device &d, const std::vector<dev::WaveTask> &
     return dt;
 }
 
-static dev::BrArgs br_args(const mm_ctx &c, const Device &d)
+dev::BrArgs br_args(const mm_ctx &c, const Device &d)
 {
     dev::BrArgs A{};
     A.ct_stride = c.p.n + 1;
@@ -306,7 +259,7 @@ static dev::BrArgs br_args(const mm_ctx &c, const Device &d)
     return A;
 }
 
-static uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count)
+uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count)
 {
     const size_t col_tiles = (c.p.n + 1 + 63) / 64;
     const size_t ct_tiles = (count + 4 * dev::KS_CTS_PER_WAVE - 1) / (4 * dev::KS_CTS_PER_WAVE);
@@ -316,13 +269,15 @@ static uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count)
     return (uint32_t)P;
 }
 
-// Enqueue key switch + final modulus switch of `count` extracted samples.
-static void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, size_t count, uint32_t *out,
-                              const uint32_t *q_out_per_ct, uint32_t q_out, uint32_t P, uint64_t *part,
-                              hipStream_t st)
+// Enqueue key switch + final modulus switch of `count` extracted samples
+// (row k of the output is sample rows[k] of ext, or sample k when rows is null).
+void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const int32_t *rows, size_t count,
+                       uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, uint32_t P, uint64_t *part,
+                       hipStream_t st)
 {
     dev::KsArgs K{};
     K.lwe_N = ext;
+    K.rows = rows;
     K.ksk = d.ksk;
     K.part = part;
     K.count = count;
@@ -332,7 +287,7 @@ static void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, s
     K.log2Bks = c.p.log2_Bks;
     K.l_ks = c.p.l_ks;
     dev::launch_keyswitch(K, P, st);
-    dev::launch_ks_finalize(part, ext, out, count, c.p.n, c.p.N, P, c.p.Q, q_out_per_ct, q_out, st);
+    dev::launch_ks_finalize(part, ext, rows, out, count, c.p.n, c.p.N, P, c.p.Q, q_out_per_ct, q_out, st);
 }
 
 // The batched path for ciphertexts already on the device.
@@ -376,7 +331,7 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
 
     const bool timed = d.timing;
     auto enqueue_br = [&](hipStream_t s) { dev::launch_blind_rotate(N, A, grid, s); };
-    auto enqueue_ks = [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, count, d_out, qv, q_scalar, P, part, s); };
+    auto enqueue_ks = [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, P, part, s); };
     if (!use_graph) {
         if (timed) HIPC(hipEventRecord(d.tev[0], st));
         enqueue_br(st);
@@ -552,7 +507,7 @@ void run_keyswitch(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe
     uint32_t *dout = stage_out(d, WS_OUT, lwe_n, count * W, dptr);
     const uint32_t P = ks_splits(c, d, count);
     uint64_t *part = (uint64_t *)ws(d, WS_PART, (size_t)P * count * W * 8);
-    enqueue_keyswitch(c, d, din, count, dout, nullptr, c.p.Q, P, part, st);
+    enqueue_keyswitch(c, d, din, nullptr, count, dout, nullptr, c.p.Q, P, part, st);
     HIPC(hipGetLastError());
     finish_out(lwe_n, dout, count * W, dptr, st);
 }

@@ -1,0 +1,84 @@
+// Device-side state shared by the batch path (device.cpp) and the serving
+// loop (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mmpm_internal.hpp"
+
+namespace mm {
+
+#define HIPC(expr)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            throw ::mm::Error(MM_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+enum WsSlot { WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_COUNT };
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct PinBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;  // last stream use of the buffer
+};
+
+struct Device {
+    int id = -1, num_cu = 0;
+    uint32_t qn = 0, c_fix = 0;
+    uint32_t *bsk = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
+    size_t tv_words = 0, tables_uploaded = 0;
+    DevBuf ws[WS_COUNT];
+    PinBuf pin[2];
+    hipStream_t own = nullptr;
+    struct Graph {
+        std::string key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    std::map<std::string, int> tuned;  // batch shape -> schedule index
+    int ws_generation = 0;
+    bool timing = false;
+    hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // before BR, after BR, after key switch
+
+    ~Device()
+    {
+        hipSetDevice(id);
+        hipDeviceSynchronize();
+        for (auto &g : graphs)
+            if (g.exec) hipGraphExecDestroy(g.exec);
+        for (auto &b : ws)
+            if (b.p) hipFree(b.p);
+        for (auto &b : pin) {
+            if (b.p) hipHostFree(b.p);
+            if (b.ev) hipEventDestroy(b.ev);
+        }
+        for (void *p : {(void *)bsk, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
+            if (p) hipFree(p);
+        for (auto &e : tev)
+            if (e) hipEventDestroy(e);
+        if (own) hipStreamDestroy(own);
+    }
+};
+
+Device &ensure_device(mm_ctx &c);
+void *ws(Device &d, int slot, size_t bytes);
+void *pinned(Device &d, int slot, size_t bytes);
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts);
+dev::BrArgs br_args(const mm_ctx &c, const Device &d);
+uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count);
+void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const int32_t *rows, size_t count,
+                       uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, uint32_t P, uint64_t *part,
+                       hipStream_t st);
+
+}  // namespace mm

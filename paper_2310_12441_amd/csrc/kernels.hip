@@ -248,7 +248,8 @@ __global__ void __launch_bounds__(256) k_keyswitch(KsArgs A)
     for (int q = 0; q < CPW; q++) {
         const size_t ct = ((size_t)blockIdx.y * 4 + wave) * CPW + q;
         ok[q] = ct < A.count;
-        src[q] = A.lwe_N + (ok[q] ? ct : 0) * (A.N + 1);
+        const size_t srow = ok[q] ? (A.rows ? (size_t)A.rows[ct] : ct) : 0;
+        src[q] = A.lwe_N + srow * (A.N + 1);
         acc[q] = 0;
     }
     if (col < W) {
@@ -275,7 +276,7 @@ __global__ void __launch_bounds__(256) k_keyswitch(KsArgs A)
 // (0^n, b) - sum of the partials, then the modulus switch Q -> q_out
 // (q_out = Q keeps the residues).  out[ct][n+1].
 __global__ void k_ks_finalize(const uint64_t *__restrict__ part, const uint32_t *__restrict__ lwe_N,
-                              uint32_t *__restrict__ out, size_t count, uint32_t n, uint32_t N, uint32_t splits,
+                              const int32_t *__restrict__ rows, uint32_t *__restrict__ out, size_t count, uint32_t n, uint32_t N, uint32_t splits,
                               uint32_t Q, const uint32_t *__restrict__ q_out_per_ct, uint32_t q_out)
 {
     const uint32_t W = n + 1;
@@ -289,12 +290,32 @@ __global__ void k_ks_finalize(const uint64_t *__restrict__ part, const uint32_t 
         uint32_t x;
         if (col < n) x = v ? Q - v : 0;
         else {
-            const uint32_t b = lwe_N[ct * (N + 1) + N];
+            const size_t srow = rows ? (size_t)rows[ct] : ct;
+            const uint32_t b = lwe_N[srow * (N + 1) + N];
             x = b >= v ? b - v : b + Q - v;
         }
         const uint32_t qo = q_out_per_ct ? q_out_per_ct[ct] : q_out;
         out[t] = (qo == Q) ? x : modswitch_dev(x, Q, qo);
     }
+}
+
+// dst[rows[k]] = src[k] for rows of W words (staged ciphertexts into their slots).
+__global__ void k_scatter_rows(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                               const int32_t *__restrict__ rows, size_t count, uint32_t W)
+{
+    const size_t total = count * W;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = t / W;
+        dst[(size_t)rows[k] * W + (t - k * W)] = src[t];
+    }
+}
+
+void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,
+                         hipStream_t st)
+{
+    const size_t total = count * W;
+    const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_scatter_rows, dim3(std::max(grid, 1)), dim3(256), 0, st, src, dst, rows, count, W);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -405,13 +426,13 @@ void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st)
     hipLaunchKernelGGL(k_keyswitch, grid, dim3(256), 0, st, A);
 }
 
-void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, uint32_t *out, size_t count, uint32_t n,
-                        uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct, uint32_t q_out,
-                        hipStream_t st)
+void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, const int32_t *rows, uint32_t *out, size_t count,
+                        uint32_t n, uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct,
+                        uint32_t q_out, hipStream_t st)
 {
     const size_t total = count * (n + 1);
     const int grid = (int)std::min<size_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_ks_finalize, dim3(std::max(grid, 1)), dim3(256), 0, st, part, lwe_N, out, count, n, N,
+    hipLaunchKernelGGL(k_ks_finalize, dim3(std::max(grid, 1)), dim3(256), 0, st, part, lwe_N, rows, out, count, n, N,
                        splits, Q, q_out_per_ct, q_out);
 }
 

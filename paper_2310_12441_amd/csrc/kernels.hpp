@@ -45,7 +45,8 @@ struct BrArgs {
 constexpr int KS_CTS_PER_WAVE = 4;
 
 struct KsArgs {
-    const uint32_t *lwe_N;  // [count][N + 1] at Q
+    const uint32_t *lwe_N;  // extracted samples at Q, [*][N + 1]
+    const int32_t *rows;    // output row k reads sample rows[k] (null: sample k)
     const uint32_t *ksk;    // [N][l_ks][B_ks][n + 1]
     uint64_t *part;         // [splits][count][n + 1]
     size_t count;
@@ -53,6 +54,8 @@ struct KsArgs {
 };
 
 hipError_t init_kernel_attributes();
+void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,
+                         hipStream_t st);
 void launch_blind_rotate(uint32_t N, const BrArgs &A, int grid, hipStream_t st);
 size_t br_lds_bytes(uint32_t N);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
@@ -66,7 +69,8 @@ void launch_modswitch(const uint32_t *in, uint32_t *out, size_t count, uint32_t 
 void launch_sample_extract(const uint32_t *rlwe, uint32_t *lwe, size_t count, uint32_t N, uint32_t Q,
                            hipStream_t st);
 void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st);
-void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, uint32_t *out, size_t count, uint32_t n,
+void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, const int32_t *rows, uint32_t *out, size_t count,
+                        uint32_t n,
                         uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct, uint32_t q_out,
                         hipStream_t st);
 

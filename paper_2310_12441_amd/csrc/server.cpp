@@ -1,20 +1,557 @@
-// Serving loop (continuous batching); filled in below the stub.
-#include "mmpm_internal.hpp"
+// Serving loop: continuous batching of single bootstrap requests.
+//
+// Requests of any table (any t, t', r) are admitted into device-resident
+// slots as memory allows.  Every launch ("tick") advances each resident
+// ciphertext by `chunk` CMux steps, its accumulator staying in device memory
+// between ticks, so a request that arrives while others are on the GPU joins
+// them at the next tick instead of waiting for a whole batch to drain.  The
+// slots are split into two partitions with a stream each; while one
+// partition's tick runs, the host harvests and relaunches the other, so the
+// two overlap on the device.  Ciphertexts that reach step n are key-switched in
+// the same tick and their results copied back.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <set>
+#include <thread>
+#include <unordered_map>
+
+#include "device_internal.hpp"
 
 namespace mm {
-struct Server {};
-Server *server_start(mm_ctx &, size_t, uint32_t) { throw Error(MM_ESTATE, "serving not built yet"); }
-void server_stop(Server *s) { delete s; }
+
+using clk = std::chrono::steady_clock;
+
+namespace {
+
+// Buddy allocator over accumulator units (one unit = the (a, b) pair of one
+// ring component, 2N words); a ciphertext with vector length r takes a block
+// of 2^ceil(log2 r) units, r <= 8.
+struct Buddy {
+    std::set<uint32_t> free_[4];
+    void init(uint32_t units)
+    {
+        for (auto &f : free_) f.clear();
+        for (uint32_t u = 0; u + 8 <= units; u += 8) free_[3].insert(u);
+    }
+    int64_t alloc(uint32_t order)
+    {
+        uint32_t o = order;
+        while (o < 4 && free_[o].empty()) o++;
+        if (o == 4) return -1;
+        uint32_t start = *free_[o].begin();
+        free_[o].erase(free_[o].begin());
+        while (o > order) {  // split, keep the lower half
+            o--;
+            free_[o].insert(start + (1u << o));
+        }
+        return start;
+    }
+    void release(uint32_t start, uint32_t order)
+    {
+        while (order < 3) {
+            const uint32_t buddy = start ^ (1u << order);
+            auto it = free_[order].find(buddy);
+            if (it == free_[order].end()) break;
+            free_[order].erase(it);
+            start = std::min(start, buddy);
+            order++;
+        }
+        free_[order].insert(start);
+    }
+};
+
+uint32_t order_of(uint32_t r)
+{
+    uint32_t o = 0;
+    while ((1u << o) < r) o++;
+    return o;
+}
+
+struct Req {
+    uint64_t ticket;
+    int table;
+    std::vector<uint32_t> ct;
+    clk::time_point t0;
+};
+
+struct Active {
+    uint64_t ticket;
+    int table;
+    uint32_t slot, unit, order, step;
+    clk::time_point t0;
+};
+
+struct Result {
+    std::vector<uint32_t> ct;
+    double ms;
+};
+
+template <class T>
+struct DevHost {
+    T *d = nullptr;
+    T *h = nullptr;
+    size_t cap = 0;
+    void reserve(size_t n)
+    {
+        if (n <= cap) return;
+        release();
+        const size_t want = std::max<size_t>(n * 2, 256);
+        if (hipMalloc((void **)&d, want * sizeof(T)) != hipSuccess ||
+            hipHostMalloc((void **)&h, want * sizeof(T), hipHostMallocDefault) != hipSuccess)
+            throw Error(MM_ENOMEM, "server staging allocation failed");
+        cap = want;
+    }
+    void release()
+    {
+        if (d) hipFree(d);
+        if (h) hipHostFree(h);
+        d = nullptr;
+        h = nullptr;
+        cap = 0;
+    }
+};
+
+struct Part {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    std::vector<Active> active, finishing;
+    DevHost<dev::WaveTask> tasks;
+    DevHost<int32_t> rows, stage_rows;
+    DevHost<uint32_t> out, stage, qout;
+    uint64_t *part = nullptr;
+    size_t part_cap = 0;
+};
+
+}  // namespace
+
+struct Server {
+    mm_ctx *c = nullptr;
+    uint32_t chunk = 64, max_cts = 0, units = 0;
+    uint32_t *d_acc = nullptr, *d_ct = nullptr, *d_ext = nullptr;
+    Buddy buddy;
+    std::vector<uint32_t> free_slots;
+    Part part[2];
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req> pending;
+    size_t pending_cap = 1u << 20;
+    std::unordered_map<uint64_t, Result> done;
+    std::vector<double> lat;
+    uint64_t next_ticket = 1, completed = 0;
+    bool have_first = false;
+    clk::time_point t_first, t_last;
+    std::atomic<bool> stop{false};
+    std::thread th;
+    int next_admit = 0;
+
+    void loop();
+    bool harvest(Part &p);
+    void launch(Part &p);
+    uint64_t submit(int table, const uint32_t *ct, clk::time_point t0, int *rc);
+    ~Server();
+};
+
+Server::~Server()
+{
+    hipSetDevice(c->dev->id);
+    for (auto &p : part) {
+        if (p.st) hipStreamSynchronize(p.st);
+        p.tasks.release();
+        p.rows.release();
+        p.stage_rows.release();
+        p.out.release();
+        p.stage.release();
+        p.qout.release();
+        if (p.part) hipFree(p.part);
+        if (p.ev) hipEventDestroy(p.ev);
+        if (p.st) hipStreamDestroy(p.st);
+    }
+    if (d_acc) hipFree(d_acc);
+    if (d_ct) hipFree(d_ct);
+    if (d_ext) hipFree(d_ext);
+}
+
+#define SRV_HIP(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            throw ::mm::Error(MM_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
+{
+    MM_REQUIRE(chunk >= 1 && chunk <= c.p.n, "chunk_steps must be in [1, n]");
+    Device &d = ensure_device(c);
+    const size_t N = c.p.N, W = c.p.n + 1;
+    // per ciphertext slot: input, extracted sample, key-switch partial row; per unit: one (a, b) pair
+    const size_t per_ct = (W + N + 1) * 4 + W * 8;
+    const size_t per_unit = 2 * N * 4;
+    const size_t units = (budget / (per_ct + per_unit)) / 8 * 8;
+    MM_REQUIRE(units >= 8, "HBM budget too small for one slot group");
+    auto *s = new Server();
+    s->c = &c;
+    s->chunk = chunk;
+    s->units = (uint32_t)units;
+    s->max_cts = (uint32_t)units;
+    try {
+        if (hipMalloc((void **)&s->d_acc, units * per_unit) != hipSuccess ||
+            hipMalloc((void **)&s->d_ct, (size_t)s->max_cts * W * 4) != hipSuccess ||
+            hipMalloc((void **)&s->d_ext, (size_t)s->max_cts * (N + 1) * 4) != hipSuccess)
+            throw Error(MM_ENOMEM, "server arena allocation failed");
+        s->buddy.init(s->units);
+        s->free_slots.resize(s->max_cts);
+        for (uint32_t i = 0; i < s->max_cts; i++) s->free_slots[i] = s->max_cts - 1 - i;
+        for (auto &p : s->part) {
+            SRV_HIP(hipStreamCreateWithFlags(&p.st, hipStreamNonBlocking));
+            SRV_HIP(hipEventCreateWithFlags(&p.ev, hipEventDisableTiming));
+        }
+    } catch (...) {
+        delete s;
+        throw;
+    }
+    s->th = std::thread([s] { s->loop(); });
+    return s;
+}
+
+void server_stop(Server *s)
+{
+    if (!s) return;
+    s->stop = true;
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    delete s;
+}
+
+uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *rc)
+{
+    const size_t W = c->p.n + 1;
+    std::lock_guard<std::mutex> g(mu);
+    if (table < 0 || (size_t)table >= c->tables.size()) {
+        *rc = MM_EINVAL;
+        return 0;
+    }
+    if (pending.size() >= pending_cap || stop) {
+        *rc = MM_EBUSY;
+        return 0;
+    }
+    Req r{next_ticket++, table, std::vector<uint32_t>(ct, ct + W), t0};
+    if (!have_first) {
+        have_first = true;
+        t_first = t0;
+    }
+    pending.push_back(std::move(r));
+    cv.notify_all();
+    *rc = MM_OK;
+    return pending.back().ticket;
+}
+
+// Collect the results of a finished tick.  Returns true if it harvested.
+bool Server::harvest(Part &p)
+{
+    if (!p.busy) return false;
+    if (hipEventQuery(p.ev) != hipSuccess) return false;
+    const size_t W = c->p.n + 1;
+    const auto now = clk::now();
+    std::lock_guard<std::mutex> g(mu);
+    for (size_t k = 0; k < p.finishing.size(); k++) {
+        const Active &a = p.finishing[k];
+        Result res{std::vector<uint32_t>(p.out.h + k * W, p.out.h + (k + 1) * W),
+                   std::chrono::duration<double, std::milli>(now - a.t0).count()};
+        lat.push_back(res.ms);
+        done.emplace(a.ticket, std::move(res));
+        free_slots.push_back(a.slot);
+        buddy.release(a.unit, a.order);
+        completed++;
+    }
+    if (!p.finishing.empty()) t_last = now;
+    p.finishing.clear();
+    p.busy = false;
+    return true;
+}
+
+// Admit what fits, then enqueue one tick of this partition.
+void Server::launch(Part &p)
+{
+    const uint32_t N = c->p.N, W = c->p.n + 1, n = c->p.n;
+    std::vector<Active> fresh;
+    std::vector<Req> fresh_req;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        while (!pending.empty() && !free_slots.empty()) {
+            const Req &q = pending.front();
+            const uint32_t order = order_of(c->tables[q.table].r);
+            const int64_t unit = buddy.alloc(order);
+            if (unit < 0) break;  // no accumulator memory: wait for completions
+            Active a{q.ticket, q.table, free_slots.back(), (uint32_t)unit, order, 0, q.t0};
+            free_slots.pop_back();
+            fresh.push_back(a);
+            fresh_req.push_back(std::move(pending.front()));
+            pending.pop_front();
+        }
+    }
+    if (fresh.empty() && p.active.empty()) return;
+    std::lock_guard<std::mutex> dev_lock(c->lock);
+    Device &d = ensure_device(*c);
+    if (!fresh.empty()) {
+        p.stage.reserve(fresh.size() * W);
+        p.stage_rows.reserve(fresh.size());
+        for (size_t k = 0; k < fresh.size(); k++) {
+            std::memcpy(p.stage.h + k * W, fresh_req[k].ct.data(), W * 4);
+            p.stage_rows.h[k] = (int32_t)fresh[k].slot;
+        }
+        SRV_HIP(hipMemcpyAsync(p.stage.d, p.stage.h, fresh.size() * W * 4, hipMemcpyHostToDevice, p.st));
+        SRV_HIP(hipMemcpyAsync(p.stage_rows.d, p.stage_rows.h, fresh.size() * 4, hipMemcpyHostToDevice, p.st));
+        dev::launch_scatter_rows(p.stage.d, d_ct, p.stage_rows.d, fresh.size(), W, p.st);
+        p.active.insert(p.active.end(), fresh.begin(), fresh.end());
+    }
+    // one task per resident ciphertext, packed into 8-wave groups
+    std::vector<dev::WaveTask> cts(p.active.size());
+    for (size_t k = 0; k < p.active.size(); k++) {
+        const Active &a = p.active[k];
+        const Table &t = c->tables[a.table];
+        dev::WaveTask &w = cts[k];
+        w.ct = (int32_t)a.slot;
+        w.r = t.r;
+        w.tv_off = (uint32_t)t.dev_offset;
+        w.q_in = t.q_in;
+        w.i0 = a.step;
+        w.flags = (a.step == 0 ? dev::TASK_INIT : 0u) | dev::TASK_STORE | dev::TASK_EXTRACT;
+        w.acc_off = (uint64_t)a.unit * 2 * N;
+    }
+    auto tasks = pack_tasks(cts);
+    p.tasks.reserve(tasks.size());
+    std::memcpy(p.tasks.h, tasks.data(), tasks.size() * sizeof(dev::WaveTask));
+    SRV_HIP(hipMemcpyAsync(p.tasks.d, p.tasks.h, tasks.size() * sizeof(dev::WaveTask), hipMemcpyHostToDevice, p.st));
+    dev::BrArgs A = br_args(*c, d);
+    A.tasks = p.tasks.d;
+    A.num_groups = (int)(tasks.size() / 8);
+    A.steps = (int)chunk;
+    A.ct_in = d_ct;
+    A.acc_state = d_acc;
+    A.ext_out = d_ext;
+    dev::launch_blind_rotate(N, A, std::min(A.num_groups, d.num_cu), p.st);
+
+    // ciphertexts that reach step n in this tick: key switch and copy back
+    std::vector<Active> keep;
+    p.finishing.clear();
+    for (auto &a : p.active) {
+        if (a.step + chunk >= n) p.finishing.push_back(a);
+        else {
+            a.step += chunk;
+            keep.push_back(a);
+        }
+    }
+    p.active.swap(keep);
+    const size_t F = p.finishing.size();
+    if (F) {
+        p.rows.reserve(F);
+        p.qout.reserve(F);
+        p.out.reserve(F * W);
+        for (size_t k = 0; k < F; k++) {
+            p.rows.h[k] = (int32_t)p.finishing[k].slot;
+            p.qout.h[k] = c->tables[p.finishing[k].table].q_in;
+        }
+        SRV_HIP(hipMemcpyAsync(p.rows.d, p.rows.h, F * 4, hipMemcpyHostToDevice, p.st));
+        SRV_HIP(hipMemcpyAsync(p.qout.d, p.qout.h, F * 4, hipMemcpyHostToDevice, p.st));
+        const uint32_t P = ks_splits(*c, d, F);
+        const size_t need = (size_t)P * F * W;
+        if (p.part_cap < need) {
+            SRV_HIP(hipStreamSynchronize(p.st));
+            if (p.part) SRV_HIP(hipFree(p.part));
+            p.part = nullptr;
+            p.part_cap = 0;
+            if (hipMalloc((void **)&p.part, need * 2 * 8) != hipSuccess) throw Error(MM_ENOMEM, "server key-switch buffer");
+            p.part_cap = need * 2;
+        }
+        enqueue_keyswitch(*c, d, d_ext, p.rows.d, F, p.out.d, p.qout.d, 0, P, p.part, p.st);
+        SRV_HIP(hipMemcpyAsync(p.out.h, p.out.d, F * W * 4, hipMemcpyDeviceToHost, p.st));
+    }
+    SRV_HIP(hipGetLastError());
+    SRV_HIP(hipEventRecord(p.ev, p.st));
+    p.busy = true;
+}
+
+void Server::loop()
+{
+    try {
+        hipSetDevice(c->dev->id);
+        for (;;) {
+            bool progress = false;
+            for (int k = 0; k < 2; k++) {
+                Part &p = part[(next_admit + k) & 1];
+                progress |= harvest(p);
+                if (!p.busy) {
+                    launch(p);
+                    progress |= p.busy;
+                }
+            }
+            next_admit ^= 1;
+            const bool idle = !part[0].busy && !part[1].busy;
+            std::unique_lock<std::mutex> g(mu);
+            if (idle && pending.empty()) {
+                if (stop) break;
+                cv.wait_for(g, std::chrono::milliseconds(5));
+            } else if (!progress) {
+                g.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
+            }
+        }
+    } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> g(c->lock);
+        c->err = std::string("server: ") + e.what();
+        stop = true;
+    }
+}
+
 }  // namespace mm
 
-extern "C" {
-int mm_server_start(mm_ctx *, size_t, uint32_t, mm_server **) { return MM_ESTATE; }
-int mm_submit(mm_server *, int, const uint32_t *, uint64_t *) { return MM_ESTATE; }
-int mm_poll(mm_server *, uint64_t, uint32_t *) { return MM_ESTATE; }
-int mm_server_stats(mm_server *, double *, double *, double *, uint64_t *) { return MM_ESTATE; }
-int mm_server_stop(mm_server *) { return MM_ESTATE; }
-int mm_server_replay(mm_server *, const int *, const uint32_t *, const int64_t *, size_t, uint32_t *, double *)
+struct mm_server {
+    mm::Server *s;
+};
+
+namespace {
+
+template <class F>
+int srv_guard(mm_ctx *c, F &&f)
 {
-    return MM_ESTATE;
+    try {
+        f();
+        return MM_OK;
+    } catch (const mm::Error &e) {
+        if (c) c->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return MM_ENOMEM;
+    } catch (const std::exception &e) {
+        if (c) c->err = e.what();
+        return MM_EDEVICE;
+    }
 }
+
+}  // namespace
+
+extern "C" {
+
+int mm_server_start(mm_ctx *ctx, size_t hbm_budget_bytes, uint32_t chunk_steps, mm_server **out)
+{
+    if (!ctx || !out) return MM_EINVAL;
+    if (ctx->server) return MM_ESTATE;
+    return srv_guard(ctx, [&] {
+        mm::Server *s;
+        {
+            std::lock_guard<std::mutex> g(ctx->lock);
+            s = mm::server_start(*ctx, hbm_budget_bytes, chunk_steps);
+        }
+        ctx->server = s;
+        *out = new mm_server{s};
+    });
 }
+
+int mm_submit(mm_server *h, int table_id, const uint32_t *ct, uint64_t *ticket)
+{
+    if (!h || !h->s || !ct || !ticket) return MM_EINVAL;
+    int rc = MM_OK;
+    *ticket = h->s->submit(table_id, ct, mm::clk::now(), &rc);
+    return rc;
+}
+
+int mm_poll(mm_server *h, uint64_t ticket, uint32_t *ct_out)
+{
+    if (!h || !h->s || !ct_out) return MM_EINVAL;
+    mm::Server &s = *h->s;
+    std::lock_guard<std::mutex> g(s.mu);
+    auto it = s.done.find(ticket);
+    if (it == s.done.end()) return (ticket > 0 && ticket < s.next_ticket) ? MM_EAGAIN : MM_EINVAL;
+    std::memcpy(ct_out, it->second.ct.data(), it->second.ct.size() * 4);
+    s.done.erase(it);
+    return MM_OK;
+}
+
+int mm_server_stats(mm_server *h, double *p50_ms, double *p99_ms, double *boots_per_s, uint64_t *completed)
+{
+    if (!h || !h->s) return MM_EINVAL;
+    mm::Server &s = *h->s;
+    std::lock_guard<std::mutex> g(s.mu);
+    std::vector<double> v(s.lat);
+    auto pct = [&](double q) {
+        if (v.empty()) return 0.0;
+        size_t k = (size_t)(q * (v.size() - 1) + 0.5);
+        std::nth_element(v.begin(), v.begin() + k, v.end());
+        return v[k];
+    };
+    if (p50_ms) *p50_ms = pct(0.50);
+    if (p99_ms) *p99_ms = pct(0.99);
+    if (boots_per_s) {
+        const double secs = s.completed ? std::chrono::duration<double>(s.t_last - s.t_first).count() : 0.0;
+        *boots_per_s = secs > 0 ? (double)s.completed / secs : 0.0;
+    }
+    if (completed) *completed = s.completed;
+    return MM_OK;
+}
+
+int mm_server_stop(mm_server *h)
+{
+    if (!h || !h->s) return MM_EINVAL;
+    mm_ctx *c = h->s->c;
+    mm::server_stop(h->s);
+    if (c) c->server = nullptr;
+    delete h;
+    return MM_OK;
+}
+
+int mm_server_replay(mm_server *h, const int *table_ids, const uint32_t *ct_in, const int64_t *arrival_ns,
+                     size_t count, uint32_t *ct_out, double *latency_ms)
+{
+    if (!h || !h->s || (count && (!table_ids || !ct_in || !arrival_ns || !ct_out || !latency_ms))) return MM_EINVAL;
+    mm::Server &s = *h->s;
+    const size_t W = s.c->p.n + 1;
+    const auto start = mm::clk::now();
+    std::vector<uint64_t> tickets(count, 0);
+    std::vector<mm::clk::time_point> t0(count);
+    size_t next_poll = 0;
+    auto poll_some = [&](bool all) {
+        std::lock_guard<std::mutex> g(s.mu);
+        while (next_poll < count && tickets[next_poll]) {
+            auto it = s.done.find(tickets[next_poll]);
+            if (it == s.done.end()) {
+                if (!all) break;
+                return false;
+            }
+            std::memcpy(ct_out + next_poll * W, it->second.ct.data(), W * 4);
+            latency_ms[next_poll] = it->second.ms;
+            s.done.erase(it);
+            next_poll++;
+        }
+        return next_poll == count;
+    };
+    for (size_t k = 0; k < count; k++) {
+        t0[k] = start + std::chrono::nanoseconds(arrival_ns[k]);
+        for (;;) {  // wait for the scheduled arrival
+            const auto now = mm::clk::now();
+            if (now >= t0[k]) break;
+            const auto gap = t0[k] - now;
+            if (gap > std::chrono::microseconds(200)) std::this_thread::sleep_for(gap - std::chrono::microseconds(100));
+        }
+        for (;;) {
+            int rc = MM_OK;
+            tickets[k] = s.submit(table_ids[k], ct_in + k * W, t0[k], &rc);
+            if (rc == MM_OK) break;
+            if (rc != MM_EBUSY) return rc;
+            std::this_thread::sleep_for(std::chrono::microseconds(100));
+        }
+        if ((k & 63) == 63) poll_some(false);
+    }
+    for (;;) {
+        if (poll_some(false) && next_poll == count) break;
+        if (s.stop) return MM_EDEVICE;
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    return MM_OK;
+}
+
+}  // extern "C"
