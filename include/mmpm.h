@@ -190,6 +190,12 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
 int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
                 int *choice);
 
+/* Number of candidate schedules for this batch shape, and pinning one of
+ * them (0 <= choice < *n) for the shape without timing; every schedule gives
+ * identical results. */
+int mm_schedule_count(mm_ctx *ctx, const int *table_ids, size_t count, int *n);
+int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice);
+
 /* ---- serving: continuous batching ---- */
 
 /* Start a server on ctx.  It owns up to `slots` in-flight ciphertexts whose

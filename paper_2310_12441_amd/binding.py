@@ -23,7 +23,8 @@ SYMBOLS = [
     "mm_keygen", "mm_free", "mm_last_error", "mm_get_params", "mm_export_bsk", "mm_export_ksk",
     "mm_device_init", "mm_table_create", "mm_table_info", "mm_table_export", "mm_encrypt", "mm_decrypt",
     "mm_bootstrap", "mm_modswitch", "mm_blind_rotate", "mm_external_product", "mm_sample_extract",
-    "mm_keyswitch", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune", "mm_server_start", "mm_submit", "mm_poll",
+    "mm_keyswitch", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune",
+    "mm_schedule_count", "mm_set_schedule", "mm_server_start", "mm_submit", "mm_poll",
     "mm_server_stats", "mm_server_stop", "mm_server_replay",
 ]
 
@@ -71,6 +72,8 @@ def _load():
         "mm_set_timing": (i32, [vp, i32]),
         "mm_last_timing": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "mm_autotune": (i32, [vp, vp, vp, sz, C.POINTER(i32)]),
+        "mm_schedule_count": (i32, [vp, vp, sz, C.POINTER(i32)]),
+        "mm_set_schedule": (i32, [vp, vp, sz, i32]),
         "mm_server_start": (i32, [vp, sz, u32, C.POINTER(vp)]),
         "mm_submit": (i32, [vp, i32, vp, C.POINTER(u64)]),
         "mm_poll": (i32, [vp, u64, vp]),
@@ -286,6 +289,16 @@ class Context:
         self._check(lib.mm_autotune(self.h, ids.ctypes.data_as(C.c_void_p), ct.ctypes.data_as(C.c_void_p), ids.size,
                                     C.byref(ch)))
         return ch.value
+
+    def schedule_count(self, table_ids) -> int:
+        ids = _i32(np.atleast_1d(table_ids))
+        n = C.c_int()
+        self._check(lib.mm_schedule_count(self.h, ids.ctypes.data_as(C.c_void_p), ids.size, C.byref(n)))
+        return n.value
+
+    def set_schedule(self, table_ids, choice: int):
+        ids = _i32(np.atleast_1d(table_ids))
+        self._check(lib.mm_set_schedule(self.h, ids.ctypes.data_as(C.c_void_p), ids.size, choice))
 
     # ---- serving
     def server_start(self, hbm_budget_bytes: int, chunk_steps: int = 32) -> "Server":

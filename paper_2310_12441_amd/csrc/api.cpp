@@ -204,4 +204,18 @@ int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t
     return guard(ctx, [&] { *choice = mm::run_autotune(*ctx, table_ids, ct_in, count); });
 }
 
+int mm_schedule_count(mm_ctx *ctx, const int *table_ids, size_t count, int *n)
+{
+    if (!ctx || !n || !table_ids) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->lock);
+    return guard(ctx, [&] { *n = mm::schedule_count(*ctx, table_ids, count); });
+}
+
+int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
+{
+    if (!ctx || !table_ids) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->lock);
+    return guard(ctx, [&] { mm::set_schedule(*ctx, table_ids, count, choice); });
+}
+
 }  // extern "C"

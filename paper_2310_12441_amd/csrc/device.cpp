@@ -176,7 +176,7 @@ static void finish_out(uint32_t *host, const uint32_t *dev, size_t words, bool d
 // Pack ciphertexts into groups of 8 wave slots, first-fit over r descending,
 // each ciphertext's components on consecutive waves of one group.  cts[k] is
 // the task of ciphertext k with comp = 0; the result holds 8 tasks per group.
-std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts)
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw)
 {
     std::vector<size_t> order(cts.size());
     std::iota(order.begin(), order.end(), 0);
@@ -187,26 +187,26 @@ std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts)
     for (size_t o : order) {
         const uint32_t r = cts[o].r;
         size_t g = first_open;
-        while (g < used.size() && used[g] + r > 8) g++;
+        while (g < used.size() && used[g] + r > gw) g++;
         if (g == used.size()) {
             used.push_back(0);
             dev::WaveTask idle{};
             idle.ct = -1;
-            tasks.insert(tasks.end(), 8, idle);
+            tasks.insert(tasks.end(), gw, idle);
         }
         for (uint32_t j = 0; j < r; j++) {
             dev::WaveTask w = cts[o];
             w.comp = j;
-            tasks[g * 8 + used[g] + j] = w;
+            tasks[g * gw + used[g] + j] = w;
         }
         used[g] += r;
-        while (first_open < used.size() && used[first_open] == 8) first_open++;
+        while (first_open < used.size() && used[first_open] == gw) first_open++;
     }
     return tasks;
 }
 
 static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, size_t count, uint32_t flags,
-                                              uint32_t i0, const std::vector<uint64_t> &acc_off)
+                                              uint32_t i0, const std::vector<uint64_t> &acc_off, uint32_t gw = 8)
 {
     std::vector<dev::WaveTask> cts(count);
     for (size_t k = 0; k < count; k++) {
@@ -221,7 +221,7 @@ static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, s
         w.flags = flags;
         w.acc_off = acc_off.empty() ? 0 : acc_off[k];
     }
-    return pack_tasks(cts);
+    return pack_tasks(cts, gw);
 }
 
 static void check_ids(const mm_ctx &c, const int *ids, size_t count)
@@ -269,10 +269,29 @@ uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count)
     return (uint32_t)P;
 }
 
+// Key-switch schedule for `count` samples: the LDS-tiled kernel (cpw > 0)
+// for large batches, the i-split kernel for small ones.
+KsSched ks_default(const mm_ctx &c, const Device &d, size_t count)
+{
+    KsSched k;
+    const uint32_t rows = c.p.l_ks << c.p.log2_Bks;
+    if (count >= 256 && rows <= (uint32_t)dev::KS_TILED_MAX_ROWS) {
+        k.cpw = 32;
+        const size_t blocks = ((c.p.n + 1 + 63) / 64) * ((count + 4 * k.cpw - 1) / (4 * k.cpw));
+        k.P = (uint32_t)std::max<size_t>(1, std::min<size_t>(4, (2 * (size_t)d.num_cu + blocks - 1) / blocks));
+    } else {
+        k.cpw = 0;
+        k.P = ks_splits(c, d, count);
+    }
+    return k;
+}
+
+size_t ks_part_words(const mm_ctx &c, const KsSched &k, size_t count) { return (size_t)k.P * count * (c.p.n + 1); }
+
 // Enqueue key switch + final modulus switch of `count` extracted samples
 // (row k of the output is sample rows[k] of ext, or sample k when rows is null).
 void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const int32_t *rows, size_t count,
-                       uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, uint32_t P, uint64_t *part,
+                       uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, const KsSched &ks, uint64_t *part,
                        hipStream_t st)
 {
     dev::KsArgs K{};
@@ -286,17 +305,67 @@ void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const in
     K.Q = c.p.Q;
     K.log2Bks = c.p.log2_Bks;
     K.l_ks = c.p.l_ks;
-    dev::launch_keyswitch(K, P, st);
-    dev::launch_ks_finalize(part, ext, rows, out, count, c.p.n, c.p.N, P, c.p.Q, q_out_per_ct, q_out, st);
+    if (ks.cpw > 0) dev::launch_keyswitch_tiled(K, ks.cpw, ks.P, st);
+    else dev::launch_keyswitch(K, ks.P, st);
+    dev::launch_ks_finalize(part, ext, rows, out, count, c.p.n, c.p.N, ks.P, c.p.Q, q_out_per_ct, q_out, st);
 }
+
+static uint32_t max_r(const mm_ctx &c, const int *ids, size_t count)
+{
+    uint32_t m = 1;
+    for (size_t i = 0; i < count; i++) m = std::max(m, c.tables[ids[i]].r);
+    return m;
+}
+
+static std::string shape_key(const mm_ctx &c, const int *ids, size_t count)
+{
+    uint64_t sum_r = 0;
+    for (size_t i = 0; i < count; i++) sum_r += c.tables[ids[i]].r;
+    return std::to_string(c.p.N) + "/" + std::to_string(count) + "/" + std::to_string(sum_r) + "/" +
+           std::to_string(max_r(c, ids, count));
+}
+
+// Candidate schedules for a batch: group width x key-switch tiling.
+static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int *ids, size_t count)
+{
+    std::vector<Sched> out;
+    const bool narrow_ok = max_r(c, ids, count) <= 4;
+    std::vector<KsSched> ks{ks_default(c, d, count)};
+    const uint32_t rows = c.p.l_ks << c.p.log2_Bks;
+    if (rows <= (uint32_t)dev::KS_TILED_MAX_ROWS && count >= 64)
+        for (int cpw : {16, 32, 64})
+            for (uint32_t P : {1u, 2u, 4u}) {
+                KsSched k{cpw, P};
+                if (k.cpw != ks[0].cpw || k.P != ks[0].P) ks.push_back(k);
+            }
+    if (count < 256) ks.push_back(KsSched{0, ks_splits(c, d, count)});
+    for (int gw : {8, 4}) {
+        if (gw == 4 && !narrow_ok) continue;
+        for (auto &k : ks) out.push_back(Sched{gw, k});
+    }
+    return out;
+}
+
+static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size_t count)
+{
+    auto it = d.tuned.find(shape_key(c, ids, count));
+    if (it != d.tuned.end()) {
+        auto cand = candidates(c, d, ids, count);
+        if (it->second >= 0 && (size_t)it->second < cand.size()) return cand[it->second];
+    }
+    return Sched{8, ks_default(c, d, count)};
+}
+
+static int br_grid(const Device &d, int groups, int gw) { return std::min(groups, d.num_cu * (gw == 4 ? 2 : 1)); }
 
 // The batched path for ciphertexts already on the device.
 static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
-                            uint32_t q_out, bool use_graph, hipStream_t st)
+                            uint32_t q_out, bool use_graph, hipStream_t st, const Sched *force = nullptr)
 {
-    const uint32_t N = c.p.N, W = c.p.n + 1;
-    auto tasks = pack_groups(c, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {});
-    const int groups = (int)(tasks.size() / 8);
+    const uint32_t N = c.p.N;
+    const Sched S = force ? *force : schedule_for(c, d, ids, count);
+    auto tasks = pack_groups(c, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw);
+    const int groups = (int)(tasks.size() / S.gw);
     // per-ciphertext output modulus
     const uint32_t *qv = nullptr;
     uint32_t q_scalar = q_out;
@@ -314,10 +383,9 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
             qv = dq;
         }
     }
-    const uint32_t P = ks_splits(c, d, count);
     // allocate every buffer before a capture
     uint32_t *ext = (uint32_t *)ws(d, WS_EXT, count * (N + 1) * 4);
-    uint64_t *part = (uint64_t *)ws(d, WS_PART, (size_t)P * count * W * 8);
+    uint64_t *part = (uint64_t *)ws(d, WS_PART, ks_part_words(c, S.ks, count) * 8);
     dev::WaveTask *dt = upload_tasks(d, tasks, st);
 
     dev::BrArgs A = br_args(c, d);
@@ -327,11 +395,13 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
     A.ct_in = d_in;
     A.ext_out = ext;
     A.acc_state = nullptr;
-    const int grid = std::min(groups, d.num_cu);
+    const int grid = br_grid(d, groups, S.gw);
 
     const bool timed = d.timing;
-    auto enqueue_br = [&](hipStream_t s) { dev::launch_blind_rotate(N, A, grid, s); };
-    auto enqueue_ks = [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, P, part, s); };
+    auto enqueue_br = [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s); };
+    auto enqueue_ks = [&](hipStream_t s) {
+        enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, S.ks, part, s);
+    };
     if (!use_graph) {
         if (timed) HIPC(hipEventRecord(d.tev[0], st));
         enqueue_br(st);
@@ -341,10 +411,10 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
         HIPC(hipGetLastError());
         return;
     }
-    const std::string key = std::to_string(count) + "/" + std::to_string(groups) + "/" + std::to_string(P) + "/" +
-                            std::to_string(q_scalar) + "/" + std::to_string((uintptr_t)qv) + "/" +
-                            std::to_string((uintptr_t)d_in) + "/" + std::to_string((uintptr_t)d_out) + "/" +
-                            std::to_string(d.ws_generation);
+    const std::string key = std::to_string(count) + "/" + std::to_string(groups) + "/" + std::to_string(S.gw) + "/" +
+                            std::to_string(S.ks.cpw) + "/" + std::to_string(S.ks.P) + "/" + std::to_string(q_scalar) +
+                            "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
+                            std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
     // One graph holds the whole launch sequence; with timing on, the blind
     // rotation and the key switch are two graphs so that events can sit
     // between them on the stream.
@@ -429,7 +499,7 @@ void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t c
     A.steps = (int)steps;
     A.ct_in = d_in;
     A.acc_state = d_acc;
-    dev::launch_blind_rotate(N, A, std::min(A.num_groups, d.num_cu), st);
+    dev::launch_blind_rotate(N, A, 8, std::min(A.num_groups, d.num_cu), st);
     HIPC(hipGetLastError());
     finish_out(acc_out, d_acc, words, dptr, st);
 }
@@ -505,9 +575,9 @@ void run_keyswitch(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe
     const uint32_t N = c.p.N, W = c.p.n + 1;
     const uint32_t *din = stage_in(d, WS_IN, lwe_N, count * (N + 1), dptr, st);
     uint32_t *dout = stage_out(d, WS_OUT, lwe_n, count * W, dptr);
-    const uint32_t P = ks_splits(c, d, count);
-    uint64_t *part = (uint64_t *)ws(d, WS_PART, (size_t)P * count * W * 8);
-    enqueue_keyswitch(c, d, din, nullptr, count, dout, nullptr, c.p.Q, P, part, st);
+    const KsSched ks = ks_default(c, d, count);
+    uint64_t *part = (uint64_t *)ws(d, WS_PART, ks_part_words(c, ks, count) * 8);
+    enqueue_keyswitch(c, d, din, nullptr, count, dout, nullptr, c.p.Q, ks, part, st);
     HIPC(hipGetLastError());
     finish_out(lwe_n, dout, count * W, dptr, st);
 }
@@ -532,13 +602,65 @@ void last_timing(mm_ctx &c, float *br_ms, float *ks_ms)
     if (ks_ms) *ks_ms = b;
 }
 
+int schedule_count(mm_ctx &c, const int *ids, size_t count)
+{
+    check_ids(c, ids, count);
+    MM_REQUIRE(count > 0, "empty batch");
+    Device &d = ensure_device(c);
+    return (int)candidates(c, d, ids, count).size();
+}
+
+void set_schedule(mm_ctx &c, const int *ids, size_t count, int choice)
+{
+    const int n = schedule_count(c, ids, count);
+    MM_REQUIRE(choice >= 0 && choice < n, "schedule index out of range");
+    c.dev->tuned[shape_key(c, ids, count)] = choice;
+}
+
+// Time every candidate schedule on this batch (one untimed run each, then the
+// blind rotation and the key switch measured separately) and remember the
+// fastest combination for the batch shape.
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
 {
-    (void)c;
-    (void)ids;
-    (void)ct_in;
-    (void)count;
-    return 0;
+    check_ids(c, ids, count);
+    MM_REQUIRE(count > 0, "empty batch");
+    Device &d = ensure_device(c);
+    const size_t W = c.p.n + 1;
+    hipStream_t st = d.own;
+    const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * W, false, st);
+    uint32_t *d_out = stage_out(d, WS_OUT, nullptr, count * W, false);
+    HIPC(hipStreamSynchronize(st));
+    auto cand = candidates(c, d, ids, count);
+    const bool was_timed = d.timing;
+    if (!d.tev[0])
+        for (auto &e : d.tev) HIPC(hipEventCreate(&e));
+    d.timing = true;
+    // best blind rotation per group width, best key switch overall
+    float best_br[2] = {1e30f, 1e30f}, best_ks = 1e30f;
+    KsSched ks_best = cand[0].ks;
+    for (size_t k = 0; k < cand.size(); k++) {
+        const Sched &S = cand[k];
+        bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
+        HIPC(hipStreamSynchronize(st));
+        bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
+        HIPC(hipEventSynchronize(d.tev[2]));
+        float br = 0, ks = 0;
+        HIPC(hipEventElapsedTime(&br, d.tev[0], d.tev[1]));
+        HIPC(hipEventElapsedTime(&ks, d.tev[1], d.tev[2]));
+        const int gi = S.gw == 4 ? 1 : 0;
+        best_br[gi] = std::min(best_br[gi], br);
+        if (ks < best_ks) {
+            best_ks = ks;
+            ks_best = S.ks;
+        }
+    }
+    d.timing = was_timed;
+    const int gw = best_br[1] < best_br[0] ? 4 : 8;
+    int choice = 0;
+    for (size_t k = 0; k < cand.size(); k++)
+        if (cand[k].gw == gw && cand[k].ks.cpw == ks_best.cpw && cand[k].ks.P == ks_best.P) choice = (int)k;
+    d.tuned[shape_key(c, ids, count)] = choice;
+    return choice;
 }
 
 }  // namespace mm

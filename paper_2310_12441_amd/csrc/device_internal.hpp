@@ -46,7 +46,7 @@ struct Device {
         hipGraphExec_t exec = nullptr;
     };
     std::vector<Graph> graphs;
-    std::map<std::string, int> tuned;  // batch shape -> schedule index
+    std::map<std::string, int> tuned;  // batch shape -> index into the schedule candidates
     int ws_generation = 0;
     bool timing = false;
     hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // before BR, after BR, after key switch
@@ -74,11 +74,26 @@ struct Device {
 Device &ensure_device(mm_ctx &c);
 void *ws(Device &d, int slot, size_t bytes);
 void *pinned(Device &d, int slot, size_t bytes);
-std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts);
+// A key-switch schedule: cpw > 0 selects the LDS-tiled kernel with cpw
+// ciphertexts per wave, cpw = 0 the i-split kernel; P splits the i range.
+struct KsSched {
+    int cpw = 0;
+    uint32_t P = 1;
+};
+
+// A batch schedule: blind-rotation group width (8 or 4 waves) and key switch.
+struct Sched {
+    int gw = 8;
+    KsSched ks;
+};
+
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw);
+KsSched ks_default(const mm_ctx &c, const Device &d, size_t count);
+size_t ks_part_words(const mm_ctx &c, const KsSched &k, size_t count);
 dev::BrArgs br_args(const mm_ctx &c, const Device &d);
 uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count);
 void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const int32_t *rows, size_t count,
-                       uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, uint32_t P, uint64_t *part,
+                       uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, const KsSched &ks, uint64_t *part,
                        hipStream_t st);
 
 }  // namespace mm

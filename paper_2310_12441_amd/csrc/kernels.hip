@@ -48,8 +48,8 @@ struct BrLds {
     static constexpr int WAVE_WORDS = 2 * Geo<N>::POLYW + Geo<N>::SLOTW;
 };
 
-template <int N>
-__global__ void __launch_bounds__(512, 1) k_blind_rotate(BrArgs A)
+template <int N, int GW>
+__global__ void __launch_bounds__(64 * GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N>;
     constexpr int E = G::E, P = G::POLYW;
@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(512, 1) k_blind_rotate(BrArgs A)
     const GadgetC g{A.log2B, A.l, A.sg};
 
     for (int grp = blockIdx.x; grp < A.num_groups; grp += gridDim.x) {
-        const WaveTask T = A.tasks[grp * 8 + wave];
+        const WaveTask T = A.tasks[grp * GW + wave];
         const bool has = T.ct >= 0;
         const uint32_t r = has ? T.r : 1u, M = 2u * N * r;
         const uint32_t *ct = A.ct_in + (size_t)(has ? T.ct : 0) * A.ct_stride;
@@ -273,6 +273,83 @@ __global__ void __launch_bounds__(256) k_keyswitch(KsArgs A)
     }
 }
 
+// Key switch for large batches.  A workgroup (4 waves) owns 64 columns of the
+// output and 4 CPW ciphertexts; for each input coordinate i it stages the
+// l_ks x B_ks candidate rows KSK[i][*][*][cols] in LDS (double-buffered through
+// registers) and every wave adds, for each of its CPW ciphertexts, the l_ks rows
+// its digits select.  KSK traffic: one read of the column slice per ciphertext
+// tile.  Partial sums over the i-split blockIdx.z go to part (reduced mod Q).
+template <int CPW>
+__global__ void __launch_bounds__(256) k_keyswitch_tiled(KsArgs A)
+{
+    constexpr int ROWS = KS_TILED_MAX_ROWS;  // l_ks * B_ks <= 128
+    __shared__ uint32_t tile[2][ROWS * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t W = A.n + 1, Bks = 1u << A.log2Bks, rows = A.l_ks * Bks;
+    const uint32_t col0 = blockIdx.x * 64, col = col0 + lane;
+    const uint32_t iper = (A.N + gridDim.z - 1) / gridDim.z;
+    const uint32_t i_begin = blockIdx.z * iper, i_end = min(A.N, i_begin + iper);
+    const size_t ct_base = ((size_t)blockIdx.y * 4 + wave) * CPW;
+    // lane q of the wave reads coordinate i of ciphertext ct_base + q (q < CPW)
+    const size_t my_ct = ct_base + (lane < CPW ? lane : 0);
+    const bool my_ok = lane < CPW && my_ct < A.count;
+    const uint32_t *my_src = A.lwe_N + (my_ok ? (A.rows ? (size_t)A.rows[my_ct] : my_ct) : 0) * (A.N + 1);
+    uint32_t acc[CPW];
+#pragma unroll
+    for (int q = 0; q < CPW; q++) acc[q] = 0;
+
+    // each thread moves rows*64/256 words of a tile
+    const int per_thread = (int)(rows * 64 / 256);
+    uint32_t stage[ROWS / 4];
+    auto fetch = [&](uint32_t i) {
+        const uint32_t *base = A.ksk + (size_t)i * rows * W;
+#pragma unroll
+        for (int k = 0; k < ROWS / 4; k++) {
+            if (k < per_thread) {
+                const uint32_t e = threadIdx.x + 256u * k, rr = e >> 6, c = col0 + (e & 63);
+                stage[k] = c < W ? base[(size_t)rr * W + c] : 0u;
+            }
+        }
+    };
+    auto put = [&](int b) {
+#pragma unroll
+        for (int k = 0; k < ROWS / 4; k++)
+            if (k < per_thread) tile[b][threadIdx.x + 256 * k] = stage[k];
+    };
+    if (i_begin < i_end) {
+        fetch(i_begin);
+        put(0);
+    }
+    __syncthreads();
+    int b = 0;
+    for (uint32_t i = i_begin; i < i_end; i++) {
+        if (i + 1 < i_end) fetch(i + 1);
+        const uint32_t mine = my_ok ? my_src[i] : 0u;
+#pragma unroll
+        for (int q = 0; q < CPW; q++) {
+            const uint32_t a = __builtin_amdgcn_readlane(mine, q);
+            uint32_t s = 0;
+            for (uint32_t j = 0; j < A.l_ks; j++) {
+                const uint32_t sh = j * A.log2Bks;
+                const uint32_t d = sh < 32 ? (a >> sh) & (Bks - 1) : 0u;
+                s = add_q(s, tile[b][(j * Bks + d) * 64 + lane], A.Q);
+            }
+            acc[q] = add_q(acc[q], s, A.Q);
+        }
+        __syncthreads();
+        if (i + 1 < i_end) put(b ^ 1);
+        __syncthreads();
+        b ^= 1;
+    }
+    if (col < W) {
+#pragma unroll
+        for (int q = 0; q < CPW; q++) {
+            const size_t ct = ct_base + q;
+            if (ct < A.count) A.part[((size_t)blockIdx.z * A.count + ct) * W + col] = acc[q];
+        }
+    }
+}
+
 // (0^n, b) - sum of the partials, then the modulus switch Q -> q_out
 // (q_out = Q keeps the residues).  out[ct][n+1].
 __global__ void k_ks_finalize(const uint64_t *__restrict__ part, const uint32_t *__restrict__ lwe_N,
@@ -320,44 +397,52 @@ void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows
 
 // ------------------------------------------------------------------ launchers
 
-template <int N>
-static void launch_br_n(const BrArgs &A, int grid, hipStream_t st)
-{
-    const size_t lds = (size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_blind_rotate<N>, dim3(grid), dim3(512), lds, st, A);
-}
-
-template <int N>
+template <int N, int GW>
 static hipError_t br_attr_n()
 {
-    return hipFuncSetAttribute((const void *)k_blind_rotate<N>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)((size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t)));
+    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((size_t)GW * BrLds<N>::WAVE_WORDS * sizeof(uint32_t)));
 }
 
 hipError_t init_kernel_attributes()
 {
-    hipError_t e = br_attr_n<256>();
-    if (e == hipSuccess) e = br_attr_n<512>();
-    if (e == hipSuccess) e = br_attr_n<1024>();
+    hipError_t e = br_attr_n<256, 8>();
+    if (e == hipSuccess) e = br_attr_n<512, 8>();
+    if (e == hipSuccess) e = br_attr_n<1024, 8>();
+    if (e == hipSuccess) e = br_attr_n<256, 4>();
+    if (e == hipSuccess) e = br_attr_n<512, 4>();
+    if (e == hipSuccess) e = br_attr_n<1024, 4>();
     return e;
 }
 
-void launch_blind_rotate(uint32_t N, const BrArgs &A, int grid, hipStream_t st)
+template <int N>
+static void launch_br_n(const BrArgs &A, int gw, int grid, hipStream_t st)
+{
+    if (gw == 4) {
+        const size_t lds = (size_t)4 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_blind_rotate<N, 4>), dim3(grid), dim3(256), lds, st, A);
+    } else {
+        const size_t lds = (size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_blind_rotate<N, 8>), dim3(grid), dim3(512), lds, st, A);
+    }
+}
+
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st)
 {
     switch (N) {
-    case 256: launch_br_n<256>(A, grid, st); break;
-    case 512: launch_br_n<512>(A, grid, st); break;
-    case 1024: launch_br_n<1024>(A, grid, st); break;
+    case 256: launch_br_n<256>(A, gw, grid, st); break;
+    case 512: launch_br_n<512>(A, gw, grid, st); break;
+    case 1024: launch_br_n<1024>(A, gw, grid, st); break;
     default: break;
     }
 }
 
-size_t br_lds_bytes(uint32_t N)
+size_t br_lds_bytes(uint32_t N, int gw)
 {
     switch (N) {
-    case 256: return (size_t)8 * BrLds<256>::WAVE_WORDS * 4;
-    case 512: return (size_t)8 * BrLds<512>::WAVE_WORDS * 4;
-    default: return (size_t)8 * BrLds<1024>::WAVE_WORDS * 4;
+    case 256: return (size_t)gw * BrLds<256>::WAVE_WORDS * 4;
+    case 512: return (size_t)gw * BrLds<512>::WAVE_WORDS * 4;
+    default: return (size_t)gw * BrLds<1024>::WAVE_WORDS * 4;
     }
 }
 
@@ -416,6 +501,18 @@ void launch_sample_extract(const uint32_t *rlwe, uint32_t *lwe, size_t count, ui
     const size_t total = count * (N + 1);
     const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_sample_extract, dim3(std::max(grid, 1)), dim3(256), 0, st, rlwe, lwe, count, N, Q);
+}
+
+void launch_keyswitch_tiled(const KsArgs &A, int cpw, uint32_t splits, hipStream_t st)
+{
+    const uint32_t W = A.n + 1;
+    const uint32_t cts_per_block = 4u * cpw;
+    dim3 grid((W + 63) / 64, (uint32_t)((A.count + cts_per_block - 1) / cts_per_block), splits);
+    switch (cpw) {
+    case 16: hipLaunchKernelGGL(k_keyswitch_tiled<16>, grid, dim3(256), 0, st, A); break;
+    case 32: hipLaunchKernelGGL(k_keyswitch_tiled<32>, grid, dim3(256), 0, st, A); break;
+    default: hipLaunchKernelGGL(k_keyswitch_tiled<64>, grid, dim3(256), 0, st, A); break;
+    }
 }
 
 void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st)

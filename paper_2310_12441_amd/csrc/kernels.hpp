@@ -14,8 +14,9 @@ enum : uint32_t {
     TASK_EXTRACT = 4u,  // component 0 writes the extracted LWE_N sample when step n is reached
 };
 
-// What one wave of a blind-rotation workgroup does.  A group is 8 consecutive
-// WaveTasks; the components 0..r-1 of a ciphertext sit on consecutive waves.
+// What one wave of a blind-rotation workgroup does.  A group is GW (8 or 4)
+// consecutive WaveTasks; the components 0..r-1 of a ciphertext sit on
+// consecutive waves of one group.
 struct WaveTask {
     int32_t ct;        // ciphertext index, -1 for an idle wave
     uint32_t comp;     // component j
@@ -43,12 +44,13 @@ struct BrArgs {
 };
 
 constexpr int KS_CTS_PER_WAVE = 4;
+constexpr int KS_TILED_MAX_ROWS = 128;  // l_ks * B_ks handled by the LDS-tiled key switch
 
 struct KsArgs {
     const uint32_t *lwe_N;  // extracted samples at Q, [*][N + 1]
     const int32_t *rows;    // output row k reads sample rows[k] (null: sample k)
     const uint32_t *ksk;    // [N][l_ks][B_ks][n + 1]
-    uint64_t *part;         // [splits][count][n + 1]
+    uint64_t *part;         // [splits][count][n + 1] (the tiled kernel writes u32 residues into u64 slots)
     size_t count;
     uint32_t n, N, Q, log2Bks, l_ks;
 };
@@ -56,8 +58,8 @@ struct KsArgs {
 hipError_t init_kernel_attributes();
 void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,
                          hipStream_t st);
-void launch_blind_rotate(uint32_t N, const BrArgs &A, int grid, hipStream_t st);
-size_t br_lds_bytes(uint32_t N);
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st);
+size_t br_lds_bytes(uint32_t N, int gw);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
                              const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,
                              uint32_t l, uint32_t sg, hipStream_t st);
@@ -69,6 +71,7 @@ void launch_modswitch(const uint32_t *in, uint32_t *out, size_t count, uint32_t 
 void launch_sample_extract(const uint32_t *rlwe, uint32_t *lwe, size_t count, uint32_t N, uint32_t Q,
                            hipStream_t st);
 void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st);
+void launch_keyswitch_tiled(const KsArgs &A, int cpw, uint32_t splits, hipStream_t st);
 void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, const int32_t *rows, uint32_t *out, size_t count,
                         uint32_t n,
                         uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct, uint32_t q_out,

@@ -323,18 +323,18 @@ void Server::launch(Part &p)
         w.flags = (a.step == 0 ? dev::TASK_INIT : 0u) | dev::TASK_STORE | dev::TASK_EXTRACT;
         w.acc_off = (uint64_t)a.unit * 2 * N;
     }
-    auto tasks = pack_tasks(cts);
+    auto tasks = pack_tasks(cts, 8);
     p.tasks.reserve(tasks.size());
     std::memcpy(p.tasks.h, tasks.data(), tasks.size() * sizeof(dev::WaveTask));
     SRV_HIP(hipMemcpyAsync(p.tasks.d, p.tasks.h, tasks.size() * sizeof(dev::WaveTask), hipMemcpyHostToDevice, p.st));
     dev::BrArgs A = br_args(*c, d);
     A.tasks = p.tasks.d;
-    A.num_groups = (int)(tasks.size() / 8);
+    A.num_groups = (int)(tasks.size() / 8);  // 8-wave groups (any r <= 8)
     A.steps = (int)chunk;
     A.ct_in = d_ct;
     A.acc_state = d_acc;
     A.ext_out = d_ext;
-    dev::launch_blind_rotate(N, A, std::min(A.num_groups, d.num_cu), p.st);
+    dev::launch_blind_rotate(N, A, 8, std::min(A.num_groups, d.num_cu), p.st);
 
     // ciphertexts that reach step n in this tick: key switch and copy back
     std::vector<Active> keep;
@@ -358,8 +358,8 @@ void Server::launch(Part &p)
         }
         SRV_HIP(hipMemcpyAsync(p.rows.d, p.rows.h, F * 4, hipMemcpyHostToDevice, p.st));
         SRV_HIP(hipMemcpyAsync(p.qout.d, p.qout.h, F * 4, hipMemcpyHostToDevice, p.st));
-        const uint32_t P = ks_splits(*c, d, F);
-        const size_t need = (size_t)P * F * W;
+        const KsSched ks = ks_default(*c, d, F);
+        const size_t need = ks_part_words(*c, ks, F);
         if (p.part_cap < need) {
             SRV_HIP(hipStreamSynchronize(p.st));
             if (p.part) SRV_HIP(hipFree(p.part));
@@ -368,7 +368,7 @@ void Server::launch(Part &p)
             if (hipMalloc((void **)&p.part, need * 2 * 8) != hipSuccess) throw Error(MM_ENOMEM, "server key-switch buffer");
             p.part_cap = need * 2;
         }
-        enqueue_keyswitch(*c, d, d_ext, p.rows.d, F, p.out.d, p.qout.d, 0, P, p.part, p.st);
+        enqueue_keyswitch(*c, d, d_ext, p.rows.d, F, p.out.d, p.qout.d, 0, ks, p.part, p.st);
         SRV_HIP(hipMemcpyAsync(p.out.h, p.out.d, F * W * 4, hipMemcpyDeviceToHost, p.st));
     }
     SRV_HIP(hipGetLastError());

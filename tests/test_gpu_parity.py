@@ -279,3 +279,43 @@ def test_bootstrap_device_pointers(paper):
     dev_out = paper.ctx.bootstrap([tid] * 3, dev_in)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(dev_out.cpu().numpy().view(np.uint32), host)
+
+
+def test_keyswitch_tiled_batch(paper):
+    """Large batches take the LDS-tiled key switch."""
+    say("keyswitch tiled 300")
+    rng = np.random.default_rng(300)
+    lw = rng.integers(0, Q, (300, paper.p.N + 1), dtype=np.uint32)
+    got = paper.ctx.keyswitch(lw)
+    for c in (0, 1, 150, 299):
+        np.testing.assert_array_equal(got[c], oracle.keyswitch(paper.p, paper.keys.ksk, lw[c]))
+
+
+def test_every_schedule_gives_the_same_bits(paper):
+    """All candidate schedules (4- and 8-wave groups, key-switch tilings) agree bit for bit."""
+    tabs = []
+    for k, (t, r) in enumerate(CLASS_MIX[:3]):  # r <= 4 admits 4-wave groups
+        tid, f, V = paper.table(t, t, r, 70 + k)
+        tabs.append((tid, t, r, V))
+    cls = class_mix(300, 9) % 3
+    ids = np.array([tabs[k][0] for k in cls], np.int32)
+    cts = np.array([paper.encrypt(2 * paper.p.N * tabs[k][2], tabs[k][1], messages(tabs[k][1], 1, 500 + c),
+                                  600 + c)[0] for c, k in enumerate(cls)])
+    n = paper.ctx.schedule_count(ids)
+    say("schedules", n)
+    assert n >= 4
+    ref = None
+    for choice in range(n):
+        paper.ctx.set_schedule(ids, choice)
+        out = paper.ctx.bootstrap(ids, cts)
+        if ref is None:
+            ref = out
+        np.testing.assert_array_equal(out, ref, err_msg=f"schedule {choice}")
+    for c in (0, 299):
+        tid, t, r, V = tabs[cls[c]]
+        q = 2 * paper.p.N * r
+        np.testing.assert_array_equal(ref[c], oracle.bootstrap(paper.p, r, paper.keys.bsk, paper.keys.ksk, V, q, q,
+                                                               cts[c]))
+    choice = paper.ctx.autotune(ids, cts)
+    assert 0 <= choice < n
+    np.testing.assert_array_equal(paper.ctx.bootstrap(ids, cts), ref)
