@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="ciphertexts timed on the plain path")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: one per host thread)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
+    ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -184,6 +186,42 @@ def main():
         "kernel_source_sha256_16": source_hash(),
     }
 
+    # ---- serving: Poisson arrivals of single bootstraps with mixed (t, k), keys resident
+    serving = None
+    if args.serve_requests > 0:
+        from synth import CLASS_MIX, class_mix, poisson_arrivals
+        R = args.serve_requests
+        tabs = []
+        for k, (tt, rr) in enumerate(CLASS_MIX):
+            tabs.append((ctx.table_create(tt, tt, rr, negacyclic_table(tt, tt, 100 + k)), tt, rr))
+        cls = class_mix(R, 7)
+        s_ids = np.array([tabs[k][0] for k in cls], np.int32)
+        s_ct = np.empty((R, p.n + 1), np.uint32)
+        for k, (tid_k, tt, rr) in enumerate(tabs):
+            sel = np.where(cls == k)[0]
+            qq = 2 * p.N * rr
+            edk = enc_draws(p.n, qq, sel.size, 200 + k)
+            s_ct[sel] = ctx.encrypt(qq, tt, messages(tt, sel.size, 300 + k), edk["a"], edk["e"])
+        alone = None
+        serving = {"rates_req_s": [], "p50_ms": [], "p99_ms": [], "completed_per_s": [], "requests_per_rate": R,
+                   "classes": [list(c) for c in CLASS_MIX], "chunk_steps": 63, "hbm_budget_bytes": 4 << 30}
+        for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+            srv = ctx.server_start(4 << 30, chunk_steps=63)
+            warm = min(512, R)
+            srv.replay(s_ids[:warm], s_ct[:warm], poisson_arrivals(rate, warm, 11))
+            srv.stop()
+            srv = ctx.server_start(4 << 30, chunk_steps=63)
+            out_s, lat = srv.replay(s_ids, s_ct, poisson_arrivals(rate, R, 12))
+            st = srv.stats()
+            srv.stop()
+            serving["rates_req_s"].append(rate)
+            serving["p50_ms"].append(round(float(np.percentile(lat, 50)), 3))
+            serving["p99_ms"].append(round(float(np.percentile(lat, 99)), 3))
+            serving["completed_per_s"].append(round(st["boots_per_s"], 1))
+            if alone is None:
+                alone = ctx.bootstrap(s_ids, s_ct)
+                serving["identical_to_alone"] = bool(np.array_equal(out_s, alone))
+
     # ---- CPU oracle on the host cores, on a bounded sample of the same batch
     cpu = None
     if not args.no_cpu:
@@ -223,6 +261,7 @@ def main():
         "schedule": schedule,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -252,6 +252,8 @@ dev::BrArgs br_args(const mm_ctx &c, const Device &d)
     A.log2B = c.p.log2_B;
     A.l = c.p.l;
     A.sg = c.sg;
+    A.goff = 0;
+    for (uint32_t u = 0; u + 1 < c.p.l; u++) A.goff += (1u << (c.p.log2_B - 1)) << (u * c.p.log2_B);
     A.bsk = d.bsk;
     A.twf = d.twf;
     A.twi = d.twi;

@@ -173,32 +173,28 @@ __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][Geo<N>::E], uint32_t *
 
 struct GadgetC {
     uint32_t log2B, l, sg;
+    uint32_t off;  // (B/2)(1 + B + ... + B^(l-2)): makes the low l-1 balanced digits unsigned bit fields
 };
 
-// Centred residue of x in [0, Q), rounded to a multiple of 2^sg and divided by it.
+// y' = round(centred(x) / 2^sg) + off for x in [0, Q]; x = Q is read as 0.
+// With the offset, balanced digit u < l-1 is bits [u log2B, (u+1) log2B) of y'
+// minus B/2, and the top digit is y' >> ((l-1) log2B) (arithmetic).
 __device__ __forceinline__ int32_t gadget_start(uint32_t x, const GadgetC &g, uint32_t Q)
 {
     int32_t xc = (x > (Q - 1) / 2) ? (int32_t)(x - Q) : (int32_t)x;
     if (g.sg) xc = (xc + (1 << (g.sg - 1))) >> g.sg;
-    return xc;
+    return xc + (int32_t)g.off;
 }
 
-// Next balanced base-2^log2B digit of y (low to high), as a residue mod Q; the
-// last digit keeps the remaining value (which may reach B/2).
-__device__ __forceinline__ uint32_t gadget_next(int32_t &y, bool last, const GadgetC &g, uint32_t Q)
+// Balanced digit u of y' as a residue mod Q.
+__device__ __forceinline__ uint32_t gadget_digit(int32_t y, uint32_t u, const GadgetC &g, uint32_t Q)
 {
-    int32_t d;
-    if (last) {
-        d = y;
-    } else {
-        const int32_t mask = (1 << g.log2B) - 1;
-        d = y & mask;
-        y >>= g.log2B;
-        const int32_t c = d > (mask >> 1) ? 1 : 0;
-        d -= c << g.log2B;
-        y += c;
+    if (u + 1 == g.l) {
+        const int32_t d = y >> (u * g.log2B);
+        return d < 0 ? (uint32_t)(d + (int32_t)Q) : (uint32_t)d;
     }
-    return d < 0 ? (uint32_t)(d + (int32_t)Q) : (uint32_t)d;
+    const uint32_t v = __builtin_amdgcn_ubfe((uint32_t)y, u * g.log2B, g.log2B) - (1u << (g.log2B - 1));
+    return min(v, v + Q);  // v < 0 as a signed value -> v + Q
 }
 
 // out = g^{-1}(Da, Db) x K for one RLWE pair in phase-0 layout, K the RGSW key
@@ -225,12 +221,11 @@ __device__ __forceinline__ void external_product(const uint32_t (&Da)[Geo<N>::E]
     for (uint32_t u = 0; u < g.l; u++) {
         // keep twiddle and key loads inside the iteration (register pressure)
         __asm__ volatile("" ::: "memory");
-        const bool last = (u + 1 == g.l);
         uint32_t pd[2][E];
 #pragma unroll
         for (int k = 0; k < E; k++) {
-            pd[0][k] = gadget_next(yb[k], last, g, m.Q);
-            pd[1][k] = gadget_next(ya[k], last, g, m.Q);
+            pd[0][k] = gadget_digit(yb[k], u, g, m.Q);
+            pd[1][k] = gadget_digit(ya[k], u, g, m.Q);
         }
         ntt_fwd<N, 2>(pd, slot, twf, L, m);
         // lane L now holds NTT positions E L .. E L + E - 1

@@ -19,6 +19,13 @@
 namespace mm {
 namespace dev {
 
+__host__ __device__ constexpr uint32_t gadget_offset(uint32_t log2B, uint32_t l)
+{
+    uint32_t off = 0;
+    for (uint32_t u = 0; u + 1 < l; u++) off += (1u << (log2B - 1)) << (u * log2B);
+    return off;
+}
+
 __device__ __forceinline__ uint32_t modswitch_dev(uint32_t x, uint32_t q_from, uint32_t q_to)
 {
     if (q_from == q_to) return x;
@@ -49,7 +56,7 @@ struct BrLds {
 };
 
 template <int N, int GW>
-__global__ void __launch_bounds__(64 * GW) k_blind_rotate(BrArgs A)
+__global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N>;
     constexpr int E = G::E, P = G::POLYW;
@@ -58,7 +65,7 @@ __global__ void __launch_bounds__(64 * GW) k_blind_rotate(BrArgs A)
     uint32_t *accl = lds + wave * BrLds<N>::WAVE_WORDS;  // [a | b], swizzled
     uint32_t *scr = accl + 2 * P;
     const ModQ m{A.Q, A.qn};
-    const GadgetC g{A.log2B, A.l, A.sg};
+    const GadgetC g{A.log2B, A.l, A.sg, A.goff};
 
     for (int grp = blockIdx.x; grp < A.num_groups; grp += gridDim.x) {
         const WaveTask T = A.tasks[grp * GW + wave];
@@ -101,18 +108,21 @@ __global__ void __launch_bounds__(64 * GW) k_blind_rotate(BrArgs A)
                 uint32_t src, e;
                 phi_row(c, r, T.comp, src, e);
                 const uint32_t *sp = lds + (wave - (int)T.comp + (int)src) * BrLds<N>::WAVE_WORDS;
+                // coefficient idx of x^e v is v[(idx - e) mod 2N], negated when that index is >= N;
+                // a negated source enters D as Q - v (Q is read as 0 by the decomposition)
+                const uint32_t base = (uint32_t)(L + 2 * N - (e % (2 * N)));
 #pragma unroll
                 for (int k = 0; k < E; k++) {
-                    const uint32_t idx = 64 * k + L;
-                    const uint32_t i2 = (idx + 2 * N - e) % (2 * N);
+                    const uint32_t i2 = (base + 64 * k) & (2 * N - 1);
                     const int a = swz(i2 & (N - 1));
                     uint32_t va = sp[a], vb = sp[P + a];
-                    if (i2 >= N) {
-                        va = va ? A.Q - va : 0;
-                        vb = vb ? A.Q - vb : 0;
+                    if (i2 & N) {
+                        va = A.Q - va;
+                        vb = A.Q - vb;
                     }
-                    D[0][k] = sub_q(va, accl[swz(idx)], A.Q);
-                    D[1][k] = sub_q(vb, accl[P + swz(idx)], A.Q);
+                    const int o = swz(64 * k + L);
+                    D[0][k] = sub_q(va, accl[o], A.Q);
+                    D[1][k] = sub_q(vb, accl[P + o], A.Q);
                 }
             }
             __syncthreads();  // every rotated read of this step is done
@@ -168,7 +178,7 @@ __global__ void __launch_bounds__(256) k_external_product(const uint32_t *__rest
     if (c >= count) return;
     uint32_t *slot = lds + wave * G::SLOTW;
     const ModQ m{Q, qn};
-    const GadgetC g{log2B, l, sg};
+    const GadgetC g{log2B, l, sg, gadget_offset(log2B, l)};
     uint32_t D[2][E], o[2][E];
 #pragma unroll
     for (int k = 0; k < E; k++) {

@@ -35,7 +35,7 @@ struct BrArgs {
     int steps;                 // CMux steps per launch
     const uint32_t *ct_in;     // ciphertexts at their q_in
     uint32_t ct_stride;        // n + 1
-    uint32_t n, Q, qn, log2B, l, sg;
+    uint32_t n, Q, qn, log2B, l, sg, goff;
     const uint32_t *bsk;       // [n][2l][2][N], NTT domain, x 2^32 / N mod Q
     const uint32_t *twf, *twi; // Montgomery-form twiddles
     const uint32_t *tv;        // test-vector arena
