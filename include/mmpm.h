@@ -114,6 +114,20 @@ int mm_table_create(mm_ctx *ctx, uint32_t t, uint32_t t_out, uint32_t r, uint32_
                     const uint32_t *f, int *id);
 int mm_table_info(const mm_ctx *ctx, int id, uint32_t *t, uint32_t *t_out, uint32_t *r,
                   uint32_t *q_in);
+
+/* Register an arbitrary (not nega-cyclic) f: Z_t -> Z_t', t entries in [0, t'),
+ * evaluated by two bootstraps (Sec. 4, functional bootstrapping of a general
+ * f): ciphertexts for this table encrypt x = m + b t in Z_2t (plaintext modulus
+ * 2t, m in [0, t), b an unknown top bit) at modulus q_in (0 selects 2Nr);
+ * requires t even, 2t | 2Nr.  The first bootstrap evaluates the nega-cyclic
+ * g(x) = t/2 for x in [0, t), -t/2 for x in [t, 2t); ct + ct_g - (0, (t/2)
+ * floor(q_in / 2t)) then encrypts m; the second evaluates the nega-cyclic
+ * extension F(y) = f(y), F(y + t) = -f(y).  The output encrypts f(m) with
+ * plaintext modulus t'.  A single mm_bootstrap call takes either only such
+ * tables or none of them (MM_EINVAL otherwise); mm_table_info reports t and the
+ * vector length r. */
+int mm_table_create_general(mm_ctx *ctx, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in,
+                            const uint32_t *f, int *id);
 /* The scaled test vector of table id as [r][N]. */
 int mm_table_export(const mm_ctx *ctx, int id, uint32_t *V, size_t words);
 

@@ -15,6 +15,7 @@ __all__ = [
     "test_vector", "gadget_shift", "gadget", "decompose", "keygen_bsk", "keygen_ksk",
     "encrypt", "decrypt", "lwe_phase", "external_product", "blind_rotate", "sample_extract",
     "keyswitch", "bootstrap", "bootstrap_many", "KeySet", "bsk_bytes", "ksk_bytes",
+    "general_tables", "bootstrap_general",
 ]
 
 _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
@@ -52,6 +53,9 @@ def lib():
             "orc_bootstrap": (None, [_u32] * 8 + [_u32p, _u32p, _u32p, _u32, _u32, _u32p, _u32p,
                                                  C.c_void_p, C.c_void_p, C.c_void_p]),
             "orc_bootstrap_many": (None, [_u32] * 8 + [_u32p, _u32p, _u32p, _u32, _u32, _u32p, _u64, _u32p]),
+            "orc_general_tables": (None, [_u32, _u32, _u32p, _u32p, _u32p]),
+            "orc_bootstrap_general": (None, [_u32] * 8 + [_u32p, _u32p, _u32p, _u32p, _u32, _u32, _u32,
+                                                         _u32p, _u32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -217,6 +221,21 @@ def bootstrap_many(p, r: int, bsk, ksk, V, q_in: int, q_out: int, cts) -> np.nda
     out = np.empty_like(cts)
     lib().orc_bootstrap_many(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _u(bsk),
                              _u(ksk), _u(V), q_in, q_out, cts, cts.shape[0], out)
+    return out
+
+
+def general_tables(t: int, t_out: int, f):
+    """(g, F): the two nega-cyclic tables on Z_2t for an arbitrary f: Z_t -> Z_t'."""
+    g = np.empty(2 * t, dtype=np.uint32)
+    F = np.empty(2 * t, dtype=np.uint32)
+    lib().orc_general_tables(t, t_out, _u(f), g, F)
+    return g, F
+
+
+def bootstrap_general(p, r: int, bsk, ksk, Vg, VF, q: int, t: int, q_out: int, ct) -> np.ndarray:
+    out = np.empty(p.n + 1, dtype=np.uint32)
+    lib().orc_bootstrap_general(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _u(bsk), _u(ksk),
+                                _u(Vg), _u(VF), q, t, q_out, _u(ct), out)
     return out
 
 

@@ -538,3 +538,40 @@ void orc_bootstrap_many(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint
         bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, V, q_in, q_out,
                       ct + (size_t)c * (n + 1), out + (size_t)c * (n + 1), NULL, NULL, NULL, 0);
 }
+
+/* ----------------------------------------------------------------------- */
+/* A function that is not nega-cyclic: two bootstraps (Sec. 4, end)       */
+/* ----------------------------------------------------------------------- */
+
+/* For f: Z_t -> Z_t' arbitrary, the ciphertext carries x = m + b t in Z_2t,
+ * m in [0, t), b an unknown top bit.  The two nega-cyclic tables on Z_2t:
+ *   g(x) = t/2 for x in [0, t), -t/2 for x in [t, 2t)   (the sign of x, times t/2)
+ *   F(y) = f(y) for y in [0, t), -f(y - t) for y in [t, 2t)   (mod t').
+ * Outputs g[2t] in Z_2t and F[2t] in Z_t'. */
+void orc_general_tables(uint32_t t, uint32_t t_out, const uint32_t *f, uint32_t *g, uint32_t *F)
+{
+    for (uint32_t x = 0; x < 2 * t; x++) {
+        g[x] = x < t ? t / 2 : 2 * t - t / 2;
+        F[x] = x < t ? f[x] % t_out : (t_out - f[x - t] % t_out) % t_out;
+    }
+}
+
+/* f(m) from Enc_{2t}(m + b t) at modulus q: bootstrap with g (output at q,
+ * plaintext modulus 2t), ct' = ct + ct_g - (0, (t/2) floor(q/2t)) so that
+ * ct' encrypts x - b t = m, then bootstrap ct' with F (output at q_out). */
+void orc_bootstrap_general(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
+                           uint32_t log2Bks, uint32_t lks, uint32_t r, const uint32_t *bsk,
+                           const uint32_t *ksk, const uint32_t *Vg, const uint32_t *VF, uint32_t q,
+                           uint32_t t, uint32_t q_out, const uint32_t *ct, uint32_t *out)
+{
+    uint32_t *ctg = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    uint32_t *ct2 = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, Vg, q, q, ct, ctg, NULL, NULL, NULL, 1);
+    const uint64_t shift = (uint64_t)(t / 2) * (q / (2 * t)) % q;
+    for (uint32_t k = 0; k <= n; k++) ct2[k] = (uint32_t)(((uint64_t)ct[k] + ctg[k]) % q);
+    ct2[n] = (uint32_t)(((uint64_t)ct2[n] + q - shift) % q);
+    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, VF, q, q_out, ct2, out, NULL, NULL,
+                  NULL, 1);
+    free(ctg);
+    free(ct2);
+}

@@ -21,7 +21,7 @@ MM_PLAIN = 2
 
 SYMBOLS = [
     "mm_keygen", "mm_free", "mm_last_error", "mm_get_params", "mm_export_bsk", "mm_export_ksk",
-    "mm_device_init", "mm_table_create", "mm_table_info", "mm_table_export", "mm_encrypt", "mm_decrypt",
+    "mm_device_init", "mm_table_create", "mm_table_create_general", "mm_table_info", "mm_table_export", "mm_encrypt", "mm_decrypt",
     "mm_bootstrap", "mm_modswitch", "mm_blind_rotate", "mm_external_product", "mm_sample_extract",
     "mm_keyswitch", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune",
     "mm_schedule_count", "mm_set_schedule", "mm_server_start", "mm_submit", "mm_poll",
@@ -58,6 +58,7 @@ def _load():
         "mm_export_ksk": (i32, [vp, vp, sz]),
         "mm_device_init": (i32, [vp, i32]),
         "mm_table_create": (i32, [vp, u32, u32, u32, u32, vp, C.POINTER(i32)]),
+        "mm_table_create_general": (i32, [vp, u32, u32, u32, u32, vp, C.POINTER(i32)]),
         "mm_table_info": (i32, [vp, i32, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]),
         "mm_table_export": (i32, [vp, i32, vp, sz]),
         "mm_encrypt": (i32, [vp, u32, u32, vp, sz, vp, vp, vp]),
@@ -175,6 +176,13 @@ class Context:
         f = _u32(f)
         tid = C.c_int()
         self._check(lib.mm_table_create(self.h, t, t_out, r, q_in, f.ctypes.data_as(C.c_void_p), C.byref(tid)))
+        return tid.value
+
+    def table_create_general(self, t, t_out, r, f, q_in=0) -> int:
+        f = _u32(f)
+        tid = C.c_int()
+        self._check(lib.mm_table_create_general(self.h, t, t_out, r, q_in, f.ctypes.data_as(C.c_void_p),
+                                                C.byref(tid)))
         return tid.value
 
     def table_info(self, tid):

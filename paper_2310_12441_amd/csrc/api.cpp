@@ -96,6 +96,14 @@ int mm_table_create(mm_ctx *ctx, uint32_t t, uint32_t t_out, uint32_t r, uint32_
     return guard(ctx, [&] { *id = mm::table_create(*ctx, t, t_out, r, q_in, f); });
 }
 
+int mm_table_create_general(mm_ctx *ctx, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in, const uint32_t *f,
+                            int *id)
+{
+    if (!ctx || !f || !id) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->lock);
+    return guard(ctx, [&] { *id = mm::table_create_general(*ctx, t, t_out, r, q_in, f); });
+}
+
 int mm_table_info(const mm_ctx *ctx, int id, uint32_t *t, uint32_t *t_out, uint32_t *r, uint32_t *q_in)
 {
     if (!ctx || id < 0 || (size_t)id >= ctx->tables.size()) return MM_EINVAL;
@@ -111,7 +119,7 @@ int mm_table_export(const mm_ctx *ctx, int id, uint32_t *V, size_t words)
 {
     if (!ctx || !V || id < 0 || (size_t)id >= ctx->tables.size()) return MM_EINVAL;
     const mm::Table &tb = ctx->tables[id];
-    if (words < tb.V.size()) return MM_EINVAL;
+    if (tb.V.empty() || words < tb.V.size()) return MM_EINVAL;
     std::memcpy(V, tb.V.data(), tb.V.size() * 4);
     return MM_OK;
 }

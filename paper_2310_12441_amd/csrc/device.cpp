@@ -224,11 +224,16 @@ static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, s
     return pack_tasks(cts, gw);
 }
 
-static void check_ids(const mm_ctx &c, const int *ids, size_t count)
+// Valid ids; returns how many name general (two-bootstrap) tables.
+static size_t check_ids(const mm_ctx &c, const int *ids, size_t count)
 {
     MM_REQUIRE(ids || count == 0, "null table ids");
-    for (size_t i = 0; i < count; i++)
+    size_t general = 0;
+    for (size_t i = 0; i < count; i++) {
         MM_REQUIRE(ids[i] >= 0 && (size_t)ids[i] < c.tables.size(), "table id out of range");
+        general += c.tables[ids[i]].g_id >= 0;
+    }
+    return general;
 }
 
 static dev::WaveTask *upload_tasks(Device &d, const std::vector<dev::WaveTask> &tasks, hipStream_t st)
@@ -457,7 +462,8 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
 void run_bootstrap(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count, uint32_t *ct_out, uint32_t q_out,
                    uint32_t flags, void *stream)
 {
-    check_ids(c, ids, count);
+    const size_t general = check_ids(c, ids, count);
+    MM_REQUIRE(general == 0 || general == count, "a call takes only general tables or none of them");
     MM_REQUIRE(q_out == 0 || q_out == c.p.Q || (q_out >= 2 && q_out < c.p.Q), "q_out must be 0, Q or in [2, Q)");
     if (count == 0) return;
     Device &d = ensure_device(c);
@@ -466,19 +472,43 @@ void run_bootstrap(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t coun
     const size_t W = c.p.n + 1;
     const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * W, dptr, st);
     uint32_t *d_out = stage_out(d, WS_OUT, ct_out, count * W, dptr);
-    if (flags & MM_PLAIN) {
-        for (size_t i = 0; i < count; i++)
-            bootstrap_batch(c, d, ids + i, d_in + i * W, 1, d_out + i * W, q_out, false, st);
+    auto pass = [&](const int *pid, const uint32_t *in, uint32_t *out, uint32_t qo) {
+        if (flags & MM_PLAIN) {
+            for (size_t i = 0; i < count; i++) bootstrap_batch(c, d, pid + i, in + i * W, 1, out + i * W, qo, false, st);
+        } else {
+            bootstrap_batch(c, d, pid, in, count, out, qo, true, st);
+        }
+    };
+    if (general == 0) {
+        pass(ids, d_in, d_out, q_out);
     } else {
-        bootstrap_batch(c, d, ids, d_in, count, d_out, q_out, true, st);
+        // general f: sign bootstrap, top-bit removal, then the extended f
+        std::vector<int> g_ids(count), f_ids(count);
+        uint32_t *hq = (uint32_t *)pinned(d, 1, count * 8);
+        for (size_t i = 0; i < count; i++) {
+            const Table &tb = c.tables[ids[i]];
+            g_ids[i] = tb.g_id;
+            f_ids[i] = tb.F_id;
+            hq[2 * i] = tb.q_in;
+            hq[2 * i + 1] = (uint32_t)((uint64_t)(tb.t / 2) * (tb.q_in / (2 * tb.t)) % tb.q_in);
+        }
+        uint32_t *dq = (uint32_t *)ws(d, WS_GENQ, count * 8);
+        uint32_t *tmp = (uint32_t *)ws(d, WS_GEN1, count * W * 4);
+        uint32_t *comb = (uint32_t *)ws(d, WS_GEN2, count * W * 4);
+        HIPC(hipMemcpyAsync(dq, hq, count * 8, hipMemcpyHostToDevice, st));
+        HIPC(hipEventRecord(d.pin[1].ev, st));
+        pass(g_ids.data(), d_in, tmp, 0);
+        dev::launch_lwe_combine(d_in, tmp, comb, count, (uint32_t)W, dq, st);
+        pass(f_ids.data(), comb, d_out, q_out);
     }
+    HIPC(hipGetLastError());
     finish_out(ct_out, d_out, count * W, dptr, st);
 }
 
 void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count, uint32_t steps,
                       uint32_t *acc_out, uint32_t flags, void *stream)
 {
-    check_ids(c, ids, count);
+    MM_REQUIRE(check_ids(c, ids, count) == 0, "blind rotation takes nega-cyclic tables");
     MM_REQUIRE(steps <= c.p.n, "steps must be <= n");
     if (count == 0) return;
     Device &d = ensure_device(c);
@@ -606,7 +636,7 @@ void last_timing(mm_ctx &c, float *br_ms, float *ks_ms)
 
 int schedule_count(mm_ctx &c, const int *ids, size_t count)
 {
-    check_ids(c, ids, count);
+    MM_REQUIRE(check_ids(c, ids, count) == 0, "schedules are per nega-cyclic table batch");
     MM_REQUIRE(count > 0, "empty batch");
     Device &d = ensure_device(c);
     return (int)candidates(c, d, ids, count).size();
@@ -624,7 +654,7 @@ void set_schedule(mm_ctx &c, const int *ids, size_t count, int choice)
 // fastest combination for the batch shape.
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
 {
-    check_ids(c, ids, count);
+    MM_REQUIRE(check_ids(c, ids, count) == 0, "autotuning takes nega-cyclic tables");
     MM_REQUIRE(count > 0, "empty batch");
     Device &d = ensure_device(c);
     const size_t W = c.p.n + 1;

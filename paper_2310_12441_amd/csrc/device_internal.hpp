@@ -20,7 +20,7 @@ namespace mm {
             throw ::mm::Error(MM_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
     } while (0)
 
-enum WsSlot { WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_COUNT };
+enum WsSlot { WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_GEN1, WS_GEN2, WS_GENQ, WS_COUNT };
 
 struct DevBuf {
     void *p = nullptr;

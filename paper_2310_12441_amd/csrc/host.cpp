@@ -263,4 +263,23 @@ int table_create(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_i
     return (int)c.tables.size() - 1;
 }
 
+// Two nega-cyclic tables on Z_2t carry an arbitrary f: the sign table g and
+// the nega-cyclic extension F of f (Sec. 4, general f).
+int table_create_general(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in, const uint32_t *f)
+{
+    MM_REQUIRE(t >= 2 && t % 2 == 0, "t must be even");
+    MM_REQUIRE(t_out >= 2 && t_out % 2 == 0, "t' must be even");
+    for (uint32_t m = 0; m < t; m++) MM_REQUIRE(f[m] < t_out, "table entry out of range");
+    std::vector<uint32_t> g(2 * t), F(2 * t);
+    for (uint32_t x = 0; x < 2 * t; x++) {
+        g[x] = x < t ? t / 2 : 2 * t - t / 2;
+        F[x] = x < t ? f[x] : (t_out - f[x - t]) % t_out;
+    }
+    const int gid = table_create(c, 2 * t, 2 * t, r, q_in, g.data());
+    const int fid = table_create(c, 2 * t, t_out, r, q_in, F.data());
+    Table tb{t, t_out, r, c.tables[gid].q_in, {}, 0, gid, fid};
+    c.tables.push_back(std::move(tb));
+    return (int)c.tables.size() - 1;
+}
+
 }  // namespace mm

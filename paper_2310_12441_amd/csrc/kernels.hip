@@ -405,6 +405,30 @@ void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows
     hipLaunchKernelGGL(k_scatter_rows, dim3(std::max(grid, 1)), dim3(256), 0, st, src, dst, rows, count, W);
 }
 
+// out = ct + tmp - (0, shift) mod q, per ciphertext (q, shift) = qs[2c], qs[2c+1]:
+// removes the top bit found by the sign bootstrap of a general f.
+__global__ void k_lwe_combine(const uint32_t *__restrict__ ct, const uint32_t *__restrict__ tmp,
+                              uint32_t *__restrict__ out, size_t count, uint32_t W, const uint32_t *__restrict__ qs)
+{
+    const size_t total = count * W;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = t / W;
+        const uint32_t k = (uint32_t)(t - c * W);
+        const uint64_t q = qs[2 * c];
+        uint64_t v = ((uint64_t)ct[t] + tmp[t]) % q;
+        if (k == W - 1) v = (v + q - qs[2 * c + 1] % q) % q;
+        out[t] = (uint32_t)v;
+    }
+}
+
+void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, size_t count, uint32_t W,
+                        const uint32_t *qs, hipStream_t st)
+{
+    const size_t total = count * W;
+    const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_lwe_combine, dim3(std::max(grid, 1)), dim3(256), 0, st, ct, tmp, out, count, W, qs);
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int N, int GW>

@@ -56,6 +56,8 @@ struct KsArgs {
 };
 
 hipError_t init_kernel_attributes();
+void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, size_t count, uint32_t W,
+                        const uint32_t *qs, hipStream_t st);
 void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,
                          hipStream_t st);
 void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st);

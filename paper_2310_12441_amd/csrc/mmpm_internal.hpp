@@ -49,8 +49,9 @@ struct NttTables {
 
 struct Table {
     uint32_t t, t_out, r, q_in;
-    std::vector<uint32_t> V;  // [r][N] scaled test vector
+    std::vector<uint32_t> V;  // [r][N] scaled test vector (empty for a general table)
     size_t dev_offset = 0;    // word offset in the device test-vector arena
+    int g_id = -1, F_id = -1; // general f: the sign table and the extended-f table it runs
 };
 
 struct Device;  // device-side state, defined in device.cpp
@@ -85,6 +86,7 @@ void encrypt(const mm_ctx &c, uint32_t q, uint32_t t, const uint32_t *m, size_t 
              const uint32_t *mask, const int32_t *err, uint32_t *ct);
 void decrypt(const mm_ctx &c, uint32_t q, uint32_t t, const uint32_t *ct, size_t count, uint32_t *m);
 int table_create(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in, const uint32_t *f);
+int table_create_general(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in, const uint32_t *f);
 
 // device entry points (device.hip)
 void device_init(mm_ctx &c, int device);

@@ -231,8 +231,8 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
 {
     const size_t W = c->p.n + 1;
     std::lock_guard<std::mutex> g(mu);
-    if (table < 0 || (size_t)table >= c->tables.size()) {
-        *rc = MM_EINVAL;
+    if (table < 0 || (size_t)table >= c->tables.size() || c->tables[table].g_id >= 0) {
+        *rc = MM_EINVAL;  // unknown table, or a general table (two bootstraps; not served)
         return 0;
     }
     if (pending.size() >= pending_cap || stop) {

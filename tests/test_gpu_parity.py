@@ -319,3 +319,41 @@ def test_every_schedule_gives_the_same_bits(paper):
     choice = paper.ctx.autotune(ids, cts)
     assert 0 <= choice < n
     np.testing.assert_array_equal(paper.ctx.bootstrap(ids, cts), ref)
+
+
+@pytest.mark.parametrize("identity,plain", [(False, False), (True, False), (False, True)])
+def test_general_function_tiny(tiny, identity, plain):
+    """An arbitrary f (or the identity) by two bootstraps: every m with both values of the top bit."""
+    say("general f tiny identity", identity, "plain", plain)
+    t, t_out, r = 8, 16, 2
+    rng = np.random.default_rng(41)
+    f = (np.arange(t) % t_out if identity else rng.integers(0, t_out, t)).astype(np.uint32)
+    tid = tiny.ctx.table_create_general(t, t_out, r, f)
+    g, F = oracle.general_tables(t, t_out, f)
+    Vg = oracle.test_vector(tiny.p.N, r, Q, 2 * t, 2 * t, g)
+    VF = oracle.test_vector(tiny.p.N, r, Q, 2 * t, t_out, F)
+    q = 2 * tiny.p.N * r
+    m = np.repeat(np.arange(t, dtype=np.uint32), 2)
+    b = np.tile(np.array([0, 1], dtype=np.uint32), t)
+    ct = tiny.encrypt(q, 2 * t, m + b * t, 77)
+    got = tiny.ctx.bootstrap([tid] * m.size, ct, plain=plain)
+    for c in range(m.size):
+        want = oracle.bootstrap_general(tiny.p, r, tiny.keys.bsk, tiny.keys.ksk, Vg, VF, q, t, q, ct[c])
+        np.testing.assert_array_equal(got[c], want, err_msg=f"ct {c}")
+    np.testing.assert_array_equal(oracle.decrypt(tiny.p.n, q, t_out, tiny.keys.s, got), f[m])
+
+
+def test_general_function_paper(paper):
+    t, r = 2048, 4
+    rng = np.random.default_rng(42)
+    f = rng.integers(0, t, t).astype(np.uint32)
+    tid = paper.ctx.table_create_general(t, t, r, f)
+    g, F = oracle.general_tables(t, t, f)
+    Vg = oracle.test_vector(paper.p.N, r, Q, 2 * t, 2 * t, g)
+    VF = oracle.test_vector(paper.p.N, r, Q, 2 * t, t, F)
+    q = 2 * paper.p.N * r
+    ct = paper.encrypt(q, 2 * t, np.array([5, 2047 + 2048], np.uint32), 79)
+    got = paper.ctx.bootstrap([tid] * 2, ct)
+    for c in range(2):
+        want = oracle.bootstrap_general(paper.p, r, paper.keys.bsk, paper.keys.ksk, Vg, VF, q, t, q, ct[c])
+        np.testing.assert_array_equal(got[c], want)

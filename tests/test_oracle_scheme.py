@@ -209,3 +209,41 @@ def test_modswitch_is_nearest_integer(q_from, q_to):
         hi = exact + Fraction(1, 2)
         k = hi.numerator // hi.denominator  # floor(exact + 1/2): nearest integer, ties upward
         assert o == k % q_to, (x, o, exact)
+
+
+def _general_case(seed, t=8, t_out=16, identity=False):
+    from synth import Params
+    p = Params(n=64, N=256, log2_B=8, l=3)
+    r = 2
+    keys = oracle.KeySet(p, key_draws(p, seed))
+    rng = np.random.default_rng(seed)
+    f = np.arange(t, dtype=np.uint32) % t_out if identity else rng.integers(0, t_out, t).astype(np.uint32)
+    g, F = oracle.general_tables(t, t_out, f)
+    Vg = oracle.test_vector(p.N, r, Q, 2 * t, 2 * t, g)
+    VF = oracle.test_vector(p.N, r, Q, 2 * t, t_out, F)
+    q = 2 * p.N * r
+    m = np.repeat(np.arange(t, dtype=np.uint32), 2)
+    b = np.tile(np.array([0, 1], dtype=np.uint32), t)  # unknown top bit of the Z_2t plaintext
+    ed = enc_draws(p.n, q, m.size, seed + 7)
+    ct = oracle.encrypt(p.n, q, 2 * t, keys.s, m + b * t, ed["a"], ed["e"])
+    return p, r, keys, f, Vg, VF, q, t, t_out, m, ct
+
+
+def test_general_tables_are_negacyclic():
+    f = np.array([3, 0, 7, 7, 1, 5, 2, 6], dtype=np.uint32)
+    g, F = oracle.general_tables(8, 8, f)
+    np.testing.assert_array_equal(F[:8], f)
+    assert all((int(F[x]) + int(F[x + 8])) % 8 == 0 for x in range(8))
+    assert all((int(g[x]) + int(g[x + 8])) % 16 == 0 for x in range(8))
+    assert set(g[:8].tolist()) == {4}
+
+
+@pytest.mark.parametrize("seed,identity", [(0, False), (1, False), (2, True)])
+def test_general_function_two_bootstraps(seed, identity):
+    """A function that is not nega-cyclic, on Z_2t inputs with an unknown top
+    bit: MSB removal by a sign bootstrap, then the nega-cyclic extension of f
+    (Sec. 4, end; identity f is the workload of Tables 1-2)."""
+    p, r, keys, f, Vg, VF, q, t, t_out, m, ct = _general_case(seed, identity=identity)
+    for c in range(ct.shape[0]):
+        out = oracle.bootstrap_general(p, r, keys.bsk, keys.ksk, Vg, VF, q, t, q, ct[c])
+        assert oracle.decrypt(p.n, q, t_out, keys.s, out)[0] == f[m[c]], (c, m[c])
