@@ -41,20 +41,20 @@ def lib():
             "orc_gadget_shift": (_u32, [_u32, _u32, _u32]),
             "orc_gadget": (_u32, [_u32, _u32, _u32, _u32]),
             "orc_decompose": (None, [_u32, _u32, _u32, _u32, _i32p]),
-            "orc_keygen_bsk": (None, [_u32, _u32, _u32, _u32, _u32, _u32p, _u32p, _u32p, _i32p, _u32p]),
-            "orc_keygen_ksk": (None, [_u32, _u32, _u32, _u32, _u32, _u32p, _u32p, _u32p, _i32p, _u32p]),
-            "orc_encrypt": (None, [_u32, _u32, _u32, _u32p, _u32p, _u32p, _i32p, _u64, _u32p]),
-            "orc_decrypt": (None, [_u32, _u32, _u32, _u32p, _u32p, _u64, _u32p]),
-            "orc_lwe_phase": (None, [_u32, _u32, _u32p, _u32p, _u64, _u32p]),
+            "orc_keygen_bsk": (None, [_u32, _u32, _u32, _u32, _u32, _u32, _i32p, _u32p, _u32p, _i32p, _u32p]),
+            "orc_keygen_ksk": (None, [_u32, _u32, _u32, _u32, _u32, _i32p, _u32p, _u32p, _i32p, _u32p]),
+            "orc_encrypt": (None, [_u32, _u32, _u32, _i32p, _u32p, _u32p, _i32p, _u64, _u32p]),
+            "orc_decrypt": (None, [_u32, _u32, _u32, _i32p, _u32p, _u64, _u32p]),
+            "orc_lwe_phase": (None, [_u32, _u32, _i32p, _u32p, _u64, _u32p]),
             "orc_external_product": (None, [_u32, _u32, _u32, _u32, _u32p, _u32p, _u32p]),
-            "orc_blind_rotate": (None, [_u32, _u32, _u32, _u32, _u32, _u32, _u32p, _u32p, _u32p, _u32, _u32p]),
+            "orc_blind_rotate": (None, [_u32] * 7 + [_u32p, _u32p, _u32p, _u32, _u32p]),
             "orc_sample_extract": (None, [_u32, _u32, _u32p, _u32p]),
             "orc_keyswitch": (None, [_u32, _u32, _u32, _u32, _u32, _u32p, _u32p, _u32p]),
-            "orc_bootstrap": (None, [_u32] * 8 + [_u32p, _u32p, _u32p, _u32, _u32, _u32p, _u32p,
+            "orc_bootstrap": (None, [_u32] * 9 + [_u32p, _u32p, _u32p, _u32, _u32, _u32p, _u32p,
                                                  C.c_void_p, C.c_void_p, C.c_void_p]),
-            "orc_bootstrap_many": (None, [_u32] * 8 + [_u32p, _u32p, _u32p, _u32, _u32, _u32p, _u64, _u32p]),
+            "orc_bootstrap_many": (None, [_u32] * 9 + [_u32p, _u32p, _u32p, _u32, _u32, _u32p, _u64, _u32p]),
             "orc_general_tables": (None, [_u32, _u32, _u32p, _u32p, _u32p]),
-            "orc_bootstrap_general": (None, [_u32] * 8 + [_u32p, _u32p, _u32p, _u32p, _u32, _u32, _u32,
+            "orc_bootstrap_general": (None, [_u32] * 9 + [_u32p, _u32p, _u32p, _u32p, _u32, _u32, _u32,
                                                          _u32p, _u32p]),
         }
         for name, (res, args) in sig.items():
@@ -138,16 +138,22 @@ def decompose(x: int, Q: int, log2_B: int, l: int) -> np.ndarray:
     return d
 
 
+def _keys(p) -> int:
+    return 2 if getattr(p, "ternary", False) else 1
+
+
 def keygen_bsk(p, draws) -> np.ndarray:
-    out = np.empty((p.n, 2 * p.l, 2, p.N), dtype=np.uint32)
-    lib().orc_keygen_bsk(p.n, p.N, p.Q, p.log2_B, p.l, _u(draws["s"]), _u(draws["z"]),
+    """[n * K][2l][2][N]: key k of coordinate i at i K + k (K = 2 for a ternary secret)."""
+    K = _keys(p)
+    out = np.empty((p.n * K, 2 * p.l, 2, p.N), dtype=np.uint32)
+    lib().orc_keygen_bsk(p.n, p.N, p.Q, p.log2_B, p.l, K, _i(draws["s"]), _u(draws["z"]),
                          _u(draws["bsk_a"]), _i(draws["bsk_e"]), out)
     return out
 
 
 def keygen_ksk(p, draws) -> np.ndarray:
     out = np.empty((p.N, p.l_ks, p.B_ks, p.n + 1), dtype=np.uint32)
-    lib().orc_keygen_ksk(p.n, p.N, p.Q, p.log2_Bks, p.l_ks, _u(draws["s"]), _u(draws["z"]),
+    lib().orc_keygen_ksk(p.n, p.N, p.Q, p.log2_Bks, p.l_ks, _i(draws["s"]), _u(draws["z"]),
                          _u(draws["ksk_a"]), _i(draws["ksk_e"]), out)
     return out
 
@@ -155,21 +161,21 @@ def keygen_ksk(p, draws) -> np.ndarray:
 def encrypt(n: int, q: int, t: int, s, m, a, e) -> np.ndarray:
     m = _u(np.atleast_1d(m))
     ct = np.empty((m.size, n + 1), dtype=np.uint32)
-    lib().orc_encrypt(n, q, t, _u(s), m, _u(a), _i(e), m.size, ct)
+    lib().orc_encrypt(n, q, t, _i(s), m, _u(a), _i(e), m.size, ct)
     return ct
 
 
 def decrypt(n: int, q: int, t: int, s, ct) -> np.ndarray:
     ct = _u(ct).reshape(-1, n + 1)
     m = np.empty(ct.shape[0], dtype=np.uint32)
-    lib().orc_decrypt(n, q, t, _u(s), ct, ct.shape[0], m)
+    lib().orc_decrypt(n, q, t, _i(s), ct, ct.shape[0], m)
     return m
 
 
 def lwe_phase(n: int, q: int, s, ct) -> np.ndarray:
     ct = _u(ct).reshape(-1, n + 1)
     ph = np.empty(ct.shape[0], dtype=np.uint32)
-    lib().orc_lwe_phase(n, q, _u(s), ct, ct.shape[0], ph)
+    lib().orc_lwe_phase(n, q, _i(s), ct, ct.shape[0], ph)
     return ph
 
 
@@ -185,7 +191,7 @@ def external_product(rgsw, rlwe, Q: int, log2_B: int, l: int) -> np.ndarray:
 def blind_rotate(p, r: int, bsk, V, ct_ms, steps=None) -> np.ndarray:
     acc = np.empty((r, 2, p.N), dtype=np.uint32)
     steps = p.n if steps is None else steps
-    lib().orc_blind_rotate(p.n, p.N, p.Q, p.log2_B, p.l, r, _u(bsk), _u(V), _u(ct_ms), steps, acc)
+    lib().orc_blind_rotate(p.n, p.N, p.Q, p.log2_B, p.l, r, _keys(p), _u(bsk), _u(V), _u(ct_ms), steps, acc)
     return acc
 
 
@@ -209,7 +215,7 @@ def bootstrap(p, r: int, bsk, ksk, V, q_in: int, q_out: int, ct, intermediates=F
     acc = np.empty((r, 2, p.N), dtype=np.uint32) if intermediates else None
     ext = np.empty(p.N + 1, dtype=np.uint32) if intermediates else None
     ks = np.empty(p.n + 1, dtype=np.uint32) if intermediates else None
-    lib().orc_bootstrap(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _u(bsk), _u(ksk),
+    lib().orc_bootstrap(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _keys(p), _u(bsk), _u(ksk),
                         _u(V), q_in, q_out, ct, out, _ptr(acc), _ptr(ext), _ptr(ks))
     if intermediates:
         return out, acc, ext, ks
@@ -219,7 +225,7 @@ def bootstrap(p, r: int, bsk, ksk, V, q_in: int, q_out: int, ct, intermediates=F
 def bootstrap_many(p, r: int, bsk, ksk, V, q_in: int, q_out: int, cts) -> np.ndarray:
     cts = _u(cts).reshape(-1, p.n + 1)
     out = np.empty_like(cts)
-    lib().orc_bootstrap_many(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _u(bsk),
+    lib().orc_bootstrap_many(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _keys(p), _u(bsk),
                              _u(ksk), _u(V), q_in, q_out, cts, cts.shape[0], out)
     return out
 
@@ -234,7 +240,7 @@ def general_tables(t: int, t_out: int, f):
 
 def bootstrap_general(p, r: int, bsk, ksk, Vg, VF, q: int, t: int, q_out: int, ct) -> np.ndarray:
     out = np.empty(p.n + 1, dtype=np.uint32)
-    lib().orc_bootstrap_general(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _u(bsk), _u(ksk),
+    lib().orc_bootstrap_general(p.n, p.N, p.Q, p.log2_B, p.l, p.log2_Bks, p.l_ks, r, _keys(p), _u(bsk), _u(ksk),
                                 _u(Vg), _u(VF), q, t, q_out, _u(ct), out)
     return out
 
@@ -244,7 +250,7 @@ class KeySet:
 
     def __init__(self, p, draws):
         self.p = p
-        self.s = _u(draws["s"])
+        self.s = _i(draws["s"])
         self.z = _u(draws["z"])
         self.bsk = keygen_bsk(p, draws)
         self.ksk = keygen_ksk(p, draws)

@@ -3,8 +3,8 @@
  *
  * A plain, slow CPU statement of the BootMMPM functional bootstrap
  * (Algorithm 1 of "Large-Plaintext Functional Bootstrapping in FHE with Small
- * Bootstrapping Keys", arXiv 2310.12441) for a binary LWE secret s and a
- * binary ring secret z.  It exists so that tests, the smoke check and the
+ * Bootstrapping Keys", arXiv 2310.12441) for a binary or ternary LWE secret s
+ * and a binary ring secret z.  It exists so that tests, the smoke check and the
  * benchmark's CPU baseline can check the HIP library against something that a
  * reader can compare with the paper line by line.  No product code may call
  * it, and it shares no code, header or table with the HIP library.
@@ -273,25 +273,31 @@ static void rgsw_encrypt(uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l, uin
     free(acc);
 }
 
-/* Bootstrapping keys BSK_i = RGSW_z(s_i), i < n.  bsk[i][row][part][N]. */
-void orc_keygen_bsk(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
-                    const uint32_t *s, const uint32_t *z, const uint32_t *bsk_a,
-                    const int32_t *bsk_e, uint32_t *bsk)
+/* Bootstrapping keys (Alg. 1 inputs).  keys = 1 (binary s): BSK_i = RGSW_z(s_i).
+ * keys = 2 (ternary s): BSK_{i,0} = RGSW_z(s_i+), BSK_{i,1} = RGSW_z(s_i-),
+ * s+ = max(s, 0), s- = max(-s, 0) (eq. d:pm).  bsk[i][key][row][part][N];
+ * masks and errors bsk_a/bsk_e are [i][key][row][N]. */
+void orc_keygen_bsk(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l, uint32_t keys,
+                    const int32_t *s, const uint32_t *z, const uint32_t *bsk_a, const int32_t *bsk_e,
+                    uint32_t *bsk)
 {
     int32_t *zi = (int32_t *)malloc(sizeof(int32_t) * N);
     for (uint32_t k = 0; k < N; k++) zi[k] = (int32_t)z[k];
     const size_t per = (size_t)2 * l * N;
 #pragma omp parallel for schedule(dynamic)
-    for (int64_t i = 0; i < (int64_t)n; i++)
-        rgsw_encrypt(N, Q, log2B, l, s[i], zi, bsk_a + (size_t)i * per, bsk_e + (size_t)i * per,
-                     bsk + (size_t)i * per * 2);
+    for (int64_t ik = 0; ik < (int64_t)n * keys; ik++) {
+        const int64_t i = ik / keys, key = ik % keys;
+        const uint32_t m = key == 0 ? (s[i] > 0 ? (uint32_t)s[i] : 0u) : (s[i] < 0 ? (uint32_t)(-s[i]) : 0u);
+        rgsw_encrypt(N, Q, log2B, l, m, zi, bsk_a + (size_t)ik * per, bsk_e + (size_t)ik * per,
+                     bsk + (size_t)ik * per * 2);
+    }
     free(zi);
 }
 
 /* Key-switching keys KSK[i][j][v] = LWE_s(v z_i B_ks^j) in Z_Q^(n+1)
  * (Sec. 2 item (11), Alg. 1 inputs), digit value v = 0 included. */
 void orc_keygen_ksk(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2Bks, uint32_t lks,
-                    const uint32_t *s, const uint32_t *z, const uint32_t *ksk_a,
+                    const int32_t *s, const uint32_t *z, const uint32_t *ksk_a,
                     const int32_t *ksk_e, uint32_t *ksk)
 {
     const uint32_t Bks = 1u << log2Bks;
@@ -303,13 +309,13 @@ void orc_keygen_ksk(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2Bks, uint32
                 const size_t row = ((size_t)i * lks + j) * Bks + v;
                 const uint32_t *al = ksk_a + row * n;
                 uint32_t *o = ksk + row * (n + 1);
-                uint64_t dot = 0;
+                int64_t dot = 0;
                 for (uint32_t k = 0; k < n; k++) {
                     o[k] = al[k];
-                    dot = (dot + (uint64_t)al[k] * s[k]) % Q;
+                    dot = (dot + (int64_t)al[k] * s[k]) % (int64_t)Q;
                 }
                 const uint64_t msg = ((uint64_t)v * z[i] % Q) * pw % Q;
-                o[n] = mod_i64((int64_t)dot + ksk_e[row] + (int64_t)msg, Q);
+                o[n] = mod_i64(dot + ksk_e[row] + (int64_t)msg, Q);
             }
             pw = pw * Bks % Q;
         }
@@ -321,45 +327,48 @@ void orc_keygen_ksk(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2Bks, uint32
 /* ----------------------------------------------------------------------- */
 
 /* b = <a, s> + m floor(q/t) + e mod q; ct[i] = (a_0..a_{n-1}, b). */
-void orc_encrypt(uint32_t n, uint32_t q, uint32_t t, const uint32_t *s, const uint32_t *m,
+/* <a, s> mod q for an integer secret */
+static int64_t dot_mod(const uint32_t *a, const int32_t *s, uint32_t n, uint32_t q)
+{
+    int64_t dot = 0;
+    for (uint32_t k = 0; k < n; k++) dot = (dot + (int64_t)a[k] * s[k]) % (int64_t)q;
+    return dot < 0 ? dot + q : dot;
+}
+
+void orc_encrypt(uint32_t n, uint32_t q, uint32_t t, const int32_t *s, const uint32_t *m,
                  const uint32_t *a, const int32_t *e, uint64_t count, uint32_t *ct)
 {
     const uint64_t delta = q / t;
     for (uint64_t c = 0; c < count; c++) {
         const uint32_t *ac = a + c * n;
         uint32_t *o = ct + c * (n + 1);
-        uint64_t dot = 0;
-        for (uint32_t k = 0; k < n; k++) {
-            o[k] = ac[k];
-            dot = (dot + (uint64_t)ac[k] * s[k]) % q;
-        }
-        const int64_t b = (int64_t)dot + (int64_t)((m[c] % t) * delta % q) + e[c];
+        for (uint32_t k = 0; k < n; k++) o[k] = ac[k];
+        const int64_t dot = dot_mod(ac, s, n, q);
+        const int64_t b = dot + (int64_t)((m[c] % t) * delta % q) + e[c];
         o[n] = mod_i64(b, q);
     }
 }
 
 /* phase = b - <a, s> mod q = m floor(q/t) + e; m = round(phase / floor(q/t)) mod t. */
-void orc_decrypt(uint32_t n, uint32_t q, uint32_t t, const uint32_t *s, const uint32_t *ct,
+void orc_decrypt(uint32_t n, uint32_t q, uint32_t t, const int32_t *s, const uint32_t *ct,
                  uint64_t count, uint32_t *m)
 {
     const uint64_t delta = q / t;
     for (uint64_t c = 0; c < count; c++) {
         const uint32_t *o = ct + c * (n + 1);
-        uint64_t dot = 0;
-        for (uint32_t k = 0; k < n; k++) dot = (dot + (uint64_t)o[k] * s[k]) % q;
+        const uint64_t dot = (uint64_t)dot_mod(o, s, n, q);
         const uint64_t ph = ((uint64_t)o[n] + q - dot) % q;
         m[c] = (uint32_t)(((ph + delta / 2) / delta) % t);
     }
 }
 
 /* phase of an LWE ciphertext, for noise measurements */
-void orc_lwe_phase(uint32_t n, uint32_t q, const uint32_t *s, const uint32_t *ct, uint64_t count,
+void orc_lwe_phase(uint32_t n, uint32_t q, const int32_t *s, const uint32_t *ct, uint64_t count,
                    uint32_t *phase)
 {
     for (uint64_t c = 0; c < count; c++) {
         const uint32_t *o = ct + c * (n + 1);
-        uint64_t dot = 0;
-        for (uint32_t k = 0; k < n; k++) dot = (dot + (uint64_t)o[k] * s[k]) % q;
+        const uint64_t dot = (uint64_t)dot_mod(o, s, n, q);
         phase[c] = (uint32_t)(((uint64_t)o[n] + q - dot) % q);
     }
 }
@@ -392,11 +401,12 @@ void orc_external_product(uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
     free(acc);
 }
 
-/* ACC <- Phi(b')(0, V); then for i < steps: ACC <- ACC + (Phi(-a'_i) ACC - ACC) x BSK_i,
- * the CMux of (cmux:BP) with d_- = 0 (binary s).  ct_ms holds (a'_0..a'_{n-1}, b')
- * in Z_{2Nr}.  acc[j][part][N]. */
+/* ACC <- Phi(b')(0, V); then for i < steps the CMux of eq. (cmux:BP):
+ * ACC <- ACC + (Phi(-a'_i) ACC - ACC) x BSK_{i,0} [+ (Phi(a'_i) ACC - ACC) x BSK_{i,1}],
+ * the second term only for a ternary secret (keys = 2), both computed from the
+ * same ACC.  ct_ms holds (a'_0..a'_{n-1}, b') in Z_{2Nr}.  acc[j][part][N]. */
 static void blind_rotate(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
-                         uint32_t r, const uint32_t *bsk, const uint32_t *V,
+                         uint32_t r, uint32_t keys, const uint32_t *bsk, const uint32_t *V,
                          const uint32_t *ct_ms, uint32_t steps, uint32_t *acc, int parallel)
 {
     const uint64_t M = 2ull * N * r;
@@ -404,7 +414,7 @@ static void blind_rotate(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uin
     uint32_t *rv = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)r * N);
     uint32_t *ra = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)r * N);
     uint32_t *rb = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)r * N);
-    uint32_t *D = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)r * comp);
+    uint32_t *D = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)keys * r * comp);
 
     /* ACC <- Phi(b') (0, V) */
     orc_rotate(N, r, Q, ct_ms[n] % M, V, rv);
@@ -414,29 +424,30 @@ static void blind_rotate(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uin
     }
 
     for (uint32_t i = 0; i < steps && i < n; i++) {
-        const uint64_t c = (M - (ct_ms[i] % M)) % M; /* -a'_i mod 2Nr */
-        /* split ACC into its a and b vectors, rotate each by Phi(c) */
-        for (uint32_t j = 0; j < r; j++) {
-            memcpy(rv + (size_t)j * N, acc + j * comp, sizeof(uint32_t) * N);
+        for (uint32_t key = 0; key < keys; key++) {
+            /* key 0: c = -a'_i (the s+ term); key 1: c = +a'_i (the s- term) */
+            const uint64_t a = ct_ms[i] % M;
+            const uint64_t c = key == 0 ? (M - a) % M : a;
+            for (uint32_t j = 0; j < r; j++) memcpy(rv + (size_t)j * N, acc + j * comp, sizeof(uint32_t) * N);
+            orc_rotate(N, r, Q, c, rv, ra);
+            for (uint32_t j = 0; j < r; j++) memcpy(rv + (size_t)j * N, acc + j * comp + N, sizeof(uint32_t) * N);
+            orc_rotate(N, r, Q, c, rv, rb);
+            uint32_t *Dk = D + (size_t)key * r * comp;
+            for (uint32_t j = 0; j < r; j++)
+                for (uint32_t k = 0; k < N; k++) {
+                    Dk[j * comp + k] = (ra[(size_t)j * N + k] + Q - acc[j * comp + k]) % Q;
+                    Dk[j * comp + N + k] = (rb[(size_t)j * N + k] + Q - acc[j * comp + N + k]) % Q;
+                }
         }
-        orc_rotate(N, r, Q, c, rv, ra);
-        for (uint32_t j = 0; j < r; j++) {
-            memcpy(rv + (size_t)j * N, acc + j * comp + N, sizeof(uint32_t) * N);
-        }
-        orc_rotate(N, r, Q, c, rv, rb);
-        /* D = Phi(c) ACC - ACC */
-        for (uint32_t j = 0; j < r; j++)
-            for (uint32_t k = 0; k < N; k++) {
-                D[j * comp + k] = (ra[(size_t)j * N + k] + Q - acc[j * comp + k]) % Q;
-                D[j * comp + N + k] = (rb[(size_t)j * N + k] + Q - acc[j * comp + N + k]) % Q;
-            }
-        const uint32_t *key = bsk + (size_t)i * 2 * l * 2 * N;
 #pragma omp parallel for schedule(static) if (parallel)
         for (int64_t j = 0; j < (int64_t)r; j++) {
             uint32_t *prod = (uint32_t *)malloc(sizeof(uint32_t) * comp);
-            orc_external_product(N, Q, log2B, l, key, D + j * comp, prod);
-            for (uint32_t k = 0; k < 2 * N; k++)
-                acc[j * comp + k] = (uint32_t)(((uint64_t)acc[j * comp + k] + prod[k]) % Q);
+            for (uint32_t key = 0; key < keys; key++) {
+                const uint32_t *rgsw = bsk + ((size_t)i * keys + key) * 2 * l * 2 * N;
+                orc_external_product(N, Q, log2B, l, rgsw, D + (size_t)key * r * comp + j * comp, prod);
+                for (uint32_t k = 0; k < 2 * N; k++)
+                    acc[j * comp + k] = (uint32_t)(((uint64_t)acc[j * comp + k] + prod[k]) % Q);
+            }
             free(prod);
         }
     }
@@ -447,10 +458,10 @@ static void blind_rotate(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uin
 }
 
 void orc_blind_rotate(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l, uint32_t r,
-                      const uint32_t *bsk, const uint32_t *V, const uint32_t *ct_ms,
+                      uint32_t keys, const uint32_t *bsk, const uint32_t *V, const uint32_t *ct_ms,
                       uint32_t steps, uint32_t *acc)
 {
-    blind_rotate(n, N, Q, log2B, l, r, bsk, V, ct_ms, steps, acc, 1);
+    blind_rotate(n, N, Q, log2B, l, r, keys, bsk, V, ct_ms, steps, acc, 1);
 }
 
 /* Constant-term extraction of (A, B) (eq. equ-sam-extr):
@@ -492,7 +503,7 @@ void orc_keyswitch(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2Bks, uint32_
  * entry 0; KeySwitch; ModulusSwitch Q -> q_out (skipped when q_out == Q).
  * Optional outputs (NULL to skip): acc_out (r*2*N), ext_out (N+1), ks_out (n+1). */
 static void bootstrap_one(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
-                          uint32_t log2Bks, uint32_t lks, uint32_t r, const uint32_t *bsk,
+                          uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint32_t *bsk,
                           const uint32_t *ksk, const uint32_t *V, uint32_t q_in,
                           uint32_t q_out, const uint32_t *ct, uint32_t *out,
                           uint32_t *acc_out, uint32_t *ext_out, uint32_t *ks_out, int parallel)
@@ -503,7 +514,7 @@ static void bootstrap_one(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, ui
     uint32_t *ext = (uint32_t *)malloc(sizeof(uint32_t) * (N + 1));
     uint32_t *ks = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
     orc_modswitch_vec(ct, n + 1, q_in, M, ms);
-    blind_rotate(n, N, Q, log2B, l, r, bsk, V, ms, n, acc, parallel);
+    blind_rotate(n, N, Q, log2B, l, r, keys, bsk, V, ms, n, acc, parallel);
     orc_sample_extract(N, Q, acc, ext);
     orc_keyswitch(n, N, Q, log2Bks, lks, ksk, ext, ks);
     if (q_out == Q) memcpy(out, ks, sizeof(uint32_t) * (n + 1));
@@ -518,24 +529,24 @@ static void bootstrap_one(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, ui
 }
 
 void orc_bootstrap(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
-                   uint32_t log2Bks, uint32_t lks, uint32_t r, const uint32_t *bsk,
+                   uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint32_t *bsk,
                    const uint32_t *ksk, const uint32_t *V, uint32_t q_in, uint32_t q_out,
                    const uint32_t *ct, uint32_t *out, uint32_t *acc_out, uint32_t *ext_out,
                    uint32_t *ks_out)
 {
-    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, V, q_in, q_out, ct, out,
+    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, keys, bsk, ksk, V, q_in, q_out, ct, out,
                   acc_out, ext_out, ks_out, 1);
 }
 
 /* Many ciphertexts of one table, one thread per ciphertext. */
 void orc_bootstrap_many(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
-                        uint32_t log2Bks, uint32_t lks, uint32_t r, const uint32_t *bsk,
+                        uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint32_t *bsk,
                         const uint32_t *ksk, const uint32_t *V, uint32_t q_in, uint32_t q_out,
                         const uint32_t *ct, uint64_t count, uint32_t *out)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < (int64_t)count; c++)
-        bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, V, q_in, q_out,
+        bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, keys, bsk, ksk, V, q_in, q_out,
                       ct + (size_t)c * (n + 1), out + (size_t)c * (n + 1), NULL, NULL, NULL, 0);
 }
 
@@ -560,17 +571,17 @@ void orc_general_tables(uint32_t t, uint32_t t_out, const uint32_t *f, uint32_t 
  * plaintext modulus 2t), ct' = ct + ct_g - (0, (t/2) floor(q/2t)) so that
  * ct' encrypts x - b t = m, then bootstrap ct' with F (output at q_out). */
 void orc_bootstrap_general(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint32_t l,
-                           uint32_t log2Bks, uint32_t lks, uint32_t r, const uint32_t *bsk,
+                           uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint32_t *bsk,
                            const uint32_t *ksk, const uint32_t *Vg, const uint32_t *VF, uint32_t q,
                            uint32_t t, uint32_t q_out, const uint32_t *ct, uint32_t *out)
 {
     uint32_t *ctg = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
     uint32_t *ct2 = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
-    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, Vg, q, q, ct, ctg, NULL, NULL, NULL, 1);
+    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, keys, bsk, ksk, Vg, q, q, ct, ctg, NULL, NULL, NULL, 1);
     const uint64_t shift = (uint64_t)(t / 2) * (q / (2 * t)) % q;
     for (uint32_t k = 0; k <= n; k++) ct2[k] = (uint32_t)(((uint64_t)ct[k] + ctg[k]) % q);
     ct2[n] = (uint32_t)(((uint64_t)ct2[n] + q - shift) % q);
-    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, bsk, ksk, VF, q, q_out, ct2, out, NULL, NULL,
+    bootstrap_one(n, N, Q, log2B, l, log2Bks, lks, r, keys, bsk, ksk, VF, q, q_out, ct2, out, NULL, NULL,
                   NULL, 1);
     free(ctg);
     free(ct2);

@@ -9,7 +9,8 @@ Distributions
 -------------
 * uniform residues in [0, M) for key masks and encryption masks;
 * binary secrets s in {0,1}^n and z in {0,1}^N (the secret distribution of the
-  single-key CMux with d_- = 0, Sec. 2 item (15));
+  single-key CMux with d_- = 0, Sec. 2 item (15)), or a ternary s in {-1,0,1}^n
+  (Alg. 1 as printed, two keys per coordinate);
 * the discrete Gaussian on Z with P(x) proportional to exp(-x^2 / (2 sigma^2)),
   tail-cut at 12 sigma, for every error term (sigma = 0 gives the noise-free
   mode used for end-to-end correctness at large t);
@@ -50,10 +51,15 @@ class Params:
     l_ks: int = 8     # key-switch length (ceil(31 / log2_Bks) makes it exact)
     sigma: float = 3.2
     sigma_ks: float = 3.2
+    ternary: bool = False  # s in {-1, 0, 1}^n with two RGSW keys per coordinate
 
     @property
     def B_ks(self) -> int:
         return 1 << self.log2_Bks
+
+    @property
+    def keys_per_coord(self) -> int:
+        return 2 if self.ternary else 1
 
     def noise_free(self) -> "Params":
         return replace(self, sigma=0.0, sigma_ks=0.0)
@@ -84,15 +90,18 @@ def discrete_gaussian(rng: np.random.Generator, sigma: float, size) -> np.ndarra
 def key_draws(p: Params, seed: int) -> dict:
     """All random material of one key set.
 
-    Shapes: s (n,), z (N,), bsk_a (n, 2l, N), bsk_e (n, 2l, N),
+    Shapes: s (n,) int32, z (N,), bsk_a (n * K, 2l, N), bsk_e (n * K, 2l, N) with K
+    keys per coordinate (1 binary, 2 ternary; key k of coordinate i at row i K + k),
     ksk_a (N, l_ks, B_ks, n), ksk_e (N, l_ks, B_ks).
     """
     n, N, l, Q = p.n, p.N, p.l, p.Q
+    K = p.keys_per_coord
+    lo = -1 if p.ternary else 0
     out = {
-        "s": _rng(seed, "s").integers(0, 2, size=n, dtype=np.uint32),
+        "s": _rng(seed, "s").integers(lo, 2, size=n).astype(np.int32),
         "z": _rng(seed, "z").integers(0, 2, size=N, dtype=np.uint32),
-        "bsk_a": _rng(seed, "bsk_a").integers(0, Q, size=(n, 2 * l, N), dtype=np.uint32),
-        "bsk_e": discrete_gaussian(_rng(seed, "bsk_e"), p.sigma, (n, 2 * l, N)),
+        "bsk_a": _rng(seed, "bsk_a").integers(0, Q, size=(n * K, 2 * l, N), dtype=np.uint32),
+        "bsk_e": discrete_gaussian(_rng(seed, "bsk_e"), p.sigma, (n * K, 2 * l, N)),
         "ksk_a": _rng(seed, "ksk_a").integers(0, Q, size=(N, p.l_ks, p.B_ks, n), dtype=np.uint32),
         "ksk_e": discrete_gaussian(_rng(seed, "ksk_e"), p.sigma_ks, (N, p.l_ks, p.B_ks)),
     }

@@ -247,3 +247,76 @@ def test_general_function_two_bootstraps(seed, identity):
     for c in range(ct.shape[0]):
         out = oracle.bootstrap_general(p, r, keys.bsk, keys.ksk, Vg, VF, q, t, q, ct[c])
         assert oracle.decrypt(p.n, q, t_out, keys.s, out)[0] == f[m[c]], (c, m[c])
+
+
+# ---------------------------------------------------------------- ternary secret (Alg. 1 as printed)
+
+def test_ternary_bsk_encrypts_s_plus_and_s_minus():
+    p = Params(n=6, N=32, log2_B=7, l=4, ternary=True)
+    dr = key_draws(p, 40)
+    assert set(dr["s"].tolist()) <= {-1, 0, 1}
+    bsk = oracle.keygen_bsk(p, dr)
+    g = oracle.gadget(Q, p.log2_B, p.l)
+    for i in range(p.n):
+        for key, m in ((0, max(int(dr["s"][i]), 0)), (1, max(-int(dr["s"][i]), 0))):
+            row = 0  # row u = 0 carries m g_0 on b
+            ph = rlwe_phase(bsk[2 * i + key, row, 0], bsk[2 * i + key, row, 1], dr["z"]).astype(np.int64)
+            want = dr["bsk_e"][2 * i + key, row].astype(np.int64)
+            want[0] += m * int(g[0])
+            np.testing.assert_array_equal(ph, want % Q)
+
+
+@pytest.mark.parametrize("N,r,n", [(16, 3, 9), (8, 2, 14)])
+def test_ternary_blind_rotation_trivial_key_closed_form(N, r, n):
+    """With trivial keys, ACC.b = Phi(b' - sum a'_i s_i) V for s in {-1, 0, 1}^n (eq. cmux:BP)."""
+    p = Params(n=n, N=N, log2_B=8, l=4, ternary=True)
+    rng = np.random.default_rng(N * r + n)
+    s = rng.integers(-1, 2, n)
+    sg = oracle.gadget_shift(Q, p.log2_B, p.l)
+    bsk = np.zeros((2 * n, 2 * p.l, 2, N), dtype=np.uint32)
+    bsk[:, :, 0, :] = rng.integers(0, Q, size=(2 * n, 2 * p.l, N), dtype=np.uint32)
+    for i in range(n):
+        for key, m in ((0, max(int(s[i]), 0)), (1, max(-int(s[i]), 0))):
+            for u in range(p.l):
+                gu = pow(2, sg + u * p.log2_B, Q)
+                bsk[2 * i + key, u, 1, 0] = m * gu % Q
+                bsk[2 * i + key, p.l + u, 0, 0] = (int(bsk[2 * i + key, p.l + u, 0, 0]) + m * gu) % Q
+    M = 2 * N * r
+    t = N * r
+    f = negacyclic_table(t, 64, seed=N)
+    V = oracle.test_vector(N, r, Q, t, 64, f)
+    for _ in range(3):
+        ct_ms = rng.integers(0, M, n + 1, dtype=np.uint32)
+        acc = oracle.blind_rotate(p, r, bsk, V, ct_ms)
+        phase = (int(ct_ms[n]) - int(ct_ms[:n].astype(np.int64) @ s)) % M
+        np.testing.assert_array_equal(acc[:, 1, :], oracle.rotate(V, phase, Q))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ternary_end_to_end_tiny(seed):
+    from dataclasses import replace
+    pre = PRESETS["tiny"]
+    p = replace(pre["params"], ternary=True)
+    t, t_out, r = pre["t"], pre["t_out"], pre["r"]
+    keys = oracle.KeySet(p, key_draws(p, seed + 50))
+    f = negacyclic_table(t, t_out, seed + 60)
+    V = oracle.test_vector(p.N, r, Q, t, t_out, f)
+    q = 2 * p.N * r
+    m = np.arange(t, dtype=np.uint32)
+    ed = enc_draws(p.n, q, t, seed + 70)
+    ct = oracle.encrypt(p.n, q, t, keys.s, m, ed["a"], ed["e"])
+    out = oracle.bootstrap_many(p, r, keys.bsk, keys.ksk, V, q, q, ct)
+    np.testing.assert_array_equal(oracle.decrypt(p.n, q, t_out, keys.s, out), f[m])
+
+
+def test_ternary_keyswitch_preserves_phase():
+    p = Params(n=20, N=32, ternary=True).noise_free()
+    dr = key_draws(p, 41)
+    ksk = oracle.keygen_ksk(p, dr)
+    rng = np.random.default_rng(2)
+    z = dr["z"].astype(np.int64)
+    s = dr["s"].astype(np.int64)
+    for _ in range(5):
+        c = rng.integers(0, Q, p.N + 1, dtype=np.uint32)
+        out = oracle.keyswitch(p, ksk, c)
+        assert (int(c[p.N]) - int(c[:p.N].astype(np.int64) @ z)) % Q == (int(out[p.n]) - int(out[:p.n].astype(np.int64) @ s)) % Q
