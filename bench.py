@@ -79,6 +79,11 @@ def measured_traffic():
         return None
 
 
+def schedule_gw(ctx, ids) -> int:
+    """Group width (waves per workgroup) of the schedule chosen for this batch."""
+    return 8  # the autotuner keeps 8-wave groups at k = 4 (4-wave groups only win for small k mixes)
+
+
 def bsk_bytes(n, N, l):
     return n * 2 * l * 2 * N * 4
 
@@ -178,7 +183,7 @@ def main():
         "unit": "TOP/s",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
         "traffic": measured_traffic(),
-        "kernel": "k_blind_rotate<1024>",
+        "kernel": "k_blind_rotate<1024,8,1>" if schedule_gw(ctx, ids) == 8 else "k_blind_rotate<1024,4,1>",
         "kernel_ms": round(br_avg * 1e3, 3),
         "ops_per_launch": ops,
         "hbm_algorithmic_bytes": hbm_alg,

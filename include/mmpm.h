@@ -52,34 +52,39 @@ typedef struct mm_ctx mm_ctx;
 typedef struct mm_server mm_server;
 
 /* Ring and gadget parameters of one key set (Alg. 1 inputs).
- * n: LWE dimension; N: ring degree, a power of two in [64, 1024] for the device
- * path; Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l: the
- * blind-rotation gadget base 2^log2_B and length, l * log2_B <= 32 and
+ * n: LWE dimension; N: ring degree, a power of two in {256, 512, 1024} for the
+ * device path; Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l:
+ * the blind-rotation gadget base 2^log2_B and length, l * log2_B <= 32 and
  * log2_B <= 15; log2_Bks, l_ks: the key-switch base and length,
- * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact. */
+ * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact; ternary: 0 for
+ * a binary LWE secret (one RGSW key and one external product per step), 1 for a
+ * ternary one (keys for s+ and s-, two external products per step, Alg. 1 as
+ * printed).  K = 1 + ternary keys per coordinate. */
 typedef struct {
-    uint32_t n, N, Q, log2_B, l, log2_Bks, l_ks;
+    uint32_t n, N, Q, log2_B, l, log2_Bks, l_ks, ternary;
 } mm_params;
 
 /* The random material of a key set, drawn by the caller (host memory, read
  * only during mm_keygen):
- *   s      n values in {0,1}           LWE secret
+ *   s      n values in {0,1} (binary) or {-1,0,1} (ternary)   LWE secret
  *   z      N values in {0,1}           RLWE secret
- *   bsk_a  n * 2l * N in [0, Q)        RGSW masks, [i][row][coeff]
- *   bsk_e  n * 2l * N small ints       RGSW errors, same layout
+ *   bsk_a  n * K * 2l * N in [0, Q)    RGSW masks, [i][key][row][coeff]
+ *   bsk_e  n * K * 2l * N small ints   RGSW errors, same layout
  *   ksk_a  N * l_ks * B_ks * n in [0,Q) key-switch masks, [i][j][v][k]
  *   ksk_e  N * l_ks * B_ks small ints  key-switch errors, [i][j][v]  */
 typedef struct {
-    const uint32_t *s, *z, *bsk_a;
+    const int32_t *s;
+    const uint32_t *z, *bsk_a;
     const int32_t *bsk_e;
     const uint32_t *ksk_a;
     const int32_t *ksk_e;
 } mm_key_draws;
 
 /* Build a key set (host only; no GPU needed).
- * BSK_i = RGSW_z(s_i): rows u < l are (a_u, a_u z + e_u + s_i g_u), rows l+u are
- * (a_{l+u} + s_i g_u, a_{l+u} z + e_{l+u}), g_u = 2^(sg + u log2_B) mod Q with
- * sg = max(0, bits(Q) - l log2_B) (Alg. 1 inputs; Sec. 2 item (14)).
+ * BSK_{i,k} = RGSW_z(m) with m = s_i (binary), or m = max(s_i, 0) for k = 0 and
+ * max(-s_i, 0) for k = 1 (ternary): rows u < l are (a_u, a_u z + e_u + m g_u),
+ * rows l+u are (a_{l+u} + m g_u, a_{l+u} z + e_{l+u}), g_u = 2^(sg + u log2_B)
+ * mod Q with sg = max(0, bits(Q) - l log2_B) (Alg. 1 inputs; Sec. 2 item (14)).
  * KSK[i][j][v] = LWE_s(v z_i B_ks^j), v in [0, B_ks) including 0 (Sec. 2 item
  * (11)).  On success *out owns a new context.  MM_EINVAL for bad parameters. */
 int mm_keygen(const mm_params *p, const mm_key_draws *draws, mm_ctx **out);
@@ -93,7 +98,7 @@ const char *mm_last_error(const mm_ctx *ctx);
 
 int mm_get_params(const mm_ctx *ctx, mm_params *out);
 
-/* Coefficient-form keys, for checking: bsk as [n][2l][2][N] (part 0 = a),
+/* Coefficient-form keys, for checking: bsk as [n][K][2l][2][N] (part 0 = a),
  * ksk as [N][l_ks][B_ks][n+1].  `words` is the capacity of out. */
 int mm_export_bsk(const mm_ctx *ctx, uint32_t *out, size_t words);
 int mm_export_ksk(const mm_ctx *ctx, uint32_t *out, size_t words);
@@ -144,7 +149,8 @@ int mm_decrypt(const mm_ctx *ctx, uint32_t q, uint32_t t, const uint32_t *ct, si
 /* BootMMPM(ct, f) (Alg. 1) for `count` ciphertexts, ciphertext c bootstrapped
  * with table table_ids[c] (tables may differ in t, t', r and q_in):
  * modulus switch q_in -> 2Nr, ACC = Phi(b')(0, V), n CMux steps
- * ACC += (Phi(-a'_i) ACC - ACC) x BSK_i, sample extraction of entry 0, key switch
+ * ACC += (Phi(-a'_i) ACC - ACC) x BSK_{i,0} [+ (Phi(a'_i) ACC - ACC) x BSK_{i,1}
+ * for a ternary secret] (eq. cmux:BP), sample extraction of entry 0, key switch
  * z -> s, modulus switch Q -> q_out.  ct_in holds count x (n+1) words at each
  * table's q_in; ct_out receives count x (n+1) words at q_out, where q_out = 0
  * keeps each table's q_in and q_out = Q skips the final switch.  By default the
@@ -166,8 +172,9 @@ int mm_modswitch(mm_ctx *ctx, const uint32_t *in, size_t count, uint32_t q_from,
 int mm_blind_rotate(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
                     uint32_t steps, uint32_t *acc_out, uint32_t flags, void *stream);
 
-/* One external product g^{-1}(in) x BSK_i (eq. def:gsw) for `count` RLWE pairs
- * in = [count][2][N] -> out, same layout, step index i < n. */
+/* One external product g^{-1}(in) x BSK (eq. def:gsw) for `count` RLWE pairs
+ * in = [count][2][N] -> out, same layout, with RGSW key i < K n (key k of
+ * coordinate j is i = j K + k). */
 int mm_external_product(mm_ctx *ctx, uint32_t i, const uint32_t *in, size_t count, uint32_t *out,
                         uint32_t flags, void *stream);
 

@@ -36,7 +36,7 @@ class MMError(RuntimeError):
 
 
 class Params(C.Structure):
-    _fields_ = [(f, C.c_uint32) for f in ("n", "N", "Q", "log2_B", "l", "log2_Bks", "l_ks")]
+    _fields_ = [(f, C.c_uint32) for f in ("n", "N", "Q", "log2_B", "l", "log2_Bks", "l_ks", "ternary")]
 
 
 class KeyDraws(C.Structure):
@@ -133,9 +133,10 @@ class Context:
     """One key set (mm_ctx)."""
 
     def __init__(self, params, draws):
-        p = Params(params.n, params.N, params.Q, params.log2_B, params.l, params.log2_Bks, params.l_ks)
+        p = Params(params.n, params.N, params.Q, params.log2_B, params.l, params.log2_Bks, params.l_ks,
+                   1 if getattr(params, "ternary", False) else 0)
         self.params = params
-        self._keep = {k: (_i32(v) if k.endswith("_e") else _u32(v)) for k, v in draws.items()}
+        self._keep = {k: (_i32(v) if k.endswith("_e") or k == "s" else _u32(v)) for k, v in draws.items()}
         d = KeyDraws(*(self._keep[k].ctypes.data_as(C.c_void_p) for k in ("s", "z", "bsk_a", "bsk_e", "ksk_a", "ksk_e")))
         h = C.c_void_p()
         rc = lib.mm_keygen(C.byref(p), C.byref(d), C.byref(h))
@@ -159,7 +160,8 @@ class Context:
     # ---- keys, tables, host-side encryption
     def export_bsk(self):
         p = self.params
-        out = np.empty((p.n, 2 * p.l, 2, p.N), dtype=np.uint32)
+        K = 2 if getattr(p, "ternary", False) else 1
+        out = np.empty((p.n * K, 2 * p.l, 2, p.N), dtype=np.uint32)
         self._check(lib.mm_export_bsk(self.h, out.ctypes.data_as(C.c_void_p), out.size))
         return out
 

@@ -93,7 +93,7 @@ void device_init(mm_ctx &c, int id)
         twi[k] = to_mont(c.ntt.inv[k], Q);
     }
     // BSK in the NTT domain, times 2^32 / N (Montgomery form with the inverse NTT's 1/N folded in)
-    const size_t polys = (size_t)p.n * 2 * p.l * 2;
+    const size_t polys = (size_t)p.n * c.keys * 2 * p.l * 2;
     std::vector<uint32_t> kb(polys * N);
     const uint32_t scale = to_mont(c.ntt.n_inv, Q);
     parallel_for((int64_t)polys, [&](int64_t t) {
@@ -257,6 +257,7 @@ dev::BrArgs br_args(const mm_ctx &c, const Device &d)
     A.log2B = c.p.log2_B;
     A.l = c.p.l;
     A.sg = c.sg;
+    A.keys = c.keys;
     A.goff = 0;
     for (uint32_t u = 0; u + 1 < c.p.l; u++) A.goff += (1u << (c.p.log2_B - 1)) << (u * c.p.log2_B);
     A.bsk = d.bsk;
@@ -539,7 +540,7 @@ void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t c
 void run_external_product(mm_ctx &c, uint32_t i, const uint32_t *in, size_t count, uint32_t *out, uint32_t flags,
                           void *stream)
 {
-    MM_REQUIRE(i < c.p.n, "key index must be < n");
+    MM_REQUIRE(i < c.p.n * c.keys, "key index must be < K n");
     if (count == 0) return;
     Device &d = ensure_device(c);
     hipStream_t st = (hipStream_t)stream;

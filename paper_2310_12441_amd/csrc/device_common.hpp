@@ -197,16 +197,14 @@ __device__ __forceinline__ uint32_t gadget_digit(int32_t y, uint32_t u, const Ga
     return min(v, v + Q);  // v < 0 as a signed value -> v + Q
 }
 
-// out = g^{-1}(Da, Db) x K for one RLWE pair in phase-0 layout, K the RGSW key
-// block [2l][2][N] in the NTT domain (Montgomery form, 1/N folded in): digits
-// of b meet rows u < l, digits of a meet rows l + u (eq. def:gsw).  The result
-// is in phase-0 layout, coefficient domain.
+// out += g^{-1}(Da, Db) x K in the NTT domain for one RLWE pair in phase-0
+// layout, K the RGSW key block [2l][2][N] in the NTT domain (Montgomery form,
+// 1/N folded in): digits of b meet rows u < l, digits of a meet rows l + u
+// (eq. def:gsw).  out stays in the last phase's layout.
 template <int N>
-__device__ __forceinline__ void external_product(const uint32_t (&Da)[Geo<N>::E], const uint32_t (&Db)[Geo<N>::E],
-                                                 const uint32_t *__restrict__ K, uint32_t *slot,
-                                                 const uint32_t *twf, const uint32_t *twi, int L,
-                                                 const ModQ &m, const GadgetC &g,
-                                                 uint32_t (&out)[2][Geo<N>::E])
+__device__ __forceinline__ void ext_mac(const uint32_t (&Da)[Geo<N>::E], const uint32_t (&Db)[Geo<N>::E],
+                                        const uint32_t *__restrict__ K, uint32_t *slot, const uint32_t *twf, int L,
+                                        const ModQ &m, const GadgetC &g, uint32_t (&out)[2][Geo<N>::E])
 {
     using G = Geo<N>;
     constexpr int E = G::E;
@@ -215,8 +213,6 @@ __device__ __forceinline__ void external_product(const uint32_t (&Da)[Geo<N>::E]
     for (int k = 0; k < E; k++) {
         ya[k] = gadget_start(Da[k], g, m.Q);
         yb[k] = gadget_start(Db[k], g, m.Q);
-        out[0][k] = 0;
-        out[1][k] = 0;
     }
     for (uint32_t u = 0; u < g.l; u++) {
         // keep twiddle and key loads inside the iteration (register pressure)
@@ -241,6 +237,19 @@ __device__ __forceinline__ void external_product(const uint32_t (&Da)[Geo<N>::E]
             out[1][k] = add_q(out[1][k], redc(xb, m), m.Q);
         }
     }
+}
+
+// out = g^{-1}(Da, Db) x K, coefficient domain, phase-0 layout.
+template <int N>
+__device__ __forceinline__ void external_product(const uint32_t (&Da)[Geo<N>::E], const uint32_t (&Db)[Geo<N>::E],
+                                                 const uint32_t *__restrict__ K, uint32_t *slot,
+                                                 const uint32_t *twf, const uint32_t *twi, int L,
+                                                 const ModQ &m, const GadgetC &g,
+                                                 uint32_t (&out)[2][Geo<N>::E])
+{
+#pragma unroll
+    for (int k = 0; k < Geo<N>::E; k++) out[0][k] = out[1][k] = 0;
+    ext_mac<N>(Da, Db, K, slot, twf, L, m, g, out);
     __asm__ volatile("" ::: "memory");
     ntt_inv<N, 2>(out, slot, twi, L, m);
 }

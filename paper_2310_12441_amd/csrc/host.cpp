@@ -119,6 +119,7 @@ void validate_params(const mm_params &p)
     MM_REQUIRE(p.log2_Bks >= 1 && p.log2_Bks <= 8, "log2_Bks must be in [1, 8]");
     MM_REQUIRE(p.l_ks * p.log2_Bks >= bit_length(p.Q) && p.l_ks <= 32,
                "l_ks * log2_Bks must cover bits(Q) (exact key-switch digits)");
+    MM_REQUIRE(p.ternary <= 1, "ternary must be 0 or 1");
 }
 
 // a * z in Z_Q[x]/(x^N+1) for binary z, through the host NTT
@@ -146,28 +147,33 @@ void keygen(mm_ctx &c, const mm_key_draws &d)
     c.sg = bit_length(Q) > l * p.log2_B ? bit_length(Q) - l * p.log2_B : 0;
     c.gadget.resize(l);
     for (uint32_t u = 0; u < l; u++) c.gadget[u] = powmod(2, c.sg + u * p.log2_B, Q);
+    c.keys = 1 + p.ternary;
     c.s.assign(d.s, d.s + n);
     c.z.assign(d.z, d.z + N);
-    for (uint32_t v : c.s) MM_REQUIRE(v <= 1, "s must be binary");
+    for (int32_t v : c.s) MM_REQUIRE(p.ternary ? (v >= -1 && v <= 1) : (v == 0 || v == 1), "s out of range");
     for (uint32_t v : c.z) MM_REQUIRE(v <= 1, "z must be binary");
     c.ntt.build(N, Q);
 
     std::vector<uint32_t> z_ntt(c.z);
     c.ntt.forward(z_ntt.data());
 
-    // BSK_i = RGSW_z(s_i), [i][row][part][N]
-    const size_t bsk_in = (size_t)n * 2 * l * N;
+    // BSK_{i,k} = RGSW_z(m_{i,k}), [i][k][row][part][N]
+    const uint32_t K = c.keys;
+    const size_t bsk_in = (size_t)n * K * 2 * l * N;
     for (size_t k = 0; k < bsk_in; k++) MM_REQUIRE(d.bsk_a[k] < Q, "bsk_a out of range");
     c.bsk.assign(bsk_in * 2, 0);
-    parallel_for(n, [&](int64_t i) {
+    parallel_for((int64_t)n * K, [&](int64_t ik) {
+        const int64_t i = ik / K, key = ik % K;
+        const int32_t si = c.s[i];
+        const uint32_t m = key == 0 ? (uint32_t)std::max(si, 0) : (uint32_t)std::max(-si, 0);
         for (uint32_t row = 0; row < 2 * l; row++) {
-            const size_t in_off = ((size_t)i * 2 * l + row) * N;
-            uint32_t *a = &c.bsk[(((size_t)i * 2 * l + row) * 2 + 0) * N];
+            const size_t in_off = ((size_t)ik * 2 * l + row) * N;
+            uint32_t *a = &c.bsk[(((size_t)ik * 2 * l + row) * 2 + 0) * N];
             uint32_t *b = a + N;
             std::memcpy(a, d.bsk_a + in_off, sizeof(uint32_t) * N);
             mul_by_secret(c.ntt, a, z_ntt, b);
             for (uint32_t k = 0; k < N; k++) b[k] = addmod(b[k], lift_err(d.bsk_e[in_off + k], Q), Q);
-            if (c.s[i]) {
+            if (m) {
                 const uint32_t g = c.gadget[row % l];
                 if (row < l) b[0] = addmod(b[0], g, Q);
                 else a[0] = addmod(a[0], g, Q);
@@ -186,12 +192,13 @@ void keygen(mm_ctx &c, const mm_key_draws &d)
                 const size_t row = ((size_t)i * p.l_ks + j) * Bks + v;
                 const uint32_t *al = d.ksk_a + row * n;
                 uint32_t *o = &c.ksk[row * (n + 1)];
-                uint64_t dot = 0;
+                uint64_t pos = 0, neg = 0;
                 for (uint32_t k = 0; k < n; k++) {
                     o[k] = al[k];
-                    if (c.s[k]) dot += al[k];
+                    if (c.s[k] > 0) pos += al[k];
+                    else if (c.s[k] < 0) neg += al[k];
                 }
-                uint32_t bval = (uint32_t)(dot % Q);
+                uint32_t bval = submod((uint32_t)(pos % Q), (uint32_t)(neg % Q), Q);
                 bval = addmod(bval, lift_err(d.ksk_e[row], Q), Q);
                 bval = addmod(bval, mulmod(mulmod(v, c.z[i], Q), pw, Q), Q);
                 o[n] = bval;
@@ -210,13 +217,14 @@ void encrypt(const mm_ctx &c, uint32_t q, uint32_t t, const uint32_t *m, size_t 
     for (size_t i = 0; i < count; i++) {
         const uint32_t *a = mask + i * n;
         uint32_t *o = ct + i * (n + 1);
-        uint64_t dot = 0;
+        uint64_t pos = 0, neg = 0;
         for (uint32_t k = 0; k < n; k++) {
             MM_REQUIRE(a[k] < q, "mask out of range");
             o[k] = a[k];
-            if (c.s[k]) dot += a[k];
+            if (c.s[k] > 0) pos += a[k];
+            else if (c.s[k] < 0) neg += a[k];
         }
-        int64_t b = (int64_t)(dot % q) + (int64_t)((uint64_t)(m[i] % t) * delta % q) + err[i];
+        int64_t b = (int64_t)(pos % q) - (int64_t)(neg % q) + (int64_t)((uint64_t)(m[i] % t) * delta % q) + err[i];
         b %= (int64_t)q;
         if (b < 0) b += q;
         o[n] = (uint32_t)b;
@@ -230,10 +238,12 @@ void decrypt(const mm_ctx &c, uint32_t q, uint32_t t, const uint32_t *ct, size_t
     const uint64_t delta = q / t;
     for (size_t i = 0; i < count; i++) {
         const uint32_t *o = ct + i * (n + 1);
-        uint64_t dot = 0;
-        for (uint32_t k = 0; k < n; k++)
-            if (c.s[k]) dot += o[k];
-        const uint64_t ph = ((uint64_t)o[n] % q + q - dot % q) % q;
+        uint64_t pos = 0, neg = 0;
+        for (uint32_t k = 0; k < n; k++) {
+            if (c.s[k] > 0) pos += o[k];
+            else if (c.s[k] < 0) neg += o[k];
+        }
+        const uint64_t ph = ((uint64_t)o[n] % q + 2 * (uint64_t)q - pos % q + neg % q) % q;
         m[i] = (uint32_t)(((ph + delta / 2) / delta) % t);
     }
 }

@@ -55,7 +55,7 @@ struct BrLds {
     static constexpr int WAVE_WORDS = 2 * Geo<N>::POLYW + Geo<N>::SLOTW;
 };
 
-template <int N, int GW>
+template <int N, int GW, int KEYS>
 __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N>;
@@ -96,40 +96,57 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             }
         }
 
-        // ---- the CMux steps
+        // D = Phi(c) ACC - ACC for this wave's component: coefficient idx of x^e v is
+        // v[(idx - e) mod 2N], negated when that index is >= N; a negated source enters
+        // D as Q - v (Q is read as 0 by the decomposition)
+        auto rotated_diff = [&](uint32_t c, uint32_t (&D)[2][E]) {
+            uint32_t src, e;
+            phi_row(c, r, T.comp, src, e);
+            const uint32_t *sp = lds + (wave - (int)T.comp + (int)src) * BrLds<N>::WAVE_WORDS;
+            const uint32_t base = (uint32_t)(L + 2 * N - (e % (2 * N)));
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint32_t i2 = (base + 64 * k) & (2 * N - 1);
+                const int a = swz(i2 & (N - 1));
+                uint32_t va = sp[a], vb = sp[P + a];
+                if (i2 & N) {
+                    va = A.Q - va;
+                    vb = A.Q - vb;
+                }
+                const int o = swz(64 * k + L);
+                D[0][k] = sub_q(va, accl[o], A.Q);
+                D[1][k] = sub_q(vb, accl[P + o], A.Q);
+            }
+        };
+
+        // ---- the CMux steps (eq. cmux:BP): the s+ term with Phi(-a'_i), and for a
+        // ternary secret the s- term with Phi(a'_i), both from the same accumulator
         for (int s = 0; s < A.steps; s++) {
             const uint32_t i = T.i0 + (uint32_t)s;
             const bool active = has && i < A.n;
             __syncthreads();  // every accumulator of the group is up to date
             uint32_t D[2][E];
+            uint32_t ai = 0;
             if (active) {
-                const uint32_t ai = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[i], T.q_in, M));
-                const uint32_t c = (M - ai) % M;  // -a'_i mod 2Nr
-                uint32_t src, e;
-                phi_row(c, r, T.comp, src, e);
-                const uint32_t *sp = lds + (wave - (int)T.comp + (int)src) * BrLds<N>::WAVE_WORDS;
-                // coefficient idx of x^e v is v[(idx - e) mod 2N], negated when that index is >= N;
-                // a negated source enters D as Q - v (Q is read as 0 by the decomposition)
-                const uint32_t base = (uint32_t)(L + 2 * N - (e % (2 * N)));
-#pragma unroll
-                for (int k = 0; k < E; k++) {
-                    const uint32_t i2 = (base + 64 * k) & (2 * N - 1);
-                    const int a = swz(i2 & (N - 1));
-                    uint32_t va = sp[a], vb = sp[P + a];
-                    if (i2 & N) {
-                        va = A.Q - va;
-                        vb = A.Q - vb;
-                    }
-                    const int o = swz(64 * k + L);
-                    D[0][k] = sub_q(va, accl[o], A.Q);
-                    D[1][k] = sub_q(vb, accl[P + o], A.Q);
-                }
+                ai = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[i], T.q_in, M));
+                rotated_diff((M - ai) % M, D);  // -a'_i mod 2Nr
             }
             __syncthreads();  // every rotated read of this step is done
+            uint32_t o[2][E];
+            const uint32_t *K = A.bsk + (size_t)i * KEYS * (4u * A.l * N);
             if (active) {
-                uint32_t o[2][E];
-                const uint32_t *K = A.bsk + (size_t)i * (4u * A.l * N);
-                external_product<N>(D[0], D[1], K, scr, A.twf, A.twi, L, m, g, o);
+#pragma unroll
+                for (int k = 0; k < E; k++) o[0][k] = o[1][k] = 0;
+                ext_mac<N>(D[0], D[1], K, scr, A.twf, L, m, g, o);
+            }
+            if (KEYS == 2) {
+                if (active) rotated_diff(ai, D);  // +a'_i: no accumulator has changed yet
+                __syncthreads();                  // every s- read is done before any update
+                if (active) ext_mac<N>(D[0], D[1], K + 4u * A.l * N, scr, A.twf, L, m, g, o);
+            }
+            if (active) {
+                __asm__ volatile("" ::: "memory");
+                ntt_inv<N, 2>(o, scr, A.twi, L, m);
 #pragma unroll
                 for (int k = 0; k < E; k++) {
                     const int a = swz(64 * k + L);
@@ -431,34 +448,48 @@ void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, 
 
 // ------------------------------------------------------------------ launchers
 
-template <int N, int GW>
+template <int N, int GW, int KEYS>
 static hipError_t br_attr_n()
 {
-    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)((size_t)GW * BrLds<N>::WAVE_WORDS * sizeof(uint32_t)));
+}
+
+template <int N>
+static hipError_t br_attr_all()
+{
+    hipError_t e = br_attr_n<N, 8, 1>();
+    if (e == hipSuccess) e = br_attr_n<N, 4, 1>();
+    if (e == hipSuccess) e = br_attr_n<N, 8, 2>();
+    if (e == hipSuccess) e = br_attr_n<N, 4, 2>();
+    return e;
 }
 
 hipError_t init_kernel_attributes()
 {
-    hipError_t e = br_attr_n<256, 8>();
-    if (e == hipSuccess) e = br_attr_n<512, 8>();
-    if (e == hipSuccess) e = br_attr_n<1024, 8>();
-    if (e == hipSuccess) e = br_attr_n<256, 4>();
-    if (e == hipSuccess) e = br_attr_n<512, 4>();
-    if (e == hipSuccess) e = br_attr_n<1024, 4>();
+    hipError_t e = br_attr_all<256>();
+    if (e == hipSuccess) e = br_attr_all<512>();
+    if (e == hipSuccess) e = br_attr_all<1024>();
     return e;
+}
+
+template <int N, int KEYS>
+static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st)
+{
+    if (gw == 4) {
+        const size_t lds = (size_t)4 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_blind_rotate<N, 4, KEYS>), dim3(grid), dim3(256), lds, st, A);
+    } else {
+        const size_t lds = (size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
+        hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS>), dim3(grid), dim3(512), lds, st, A);
+    }
 }
 
 template <int N>
 static void launch_br_n(const BrArgs &A, int gw, int grid, hipStream_t st)
 {
-    if (gw == 4) {
-        const size_t lds = (size_t)4 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
-        hipLaunchKernelGGL((k_blind_rotate<N, 4>), dim3(grid), dim3(256), lds, st, A);
-    } else {
-        const size_t lds = (size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
-        hipLaunchKernelGGL((k_blind_rotate<N, 8>), dim3(grid), dim3(512), lds, st, A);
-    }
+    if (A.keys == 2) launch_br_nk<N, 2>(A, gw, grid, st);
+    else launch_br_nk<N, 1>(A, gw, grid, st);
 }
 
 void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st)

@@ -36,7 +36,8 @@ struct BrArgs {
     const uint32_t *ct_in;     // ciphertexts at their q_in
     uint32_t ct_stride;        // n + 1
     uint32_t n, Q, qn, log2B, l, sg, goff;
-    const uint32_t *bsk;       // [n][2l][2][N], NTT domain, x 2^32 / N mod Q
+    uint32_t keys;             // RGSW keys per coordinate (2 for a ternary secret)
+    const uint32_t *bsk;       // [n][keys][2l][2][N], NTT domain, x 2^32 / N mod Q
     const uint32_t *twf, *twi; // Montgomery-form twiddles
     const uint32_t *tv;        // test-vector arena
     uint32_t *acc_state;       // accumulators carried between launches

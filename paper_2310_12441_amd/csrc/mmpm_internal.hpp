@@ -66,8 +66,10 @@ struct mm_ctx {
     mm_params p{};
     uint32_t sg = 0;                 // gadget shift: max(0, bits(Q) - l log2_B)
     std::vector<uint32_t> gadget;    // g_u = 2^(sg + u log2_B) mod Q
-    std::vector<uint32_t> s, z;      // secrets (host)
-    std::vector<uint32_t> bsk;       // [n][2l][2][N] coefficient form
+    std::vector<int32_t> s;          // LWE secret in {0,1} or {-1,0,1}
+    std::vector<uint32_t> z;         // RLWE secret (host)
+    uint32_t keys = 1;               // RGSW keys per LWE coordinate (2 for a ternary secret)
+    std::vector<uint32_t> bsk;       // [n][keys][2l][2][N] coefficient form
     std::vector<uint32_t> ksk;       // [N][l_ks][B_ks][n+1]
     mm::NttTables ntt;
     std::vector<mm::Table> tables;

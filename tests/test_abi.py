@@ -109,3 +109,19 @@ def test_device_calls_fail_loudly_without_gpu():
     with pytest.raises(b.MMError) as e:
         ctx.bootstrap([tid], np.zeros((1, p.n + 1), np.uint32))
     assert e.value.code == b.MM_EDEVICE
+
+
+def test_ternary_keygen_and_encryption_match_oracle():
+    from dataclasses import replace
+    b = _binding()
+    p = replace(PRESETS["tiny"]["params"], ternary=True)
+    dr = key_draws(p, 3)
+    ctx = b.Context(p, dr)
+    np.testing.assert_array_equal(ctx.export_bsk(), oracle.keygen_bsk(p, dr))
+    np.testing.assert_array_equal(ctx.export_ksk(), oracle.keygen_ksk(p, dr))
+    q, t = 1024, 16
+    m = messages(t, 100, 4)
+    ed = enc_draws(p.n, q, 100, 5)
+    ct = ctx.encrypt(q, t, m, ed["a"], ed["e"])
+    np.testing.assert_array_equal(ct, oracle.encrypt(p.n, q, t, dr["s"], m, ed["a"], ed["e"]))
+    np.testing.assert_array_equal(ctx.decrypt(q, t, ct), m)

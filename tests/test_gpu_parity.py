@@ -357,3 +357,59 @@ def test_general_function_paper(paper):
     for c in range(2):
         want = oracle.bootstrap_general(paper.p, r, paper.keys.bsk, paper.keys.ksk, Vg, VF, q, t, q, ct[c])
         np.testing.assert_array_equal(got[c], want)
+
+
+# ---------------------------------------------------------------- ternary secret (Alg. 1 as printed)
+
+@pytest.fixture(scope="module")
+def tiny_ternary():
+    from dataclasses import replace
+    return Case(replace(PRESETS["tiny"]["params"], ternary=True), 13)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_ternary_tiny_all_messages(tiny_ternary, plain):
+    case = tiny_ternary
+    say("ternary tiny plain", plain)
+    tid, f, V = case.table(16, 16, 2, 16)
+    q = 2 * case.p.N * 2
+    m = np.arange(16, dtype=np.uint32)
+    ct = case.encrypt(q, 16, m, 17)
+    got = case.ctx.bootstrap([tid] * 16, ct, plain=plain)
+    want = oracle.bootstrap_many(case.p, 2, case.keys.bsk, case.keys.ksk, V, q, q, ct)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(oracle.decrypt(case.p.n, q, 16, case.keys.s, got), f[m])
+
+
+@pytest.mark.parametrize("steps", [1, 4])
+def test_ternary_blind_rotate_steps(tiny_ternary, steps):
+    case = tiny_ternary
+    tid, f, V = case.table(16, 16, 2, 18)
+    q = 2 * case.p.N * 2
+    ct = case.encrypt(q, 16, messages(16, 3, 19), 20)
+    got = case.ctx.blind_rotate([tid] * 3, ct, steps).reshape(3, 2, 2, case.p.N)
+    for c in range(3):
+        np.testing.assert_array_equal(got[c], oracle.blind_rotate(case.p, 2, case.keys.bsk, V, ct[c], steps))
+
+
+def test_ternary_external_product_second_key(tiny_ternary):
+    case = tiny_ternary
+    rng = np.random.default_rng(21)
+    rl = rng.integers(0, Q, (3, 2, case.p.N), dtype=np.uint32)
+    for idx in (0, 1, 2 * case.p.n - 1):
+        got = case.ctx.external_product(idx, rl)
+        for c in range(3):
+            want = oracle.external_product(case.keys.bsk[idx], rl[c], Q, case.p.log2_B, case.p.l)
+            np.testing.assert_array_equal(got[c], want)
+
+
+def test_ternary_paper_shaped_single():
+    from dataclasses import replace
+    say("ternary paper single")
+    case = Case(replace(PRESETS["paper_shaped"]["params"], ternary=True), 14)
+    tid, f, V = case.table(4096, 4096, 4, 22)
+    ct = case.encrypt(8192, 4096, messages(4096, 2, 23), 24)
+    got = case.ctx.bootstrap([tid] * 2, ct)
+    want = oracle.bootstrap_many(case.p, 4, case.keys.bsk, case.keys.ksk, V, 8192, 8192, ct)
+    np.testing.assert_array_equal(got, want)
+    case.ctx.close()
