@@ -79,11 +79,6 @@ def measured_traffic():
         return None
 
 
-def schedule_gw(ctx, ids) -> int:
-    """Group width (waves per workgroup) of the schedule chosen for this batch."""
-    return 8  # the autotuner keeps 8-wave groups at k = 4 (4-wave groups only win for small k mixes)
-
-
 def bsk_bytes(n, N, l):
     return n * 2 * l * 2 * N * 4
 
@@ -131,6 +126,7 @@ def main():
 
     # ---- schedule for this batch shape (not timed)
     schedule = ctx.autotune(ids, ct)
+    sched = ctx.schedule_describe(ids)
 
     # ---- batched path (timed)
     ctx.set_timing(True)
@@ -183,7 +179,7 @@ def main():
         "unit": "TOP/s",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
         "traffic": measured_traffic(),
-        "kernel": "k_blind_rotate<1024,8,1>" if schedule_gw(ctx, ids) == 8 else "k_blind_rotate<1024,4,1>",
+        "kernel": f"k_blind_rotate<1024,{sched[0]},1>",
         "kernel_ms": round(br_avg * 1e3, 3),
         "ops_per_launch": ops,
         "hbm_algorithmic_bytes": hbm_alg,
@@ -263,7 +259,7 @@ def main():
         "batched_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
         "plain_equals_batched": plain_same,
         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
-        "schedule": schedule,
+        "schedule": {"index": schedule, "group_waves": sched[0], "ks_cts_per_wave": sched[1], "ks_splits": sched[2]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,

@@ -217,6 +217,12 @@ int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t
 int mm_schedule_count(mm_ctx *ctx, const int *table_ids, size_t count, int *n);
 int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice);
 
+/* What schedule `choice` of this batch shape is (choice < 0: the one in use):
+ * waves per blind-rotation workgroup (8 or 4), ciphertexts per wave of the
+ * LDS-tiled key switch (0 = the i-split key switch) and the number of i splits. */
+int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
+                         int *ks_cts_per_wave, int *ks_splits);
+
 /* ---- serving: continuous batching ---- */
 
 /* Start a server on ctx.  It owns up to `slots` in-flight ciphertexts whose

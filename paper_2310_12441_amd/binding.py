@@ -24,7 +24,7 @@ SYMBOLS = [
     "mm_device_init", "mm_table_create", "mm_table_create_general", "mm_table_info", "mm_table_export", "mm_encrypt", "mm_decrypt",
     "mm_bootstrap", "mm_modswitch", "mm_blind_rotate", "mm_external_product", "mm_sample_extract",
     "mm_keyswitch", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune",
-    "mm_schedule_count", "mm_set_schedule", "mm_server_start", "mm_submit", "mm_poll",
+    "mm_schedule_count", "mm_set_schedule", "mm_schedule_describe", "mm_server_start", "mm_submit", "mm_poll",
     "mm_server_stats", "mm_server_stop", "mm_server_replay",
 ]
 
@@ -75,6 +75,7 @@ def _load():
         "mm_autotune": (i32, [vp, vp, vp, sz, C.POINTER(i32)]),
         "mm_schedule_count": (i32, [vp, vp, sz, C.POINTER(i32)]),
         "mm_set_schedule": (i32, [vp, vp, sz, i32]),
+        "mm_schedule_describe": (i32, [vp, vp, sz, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "mm_server_start": (i32, [vp, sz, u32, C.POINTER(vp)]),
         "mm_submit": (i32, [vp, i32, vp, C.POINTER(u64)]),
         "mm_poll": (i32, [vp, u64, vp]),
@@ -309,6 +310,14 @@ class Context:
     def set_schedule(self, table_ids, choice: int):
         ids = _i32(np.atleast_1d(table_ids))
         self._check(lib.mm_set_schedule(self.h, ids.ctypes.data_as(C.c_void_p), ids.size, choice))
+
+    def schedule_describe(self, table_ids, choice: int = -1):
+        """(waves per blind-rotation workgroup, key-switch ciphertexts per wave, key-switch splits)."""
+        ids = _i32(np.atleast_1d(table_ids))
+        v = [C.c_int() for _ in range(3)]
+        self._check(lib.mm_schedule_describe(self.h, ids.ctypes.data_as(C.c_void_p), ids.size, choice,
+                                             *(C.byref(x) for x in v)))
+        return tuple(x.value for x in v)
 
     # ---- serving
     def server_start(self, hbm_budget_bytes: int, chunk_steps: int = 32) -> "Server":

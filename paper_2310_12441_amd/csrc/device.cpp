@@ -650,6 +650,17 @@ void set_schedule(mm_ctx &c, const int *ids, size_t count, int choice)
     c.dev->tuned[shape_key(c, ids, count)] = choice;
 }
 
+void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P)
+{
+    const int n = schedule_count(c, ids, count);
+    MM_REQUIRE(choice < n, "schedule index out of range");
+    Device &d = *c.dev;
+    const Sched S = choice >= 0 ? candidates(c, d, ids, count)[choice] : schedule_for(c, d, ids, count);
+    if (gw) *gw = S.gw;
+    if (cpw) *cpw = S.ks.cpw;
+    if (P) *P = (int)S.ks.P;
+}
+
 // Time every candidate schedule on this batch (one untimed run each, then the
 // blind rotation and the key switch measured separately) and remember the
 // fastest combination for the batch shape.
