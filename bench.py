@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="ciphertexts timed on the plain path")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: one per host thread)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mixed", type=int, default=2048,
+                    help="ciphertexts of the uneven-class batch (0: no mixed leg)")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -187,22 +189,50 @@ def main():
         "kernel_source_sha256_16": source_hash(),
     }
 
-    # ---- serving: Poisson arrivals of single bootstraps with mixed (t, k), keys resident
-    serving = None
-    if args.serve_requests > 0:
-        from synth import CLASS_MIX, class_mix, poisson_arrivals
-        R = args.serve_requests
-        tabs = []
-        for k, (tt, rr) in enumerate(CLASS_MIX):
-            tabs.append((ctx.table_create(tt, tt, rr, negacyclic_table(tt, tt, 100 + k)), tt, rr))
-        cls = class_mix(R, 7)
-        s_ids = np.array([tabs[k][0] for k in cls], np.int32)
-        s_ct = np.empty((R, p.n + 1), np.uint32)
+    # ---- uneven classes: one table per (t, k), classes drawn uniformly per ciphertext
+    from synth import CLASS_MIX, class_mix, poisson_arrivals
+    tabs = []
+    for k, (tt, rr) in enumerate(CLASS_MIX):
+        tabs.append((ctx.table_create(tt, tt, rr, negacyclic_table(tt, tt, 100 + k)), tt, rr))
+
+    def class_batch(count, mix_seed, enc_seed):
+        cls = class_mix(count, mix_seed)
+        c_ids = np.array([tabs[k][0] for k in cls], np.int32)
+        c_ct = np.empty((count, p.n + 1), np.uint32)
         for k, (tid_k, tt, rr) in enumerate(tabs):
             sel = np.where(cls == k)[0]
             qq = 2 * p.N * rr
-            edk = enc_draws(p.n, qq, sel.size, 200 + k)
-            s_ct[sel] = ctx.encrypt(qq, tt, messages(tt, sel.size, 300 + k), edk["a"], edk["e"])
+            edk = enc_draws(p.n, qq, sel.size, enc_seed + k)
+            c_ct[sel] = ctx.encrypt(qq, tt, messages(tt, sel.size, enc_seed + 100 + k), edk["a"], edk["e"])
+        return c_ids, c_ct
+
+    mixed = None
+    if args.mixed > 0:
+        M = args.mixed
+        x_ids, x_ct = class_batch(M, 8, 400)
+        x_in = torch.from_numpy(x_ct.view(np.int32)).cuda()
+        x_out = torch.empty_like(x_in)
+        x_sched = ctx.autotune(x_ids, x_ct)
+        x_desc = ctx.schedule_describe(x_ids)
+        ctx.bootstrap(x_ids, x_in, out=x_out)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps)
+        t3 = time.perf_counter()
+        for _ in range(reps):
+            ctx.bootstrap(x_ids, x_in, out=x_out)
+        torch.cuda.synchronize()
+        x_s = (time.perf_counter() - t3) / reps
+        rs = np.array([tabs[i][2] for i in class_mix(M, 8)])
+        mixed = {"batch": M, "classes": [list(c) for c in CLASS_MIX], "bootstraps_per_s": round(M / x_s, 1),
+                 "ms_per_batch": round(x_s * 1e3, 3), "components": int(rs.sum()),
+                 "schedule": {"index": x_sched, "group_waves": x_desc[0], "ks_cts_per_wave": x_desc[1],
+                              "ks_splits": x_desc[2]}}
+
+    # ---- serving: Poisson arrivals of single bootstraps with mixed (t, k), keys resident
+    serving = None
+    if args.serve_requests > 0:
+        R = args.serve_requests
+        s_ids, s_ct = class_batch(R, 7, 200)
         alone = None
         serving = {"rates_req_s": [], "p50_ms": [], "p99_ms": [], "completed_per_s": [], "requests_per_rate": R,
                    "classes": [list(c) for c in CLASS_MIX], "chunk_steps": 63, "hbm_budget_bytes": 4 << 30}
@@ -260,6 +290,7 @@ def main():
         "plain_equals_batched": plain_same,
         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
         "schedule": {"index": schedule, "group_waves": sched[0], "ks_cts_per_wave": sched[1], "ks_splits": sched[2]},
+        "mixed_classes": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
