@@ -52,8 +52,10 @@ typedef struct mm_ctx mm_ctx;
 typedef struct mm_server mm_server;
 
 /* Ring and gadget parameters of one key set (Alg. 1 inputs).
- * n: LWE dimension; N: ring degree, a power of two in {256, 512, 1024} for the
- * device path; Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l:
+ * n: LWE dimension; N: ring degree, a power of two in [64, 8192] (the device
+ * path takes 256 ... 8192; above 1024 one polynomial spans N / 1024 waves, and
+ * a table's r components must then satisfy r * N / 1024 <= 8, so r = 1 at
+ * N = 8192: the TFHE-shaped case of the comparison in Sec. 5); Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l:
  * the blind-rotation gadget base 2^log2_B and length, l * log2_B <= 32 and
  * log2_B <= 15; log2_Bks, l_ks: the key-switch base and length,
  * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact; ternary: 0 for

@@ -82,7 +82,7 @@ void device_init(mm_ctx &c, int id)
     d->num_cu = prop.multiProcessorCount;
     const mm_params &p = c.p;
     const uint32_t N = p.N, Q = p.Q;
-    MM_REQUIRE(N == 256 || N == 512 || N == 1024, "device path supports N in {256, 512, 1024}");
+    MM_REQUIRE(dev::device_supports_n(N), "device path supports N in {256, 512, ..., 8192}");
     d->qn = neg_inv_2_32(Q);
     // 2^64 / N mod Q, for the pointwise product of two forward NTTs
     d->c_fix = mulmod(to_mont(to_mont(1, Q), Q), c.ntt.n_inv, Q);
@@ -173,21 +173,27 @@ static void finish_out(uint32_t *host, const uint32_t *dev, size_t words, bool d
 
 // ------------------------------------------------------------------ batching
 
-// Pack ciphertexts into groups of 8 wave slots, first-fit over r descending,
-// each ciphertext's components on consecutive waves of one group.  cts[k] is
-// the task of ciphertext k with comp = 0; the result holds 8 tasks per group.
-std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw)
+// Pack ciphertexts into groups of gw waves = gw / wpp component slots (wpp
+// waves per polynomial), first-fit over r descending, each ciphertext's
+// components on consecutive slots of one group.  cts[k] is the task of
+// ciphertext k with comp = 0; the result holds gw tasks per group, the wpp
+// waves of a slot carrying the same task.
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp)
 {
+    const uint32_t slots = gw / wpp;
+    for (auto &t : cts)
+        MM_REQUIRE(t.r >= 1 && t.r <= slots,
+                   "a ciphertext's r components times N/1024 waves each must fit one workgroup of 8 waves");
     std::vector<size_t> order(cts.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cts[a].r > cts[b].r; });
     std::vector<dev::WaveTask> tasks;
-    std::vector<uint32_t> used;  // per group
+    std::vector<uint32_t> used;  // slots used per group
     size_t first_open = 0;
     for (size_t o : order) {
         const uint32_t r = cts[o].r;
         size_t g = first_open;
-        while (g < used.size() && used[g] + r > gw) g++;
+        while (g < used.size() && used[g] + r > slots) g++;
         if (g == used.size()) {
             used.push_back(0);
             dev::WaveTask idle{};
@@ -197,10 +203,10 @@ std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uin
         for (uint32_t j = 0; j < r; j++) {
             dev::WaveTask w = cts[o];
             w.comp = j;
-            tasks[g * gw + used[g] + j] = w;
+            for (uint32_t v = 0; v < wpp; v++) tasks[g * gw + (used[g] + j) * wpp + v] = w;
         }
         used[g] += r;
-        while (first_open < used.size() && used[first_open] == gw) first_open++;
+        while (first_open < used.size() && used[first_open] == slots) first_open++;
     }
     return tasks;
 }
@@ -221,7 +227,7 @@ static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, s
         w.flags = flags;
         w.acc_off = acc_off.empty() ? 0 : acc_off[k];
     }
-    return pack_tasks(cts, gw);
+    return pack_tasks(cts, gw, (uint32_t)dev::waves_per_poly(c.p.N));
 }
 
 // Valid ids; returns how many name general (two-bootstrap) tables.
@@ -337,7 +343,7 @@ static std::string shape_key(const mm_ctx &c, const int *ids, size_t count)
 static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int *ids, size_t count)
 {
     std::vector<Sched> out;
-    const bool narrow_ok = max_r(c, ids, count) <= 4;
+    const bool narrow_ok = max_r(c, ids, count) * (uint32_t)dev::waves_per_poly(c.p.N) <= 4;
     std::vector<KsSched> ks{ks_default(c, d, count)};
     const uint32_t rows = c.p.l_ks << c.p.log2_Bks;
     if (rows <= (uint32_t)dev::KS_TILED_MAX_ROWS && count >= 64)

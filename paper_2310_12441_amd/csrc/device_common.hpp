@@ -1,17 +1,19 @@
 // Device-side building blocks shared by the kernels: exact arithmetic mod Q
-// (Q odd, Q < 2^31), the wave-resident negacyclic NTT and the external
+// (Q odd, Q < 2^31), the negacyclic NTT held in registers, and the external
 // product of one RLWE pair by one bootstrapping-key row block.
 //
-// Data layout of one degree-N polynomial inside a wave (64 lanes, E = N/64
-// coefficients per lane): the NTT runs in NPH phases; in phase p lane L and
-// register k hold coefficient
+// Data layout of one degree-N polynomial: it is spread over WPP waves
+// (WPP = 1 up to N = 1024, N / 1024 above) that act as one set of LANES =
+// 64 WPP virtual lanes, each holding E = N / LANES coefficients.  The NTT runs
+// in NPH phases; in phase p virtual lane L and register k hold coefficient
 //     idx_p(L, k) = ((L >> R_p) << (R_p + LE)) | (k << R_p) | (L & (2^R_p - 1)),
-// R_p = max(0, 6 - p * LE), LE = log2 E.  Phase 0 (R = 6) is the natural layout
-// idx = 64 k + L used for coefficient-domain work (rotation, decomposition,
-// accumulation); the last phase (R = 0) is idx = E L + k, in which the NTT
-// output is consumed pointwise.  Butterflies whose two inputs differ in a
-// register bit are done in registers; between phases the wave swaps layout
-// through its own LDS slot.
+// R_p = max(0, LL - p * LE), LE = log2 E, LL = log2 LANES.  Phase 0 (R = LL)
+// is the natural layout idx = LANES k + L used for coefficient-domain work
+// (rotation, decomposition, accumulation); the last phase (R = 0) is
+// idx = E L + k, in which the NTT output is consumed pointwise.  Butterflies
+// whose two inputs differ in a register bit are done in registers; between
+// phases the lanes swap layout through an LDS slot (the wave's own when
+// WPP = 1, shared by the WPP waves otherwise, with workgroup barriers).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,21 +26,25 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 template <int N>
 struct Geo {
-    static constexpr int E = N / 64;
+    static constexpr int WPP = N > 1024 ? N / 1024 : 1;  // waves per polynomial
+    static constexpr int LANES = 64 * WPP;
+    static constexpr int LL = ilog2(LANES);
+    static constexpr int E = N / LANES;
     static constexpr int LE = ilog2(E);
     static constexpr int LOGN = ilog2(N);
-    static constexpr int NPH = 1 + (6 + LE - 1) / LE;
+    static constexpr int NPH = 1 + (LL + LE - 1) / LE;
     static constexpr int PAD = N / 16;            // one pad word per 16
     static constexpr int POLYW = N + PAD;         // words of one swizzled poly in LDS
-    static constexpr int SLOTW = 2 * POLYW;       // a wave's LDS slot: two polys
-    __host__ __device__ static constexpr int R(int p) { return 6 - p * LE < 0 ? 0 : 6 - p * LE; }
+    static constexpr int SLOTW = 2 * POLYW;       // an exchange slot: two polys
+    __host__ __device__ static constexpr int R(int p) { return LL - p * LE < 0 ? 0 : LL - p * LE; }
     // highest idx bit whose butterflies run in phase p
     __host__ __device__ static constexpr int HI(int p) { return p == 0 ? LOGN - 1 : R(p - 1) - 1; }
-    static_assert(N == 64 * E && E >= 4 && E <= 16, "device path supports N in {256, 512, 1024}");
+    static_assert(N == LANES * E && E >= 4 && E <= 16 && WPP <= 8,
+                  "device path supports N in {256, 512, ..., 8192}");
 };
 
 // LDS word address of coefficient idx: one pad word per 16 keeps all phase
-// layouts (strides 1, 4*64/E... and E) free of bank conflicts.
+// layouts (strides 1, 2^R_p and E between neighbouring lanes) free of bank conflicts.
 __device__ __forceinline__ int swz(int idx) { return idx + (idx >> 4); }
 
 template <int N>
@@ -87,19 +93,28 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Barrier between the lanes that share a polynomial: the wave itself, or the
+// whole workgroup when a polynomial spans several waves.
+template <int N>
+__device__ __forceinline__ void poly_sync()
+{
+    if constexpr (Geo<N>::WPP == 1) wave_sync();
+    else __syncthreads();
+}
+
 // Move NP polys from the layout of phase `from` to that of phase `to`
-// through the wave's LDS slot (NP <= 2).
+// through the LDS slot (NP <= 2).  L is the virtual lane.
 template <int N, int NP>
 __device__ __forceinline__ void relayout(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, int L, int from,
                                          int to)
 {
     using G = Geo<N>;
-    wave_sync();
+    poly_sync<N>();
 #pragma unroll
     for (int q = 0; q < NP; q++)
 #pragma unroll
         for (int k = 0; k < G::E; k++) slot[q * G::POLYW + swz(idx_of<N>(from, L, k))] = x[q][k];
-    wave_sync();
+    poly_sync<N>();
 #pragma unroll
     for (int q = 0; q < NP; q++)
 #pragma unroll
@@ -224,7 +239,7 @@ __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[Geo<N>::E], const u
             pd[1][k] = gadget_digit(ya[k], u, g, m.Q);
         }
         ntt_fwd<N, 2>(pd, slot, twf, L, m);
-        // lane L now holds NTT positions E L .. E L + E - 1
+        // virtual lane L now holds NTT positions E L .. E L + E - 1
         const uint32_t *kb_a = K + ((size_t)(u)*2 + 0) * N + L * E;
         const uint32_t *kb_b = K + ((size_t)(u)*2 + 1) * N + L * E;
         const uint32_t *ka_a = K + ((size_t)(g.l + u) * 2 + 0) * N + L * E;

@@ -2,13 +2,13 @@
 //
 // k_blind_rotate: the fused, persistent blind rotation (Alg. 1, first modulus
 //   switch, accumulator initialisation and the n CMux steps, then the sample
-//   extraction of entry 0).  One workgroup of 8 waves owns a "group" of up to 8
-//   ciphertext components; each wave owns one component j of one ciphertext
-//   and keeps that component's RLWE pair (a, b) in registers for all n steps.
-//   Each step the waves publish their pairs in LDS, read the pair that
-//   Phi(-a'_i) brings to their slot (an index-and-sign remap, eq. ex1:BPc),
-//   form D = Phi(-a'_i) ACC - ACC, and add D x BSK_i (the binary CMux of
-//   eq. cmux:BP) with a wave-resident NTT external product.
+//   extraction of entry 0).  One workgroup of GW waves owns a "group" of
+//   component slots: a slot is one wave up to N = 1024 and N / 1024 waves
+//   above, and holds one component j of one ciphertext, whose RLWE pair (a, b)
+//   stays in LDS for all n steps.  Each step the slots read the pair that
+//   Phi(-a'_i) brings to them (an index-and-sign remap, eq. ex1:BPc), form
+//   D = Phi(-a'_i) ACC - ACC, and add D x BSK_i (the binary CMux of
+//   eq. cmux:BP) with a register-resident NTT external product.
 // k_keyswitch / k_ks_finalize: the key switch z -> s (eq. equ-key-swi) and the
 //   final modulus switch Q -> q_out, batched over ciphertexts.
 #include <hip/hip_runtime.h>
@@ -49,20 +49,24 @@ __device__ __forceinline__ void phi_row(uint32_t c, uint32_t r, uint32_t j, uint
     e = a + (j < b ? 1u : 0u);
 }
 
-// LDS per wave: its accumulator pair (a, b) followed by two scratch polys.
+// LDS per component slot: its accumulator pair (a, b), then an exchange slot
+// of two polys for the NTT relayouts.
 template <int N>
 struct BrLds {
-    static constexpr int WAVE_WORDS = 2 * Geo<N>::POLYW + Geo<N>::SLOTW;
+    static constexpr int COMP_WORDS = 2 * Geo<N>::POLYW + Geo<N>::SLOTW;
 };
 
 template <int N, int GW, int KEYS>
 __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N>;
-    constexpr int E = G::E, P = G::POLYW;
+    constexpr int E = G::E, P = G::POLYW, WPP = G::WPP, LN = G::LANES;
+    static_assert(GW % WPP == 0, "a group holds whole component slots");
     extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
-    uint32_t *accl = lds + wave * BrLds<N>::WAVE_WORDS;  // [a | b], swizzled
+    const int wave = threadIdx.x >> 6;
+    const int cs = wave / WPP;                             // component slot
+    const int L = (wave % WPP) * 64 + (threadIdx.x & 63);  // virtual lane of the slot
+    uint32_t *accl = lds + cs * BrLds<N>::COMP_WORDS;      // [a | b], swizzled
     uint32_t *scr = accl + 2 * P;
     const ModQ m{A.Q, A.qn};
     const GadgetC g{A.log2B, A.l, A.sg, A.goff};
@@ -81,7 +85,7 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             const uint32_t *V = A.tv + T.tv_off + (size_t)src * N;
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                const uint32_t idx = 64 * k + L;
+                const uint32_t idx = LN * k + L;
                 const uint32_t i2 = (idx + 2 * N - (e % (2 * N))) % (2 * N);
                 const uint32_t v = V[i2 & (N - 1)];
                 accl[swz(idx)] = 0;
@@ -91,50 +95,56 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             const uint32_t *S = A.acc_state + T.acc_off + (size_t)T.comp * 2 * N;
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                accl[swz(64 * k + L)] = S[64 * k + L];
-                accl[P + swz(64 * k + L)] = S[N + 64 * k + L];
+                accl[swz(LN * k + L)] = S[LN * k + L];
+                accl[P + swz(LN * k + L)] = S[N + LN * k + L];
             }
         }
 
-        // D = Phi(c) ACC - ACC for this wave's component: coefficient idx of x^e v is
+        // D = Phi(c) ACC - ACC for this slot's component: coefficient idx of x^e v is
         // v[(idx - e) mod 2N], negated when that index is >= N; a negated source enters
         // D as Q - v (Q is read as 0 by the decomposition)
         auto rotated_diff = [&](uint32_t c, uint32_t (&D)[2][E]) {
             uint32_t src, e;
             phi_row(c, r, T.comp, src, e);
-            const uint32_t *sp = lds + (wave - (int)T.comp + (int)src) * BrLds<N>::WAVE_WORDS;
+            const uint32_t *sp = lds + (cs - (int)T.comp + (int)src) * BrLds<N>::COMP_WORDS;
             const uint32_t base = (uint32_t)(L + 2 * N - (e % (2 * N)));
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                const uint32_t i2 = (base + 64 * k) & (2 * N - 1);
+                const uint32_t i2 = (base + LN * k) & (2 * N - 1);
                 const int a = swz(i2 & (N - 1));
                 uint32_t va = sp[a], vb = sp[P + a];
                 if (i2 & N) {
                     va = A.Q - va;
                     vb = A.Q - vb;
                 }
-                const int o = swz(64 * k + L);
+                const int o = swz(LN * k + L);
                 D[0][k] = sub_q(va, accl[o], A.Q);
                 D[1][k] = sub_q(vb, accl[P + o], A.Q);
             }
         };
 
         // ---- the CMux steps (eq. cmux:BP): the s+ term with Phi(-a'_i), and for a
-        // ternary secret the s- term with Phi(a'_i), both from the same accumulator
+        // ternary secret the s- term with Phi(a'_i), both from the same accumulator.
+        // When a polynomial spans several waves its NTTs synchronise the whole
+        // workgroup, so every wave runs them (idle slots on zeros, results dropped).
         for (int s = 0; s < A.steps; s++) {
             const uint32_t i = T.i0 + (uint32_t)s;
             const bool active = has && i < A.n;
+            const bool run = active || WPP > 1;
             __syncthreads();  // every accumulator of the group is up to date
             uint32_t D[2][E];
             uint32_t ai = 0;
             if (active) {
                 ai = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[i], T.q_in, M));
                 rotated_diff((M - ai) % M, D);  // -a'_i mod 2Nr
+            } else if (WPP > 1) {
+#pragma unroll
+                for (int k = 0; k < E; k++) D[0][k] = D[1][k] = 0;
             }
             __syncthreads();  // every rotated read of this step is done
             uint32_t o[2][E];
-            const uint32_t *K = A.bsk + (size_t)i * KEYS * (4u * A.l * N);
-            if (active) {
+            const uint32_t *K = A.bsk + (size_t)(active ? i : 0u) * KEYS * (4u * A.l * N);
+            if (run) {
 #pragma unroll
                 for (int k = 0; k < E; k++) o[0][k] = o[1][k] = 0;
                 ext_mac<N>(D[0], D[1], K, scr, A.twf, L, m, g, o);
@@ -142,28 +152,30 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             if (KEYS == 2) {
                 if (active) rotated_diff(ai, D);  // +a'_i: no accumulator has changed yet
                 __syncthreads();                  // every s- read is done before any update
-                if (active) ext_mac<N>(D[0], D[1], K + 4u * A.l * N, scr, A.twf, L, m, g, o);
+                if (run) ext_mac<N>(D[0], D[1], K + 4u * A.l * N, scr, A.twf, L, m, g, o);
             }
-            if (active) {
+            if (run) {
                 __asm__ volatile("" ::: "memory");
                 ntt_inv<N, 2>(o, scr, A.twi, L, m);
+            }
+            if (active) {
 #pragma unroll
                 for (int k = 0; k < E; k++) {
-                    const int a = swz(64 * k + L);
+                    const int a = swz(LN * k + L);
                     accl[a] = add_q(accl[a], o[0][k], A.Q);
                     accl[P + a] = add_q(accl[P + a], o[1][k], A.Q);
                 }
             }
         }
 
-        // ---- results (each wave reads back only its own accumulator)
+        // ---- results (each slot reads back only its own accumulator)
         if (!has) continue;
         if (T.flags & TASK_STORE) {
             uint32_t *S = A.acc_state + T.acc_off + (size_t)T.comp * 2 * N;
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                S[64 * k + L] = accl[swz(64 * k + L)];
-                S[N + 64 * k + L] = accl[P + swz(64 * k + L)];
+                S[LN * k + L] = accl[swz(LN * k + L)];
+                S[N + LN * k + L] = accl[P + swz(LN * k + L)];
             }
         }
         if ((T.flags & TASK_EXTRACT) && T.comp == 0 && T.i0 + (uint32_t)A.steps >= A.n) {
@@ -171,7 +183,7 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             uint32_t *o = A.ext_out + (size_t)T.ct * (N + 1);
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                const uint32_t idx = 64 * k + L;
+                const uint32_t idx = LN * k + L;
                 const uint32_t v = accl[swz(idx)];
                 o[(N - idx) & (N - 1)] = idx ? (v ? A.Q - v : 0) : v;
             }
@@ -180,64 +192,74 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
     }
 }
 
-// One external product per wave: in/out [count][2][N].
+// One external product per polynomial slot (WPP waves): in/out [count][2][N].
+// A slot past the end computes on item 0 and stores nothing, so that every
+// wave reaches the workgroup barriers of a multi-wave NTT.
 template <int N>
-__global__ void __launch_bounds__(256) k_external_product(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+__global__ void __launch_bounds__(512) k_external_product(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                                           size_t count, const uint32_t *__restrict__ K,
                                                           const uint32_t *twf, const uint32_t *twi, uint32_t Q,
                                                           uint32_t qn, uint32_t log2B, uint32_t l, uint32_t sg)
 {
     using G = Geo<N>;
-    constexpr int E = G::E;
+    constexpr int E = G::E, LN = G::LANES;
     extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
-    const size_t c = (size_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (c >= count) return;
-    uint32_t *slot = lds + wave * G::SLOTW;
+    const int wave = threadIdx.x >> 6, item = wave / G::WPP;
+    const int L = (wave % G::WPP) * 64 + (threadIdx.x & 63);
+    const size_t c0 = (size_t)blockIdx.x * (blockDim.x / LN) + item;
+    if (G::WPP == 1 && c0 >= count) return;
+    const bool ok = c0 < count;
+    const size_t c = ok ? c0 : 0;
+    uint32_t *slot = lds + item * G::SLOTW;
     const ModQ m{Q, qn};
     const GadgetC g{log2B, l, sg, gadget_offset(log2B, l)};
     uint32_t D[2][E], o[2][E];
 #pragma unroll
     for (int k = 0; k < E; k++) {
-        D[0][k] = in[c * 2 * N + 64 * k + L];
-        D[1][k] = in[c * 2 * N + N + 64 * k + L];
+        D[0][k] = in[c * 2 * N + LN * k + L];
+        D[1][k] = in[c * 2 * N + N + LN * k + L];
     }
     external_product<N>(D[0], D[1], K, slot, twf, twi, L, m, g, o);
+    if (!ok) return;
 #pragma unroll
     for (int k = 0; k < E; k++) {
-        out[c * 2 * N + 64 * k + L] = o[0][k];
-        out[c * 2 * N + N + 64 * k + L] = o[1][k];
+        out[c * 2 * N + LN * k + L] = o[0][k];
+        out[c * 2 * N + N + LN * k + L] = o[1][k];
     }
 }
 
-// a * b through the wave NTT: [count][N] each.  c_fix = 2^64 / N mod Q
-// undoes two Montgomery factors and the missing 1/N.
+// a * b through the NTT, one product per polynomial slot: [count][N] each.
+// c_fix = 2^64 / N mod Q undoes two Montgomery factors and the missing 1/N.
 template <int N>
-__global__ void __launch_bounds__(256) k_negacyclic_mul(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+__global__ void __launch_bounds__(512) k_negacyclic_mul(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
                                                         uint32_t *__restrict__ out, size_t count, const uint32_t *twf,
                                                         const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t c_fix)
 {
     using G = Geo<N>;
-    constexpr int E = G::E;
+    constexpr int E = G::E, LN = G::LANES;
     extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
-    const size_t c = (size_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (c >= count) return;
-    uint32_t *slot = lds + wave * G::SLOTW;
+    const int wave = threadIdx.x >> 6, item = wave / G::WPP;
+    const int L = (wave % G::WPP) * 64 + (threadIdx.x & 63);
+    const size_t c0 = (size_t)blockIdx.x * (blockDim.x / LN) + item;
+    if (G::WPP == 1 && c0 >= count) return;
+    const bool ok = c0 < count;
+    const size_t c = ok ? c0 : 0;
+    uint32_t *slot = lds + item * G::SLOTW;
     const ModQ m{Q, qn};
     uint32_t x[2][E];
 #pragma unroll
     for (int k = 0; k < E; k++) {
-        x[0][k] = a[c * N + 64 * k + L];
-        x[1][k] = b[c * N + 64 * k + L];
+        x[0][k] = a[c * N + LN * k + L];
+        x[1][k] = b[c * N + LN * k + L];
     }
     ntt_fwd<N, 2>(x, slot, twf, L, m);
     uint32_t y[1][E];
 #pragma unroll
     for (int k = 0; k < E; k++) y[0][k] = mont_mul(mont_mul(x[0][k], x[1][k], m), c_fix, m);
     ntt_inv<N, 1>(y, slot, twi, L, m);
+    if (!ok) return;
 #pragma unroll
-    for (int k = 0; k < E; k++) out[c * N + 64 * k + L] = y[0][k];
+    for (int k = 0; k < E; k++) out[c * N + LN * k + L] = y[0][k];
 }
 
 // Sample extraction of [count][2][N] pairs.
@@ -452,37 +474,68 @@ template <int N, int GW, int KEYS>
 static hipError_t br_attr_n()
 {
     return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)((size_t)GW * BrLds<N>::WAVE_WORDS * sizeof(uint32_t)));
+                               (int)br_lds_bytes(N, GW));
 }
 
 template <int N>
 static hipError_t br_attr_all()
 {
     hipError_t e = br_attr_n<N, 8, 1>();
-    if (e == hipSuccess) e = br_attr_n<N, 4, 1>();
     if (e == hipSuccess) e = br_attr_n<N, 8, 2>();
-    if (e == hipSuccess) e = br_attr_n<N, 4, 2>();
+    if constexpr (Geo<N>::WPP <= 4) {
+        if (e == hipSuccess) e = br_attr_n<N, 4, 1>();
+        if (e == hipSuccess) e = br_attr_n<N, 4, 2>();
+    }
+    return e;
+}
+
+template <int N>
+static hipError_t slot_attr_n()
+{
+    const int lds = (int)((512 / Geo<N>::LANES) * Geo<N>::SLOTW * sizeof(uint32_t));
+    hipError_t e = hipFuncSetAttribute((const void *)k_external_product<N>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_negacyclic_mul<N>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return e;
+}
+
+template <int N>
+static hipError_t attr_n()
+{
+    hipError_t e = br_attr_all<N>();
+    if (e == hipSuccess) e = slot_attr_n<N>();
     return e;
 }
 
 hipError_t init_kernel_attributes()
 {
-    hipError_t e = br_attr_all<256>();
-    if (e == hipSuccess) e = br_attr_all<512>();
-    if (e == hipSuccess) e = br_attr_all<1024>();
+    hipError_t e = attr_n<256>();
+    if (e == hipSuccess) e = attr_n<512>();
+    if (e == hipSuccess) e = attr_n<1024>();
+    if (e == hipSuccess) e = attr_n<2048>();
+    if (e == hipSuccess) e = attr_n<4096>();
+    if (e == hipSuccess) e = attr_n<8192>();
     return e;
 }
+
+bool device_supports_n(uint32_t N)
+{
+    return N == 256 || N == 512 || N == 1024 || N == 2048 || N == 4096 || N == 8192;
+}
+
+int waves_per_poly(uint32_t N) { return N > 1024 ? (int)(N / 1024) : 1; }
 
 template <int N, int KEYS>
 static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st)
 {
-    if (gw == 4) {
-        const size_t lds = (size_t)4 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
-        hipLaunchKernelGGL((k_blind_rotate<N, 4, KEYS>), dim3(grid), dim3(256), lds, st, A);
-    } else {
-        const size_t lds = (size_t)8 * BrLds<N>::WAVE_WORDS * sizeof(uint32_t);
-        hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS>), dim3(grid), dim3(512), lds, st, A);
+    if constexpr (Geo<N>::WPP <= 4) {
+        if (gw == 4) {
+            hipLaunchKernelGGL((k_blind_rotate<N, 4, KEYS>), dim3(grid), dim3(256), br_lds_bytes(N, 4), st, A);
+            return;
+        }
     }
+    hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS>), dim3(grid), dim3(512), br_lds_bytes(N, 8), st, A);
 }
 
 template <int N>
@@ -498,17 +551,40 @@ void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStrea
     case 256: launch_br_n<256>(A, gw, grid, st); break;
     case 512: launch_br_n<512>(A, gw, grid, st); break;
     case 1024: launch_br_n<1024>(A, gw, grid, st); break;
+    case 2048: launch_br_n<2048>(A, gw, grid, st); break;
+    case 4096: launch_br_n<4096>(A, gw, grid, st); break;
+    case 8192: launch_br_n<8192>(A, gw, grid, st); break;
     default: break;
     }
+}
+
+template <int N>
+static size_t br_lds_n(int gw)
+{
+    return (size_t)(gw / Geo<N>::WPP) * BrLds<N>::COMP_WORDS * sizeof(uint32_t);
 }
 
 size_t br_lds_bytes(uint32_t N, int gw)
 {
     switch (N) {
-    case 256: return (size_t)gw * BrLds<256>::WAVE_WORDS * 4;
-    case 512: return (size_t)gw * BrLds<512>::WAVE_WORDS * 4;
-    default: return (size_t)gw * BrLds<1024>::WAVE_WORDS * 4;
+    case 256: return br_lds_n<256>(gw);
+    case 512: return br_lds_n<512>(gw);
+    case 1024: return br_lds_n<1024>(gw);
+    case 2048: return br_lds_n<2048>(gw);
+    case 4096: return br_lds_n<4096>(gw);
+    default: return br_lds_n<8192>(gw);
     }
+}
+
+// Blocks of 4 waves (8 when one polynomial spans 8 waves); one item per slot.
+template <int N>
+static void slot_launch_shape(size_t count, dim3 &grid, dim3 &block, size_t &lds)
+{
+    const int threads = std::max(256, Geo<N>::LANES);
+    const int items = threads / Geo<N>::LANES;
+    grid = dim3((unsigned)((count + items - 1) / items));
+    block = dim3(threads);
+    lds = (size_t)items * Geo<N>::SLOTW * sizeof(uint32_t);
 }
 
 template <int N>
@@ -516,10 +592,10 @@ static void launch_ep_n(const uint32_t *in, uint32_t *out, size_t count, const u
                         const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B, uint32_t l, uint32_t sg,
                         hipStream_t st)
 {
-    const size_t lds = (size_t)4 * Geo<N>::SLOTW * sizeof(uint32_t);
-    const int grid = (int)((count + 3) / 4);
-    hipLaunchKernelGGL(k_external_product<N>, dim3(grid), dim3(256), lds, st, in, out, count, K, twf, twi, Q, qn,
-                       log2B, l, sg);
+    dim3 grid, block;
+    size_t lds;
+    slot_launch_shape<N>(count, grid, block, lds);
+    hipLaunchKernelGGL(k_external_product<N>, grid, block, lds, st, in, out, count, K, twf, twi, Q, qn, log2B, l, sg);
 }
 
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
@@ -530,6 +606,9 @@ void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size
     case 256: launch_ep_n<256>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
     case 512: launch_ep_n<512>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
     case 1024: launch_ep_n<1024>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
+    case 2048: launch_ep_n<2048>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
+    case 4096: launch_ep_n<4096>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
+    case 8192: launch_ep_n<8192>(in, out, count, K, twf, twi, Q, qn, log2B, l, sg, st); break;
     default: break;
     }
 }
@@ -538,9 +617,10 @@ template <int N>
 static void launch_pm_n(const uint32_t *a, const uint32_t *b, uint32_t *out, size_t count, const uint32_t *twf,
                         const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t c_fix, hipStream_t st)
 {
-    const size_t lds = (size_t)4 * Geo<N>::SLOTW * sizeof(uint32_t);
-    const int grid = (int)((count + 3) / 4);
-    hipLaunchKernelGGL(k_negacyclic_mul<N>, dim3(grid), dim3(256), lds, st, a, b, out, count, twf, twi, Q, qn, c_fix);
+    dim3 grid, block;
+    size_t lds;
+    slot_launch_shape<N>(count, grid, block, lds);
+    hipLaunchKernelGGL(k_negacyclic_mul<N>, grid, block, lds, st, a, b, out, count, twf, twi, Q, qn, c_fix);
 }
 
 void launch_negacyclic_mul(uint32_t N, const uint32_t *a, const uint32_t *b, uint32_t *out, size_t count,
@@ -551,6 +631,9 @@ void launch_negacyclic_mul(uint32_t N, const uint32_t *a, const uint32_t *b, uin
     case 256: launch_pm_n<256>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
     case 512: launch_pm_n<512>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
     case 1024: launch_pm_n<1024>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
+    case 2048: launch_pm_n<2048>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
+    case 4096: launch_pm_n<4096>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
+    case 8192: launch_pm_n<8192>(a, b, out, count, twf, twi, Q, qn, c_fix, st); break;
     default: break;
     }
 }

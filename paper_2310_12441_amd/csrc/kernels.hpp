@@ -15,8 +15,9 @@ enum : uint32_t {
 };
 
 // What one wave of a blind-rotation workgroup does.  A group is GW (8 or 4)
-// consecutive WaveTasks; the components 0..r-1 of a ciphertext sit on
-// consecutive waves of one group.
+// consecutive WaveTasks.  A component slot is WPP consecutive waves (1 up to
+// N = 1024, N / 1024 above) holding the same task; the components 0..r-1 of a
+// ciphertext sit on consecutive slots of one group.
 struct WaveTask {
     int32_t ct;        // ciphertext index, -1 for an idle wave
     uint32_t comp;     // component j
@@ -57,6 +58,8 @@ struct KsArgs {
 };
 
 hipError_t init_kernel_attributes();
+bool device_supports_n(uint32_t N);  // N in {256, ..., 8192}
+int waves_per_poly(uint32_t N);
 void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, size_t count, uint32_t W,
                         const uint32_t *qs, hipStream_t st);
 void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,

@@ -231,8 +231,9 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
 {
     const size_t W = c->p.n + 1;
     std::lock_guard<std::mutex> g(mu);
-    if (table < 0 || (size_t)table >= c->tables.size() || c->tables[table].g_id >= 0) {
-        *rc = MM_EINVAL;  // unknown table, or a general table (two bootstraps; not served)
+    if (table < 0 || (size_t)table >= c->tables.size() || c->tables[table].g_id >= 0 ||
+        c->tables[table].r * (uint32_t)dev::waves_per_poly(c->p.N) > 8) {
+        *rc = MM_EINVAL;  // unknown table, a general table (two bootstraps; not served), or too wide a group
         return 0;
     }
     if (pending.size() >= pending_cap || stop) {
@@ -323,7 +324,7 @@ void Server::launch(Part &p)
         w.flags = (a.step == 0 ? dev::TASK_INIT : 0u) | dev::TASK_STORE | dev::TASK_EXTRACT;
         w.acc_off = (uint64_t)a.unit * 2 * N;
     }
-    auto tasks = pack_tasks(cts, 8);
+    auto tasks = pack_tasks(cts, 8, (uint32_t)dev::waves_per_poly(c->p.N));
     p.tasks.reserve(tasks.size());
     std::memcpy(p.tasks.h, tasks.data(), tasks.size() * sizeof(dev::WaveTask));
     SRV_HIP(hipMemcpyAsync(p.tasks.d, p.tasks.h, tasks.size() * sizeof(dev::WaveTask), hipMemcpyHostToDevice, p.st));

@@ -67,9 +67,12 @@ class Params:
 
 # Named workloads.  "tiny": n=64, N=256, k=2, t=16, base 2^8 x 3.
 # "paper_shaped": n=630, N=1024, k=4, t=2^12, base 2^7 x 4, key switch 2^4 x 8.
+# "tfhe_shaped": the same t = 2^12 by one ring of degree N k = 4096 (r = 1),
+# the TFHE side of the comparison in Sec. 5.
 PRESETS = {
     "tiny": dict(params=Params(n=64, N=256, log2_B=8, l=3), t=16, t_out=16, r=2),
     "paper_shaped": dict(params=Params(n=630, N=1024, log2_B=7, l=4), t=4096, t_out=4096, r=4),
+    "tfhe_shaped": dict(params=Params(n=630, N=4096, log2_B=7, l=4), t=4096, t_out=4096, r=1),
 }
 
 # (t, r) classes of the uneven batch and of the serving trace: q = 2Nr each.

@@ -125,3 +125,26 @@ def test_ternary_keygen_and_encryption_match_oracle():
     ct = ctx.encrypt(q, t, m, ed["a"], ed["e"])
     np.testing.assert_array_equal(ct, oracle.encrypt(p.n, q, t, dr["s"], m, ed["a"], ed["e"]))
     np.testing.assert_array_equal(ctx.decrypt(q, t, ct), m)
+
+
+@pytest.mark.parametrize("N", [2048, 8192])
+def test_keygen_and_test_vector_match_oracle_large_ring(N):
+    """Rings above 1024 (the TFHE-shaped comparison point): keys and an r = 1 test vector."""
+    b = _binding()
+    p = Params(n=6, N=N, log2_B=7, l=4)
+    dr = key_draws(p, 21)
+    ctx = b.Context(p, dr)
+    np.testing.assert_array_equal(ctx.export_bsk(), oracle.keygen_bsk(p, dr))
+    np.testing.assert_array_equal(ctx.export_ksk(), oracle.keygen_ksk(p, dr))
+    f = negacyclic_table(4096, 4096, 22)
+    tid = ctx.table_create(4096, 4096, 1, f)
+    np.testing.assert_array_equal(ctx.table_export(tid), oracle.test_vector(N, 1, p.Q, 4096, 4096, f))
+
+
+def test_ring_degree_limits():
+    b = _binding()
+    for N in (32, 16384):
+        p = Params(n=4, N=N)
+        with pytest.raises(b.MMError) as e:
+            b.Context(p, key_draws(p, 1))
+        assert e.value.code == b.MM_EINVAL
