@@ -83,6 +83,10 @@ def bsk_bytes(n, N, l):
     return n * 2 * l * 2 * N * 4
 
 
+def ksk_bytes(n, N, p):
+    return N * p.l_ks * p.B_ks * (n + 1) * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +98,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", type=int, default=2048,
                     help="ciphertexts of the uneven-class batch (0: no mixed leg)")
+    ap.add_argument("--compare", type=int, default=4096,
+                    help="batch of the MMPM vs TFHE-shaped comparison per class (0: no comparison leg)")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -228,6 +234,51 @@ def main():
                  "schedule": {"index": x_sched, "group_waves": x_desc[0], "ks_cts_per_wave": x_desc[1],
                               "ks_splits": x_desc[2]}}
 
+    # ---- Sec. 5 comparison: each class (t, k) by MMPM (N = 1024, r = k) and by one
+    # ring of degree N k (r = 1, TFHE-shaped), same n, gadget and key switch
+    comparison = None
+    if args.compare > 0:
+        C = args.compare
+        comparison = []
+
+        def timed_batch(cx, tid_c, t_c, r_c, N_c, seed):
+            qq = 2 * N_c * r_c
+            edc = enc_draws(p.n, qq, C, seed)
+            cts = cx.encrypt(qq, t_c, messages(t_c, C, seed + 1), edc["a"], edc["e"])
+            ids_c = np.full(C, tid_c, np.int32)
+            din = torch.from_numpy(cts.view(np.int32)).cuda()
+            dout = torch.empty_like(din)
+            cx.autotune(ids_c, cts)
+            cx.bootstrap(ids_c, din, out=dout)
+            torch.cuda.synchronize()
+            reps = max(1, min(args.steps, 3))
+            tt0 = time.perf_counter()
+            for _ in range(reps):
+                cx.bootstrap(ids_c, din, out=dout)
+            torch.cuda.synchronize()
+            return C * reps / (time.perf_counter() - tt0)
+
+        for k, (tt, rr) in enumerate(CLASS_MIX):
+            row = {"t": tt, "k": rr}
+            row["mmpm"] = {"N": p.N, "r": rr, "bootstraps_per_s": round(timed_batch(ctx, tabs[k][0], tt, rr, p.N,
+                                                                                    700 + k), 1),
+                           "bsk_bytes": bsk_bytes(p.n, p.N, p.l), "ksk_bytes": ksk_bytes(p.n, p.N, p)}
+            if rr == 1:
+                row["tfhe"] = dict(row["mmpm"])  # the same ring: r = 1 at N = 1024
+            else:
+                from dataclasses import replace
+                pt = replace(p, N=p.N * rr)
+                cx = binding.Context(pt, key_draws(pt, seeds["keys"]))
+                cx.device_init(0)
+                tid_t = cx.table_create(tt, tt, 1, negacyclic_table(tt, tt, 100 + k))
+                row["tfhe"] = {"N": pt.N, "r": 1, "bootstraps_per_s": round(timed_batch(cx, tid_t, tt, 1, pt.N,
+                                                                                         700 + k), 1),
+                               "bsk_bytes": bsk_bytes(pt.n, pt.N, pt.l), "ksk_bytes": ksk_bytes(pt.n, pt.N, pt)}
+                cx.close()
+                del cx
+            row["mmpm_over_tfhe_speed"] = round(row["mmpm"]["bootstraps_per_s"] / row["tfhe"]["bootstraps_per_s"], 3)
+            comparison.append(row)
+
     # ---- serving: Poisson arrivals of single bootstraps with mixed (t, k), keys resident
     serving = None
     if args.serve_requests > 0:
@@ -291,6 +342,7 @@ def main():
         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
         "schedule": {"index": schedule, "group_waves": sched[0], "ks_cts_per_wave": sched[1], "ks_splits": sched[2]},
         "mixed_classes": mixed,
+        "mmpm_vs_tfhe_shaped": comparison,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
