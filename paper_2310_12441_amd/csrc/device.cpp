@@ -102,6 +102,37 @@ void device_init(mm_ctx &c, int id)
         c.ntt.forward(dst);
         for (uint32_t k = 0; k < N; k++) dst[k] = mulmod(dst[k], scale, Q);
     });
+    // Digit-offset correction per coordinate i: the blind rotation feeds the
+    // gadget digits shifted by +B/2 (non-negative, one bit-field extract each),
+    // i.e. each digit polynomial gains (B/2)(1 + x + ... + x^(N-1)); in the NTT
+    // domain that adds (B/2) NTT(1 + ... + x^(N-1)) sum_{key,row} K/N to each
+    // output part, and the accumulator starts from minus that sum.
+    const uint32_t K = c.keys, rows = 2 * p.l;
+    std::vector<uint32_t> corr((size_t)p.n * 2 * N);
+    const uint32_t inv_r = [&] {  // 2^-32 mod Q
+        uint64_t x = to_mont(1, Q), e = Q - 2, r = 1;
+        while (e) {
+            if (e & 1) r = mulmod((uint32_t)r, (uint32_t)x, Q);
+            x = mulmod((uint32_t)x, (uint32_t)x, Q);
+            e >>= 1;
+        }
+        return (uint32_t)r;
+    }();
+    const uint32_t half_b = mulmod(1u << (p.log2_B - 1), inv_r, Q);
+    std::vector<uint32_t> ones(N, 1u);
+    c.ntt.forward(ones.data());
+    parallel_for((int64_t)p.n * 2, [&](int64_t ip) {
+        const size_t i = (size_t)ip / 2, part = (size_t)ip % 2;
+        uint32_t *dst = &corr[(i * 2 + part) * N];
+        for (uint32_t k = 0; k < N; k++) {
+            uint64_t sum = 0;
+            for (uint32_t key = 0; key < K; key++)
+                for (uint32_t row = 0; row < rows; row++)
+                    sum += kb[((((size_t)i * K + key) * rows + row) * 2 + part) * N + k];
+            const uint32_t cval = mulmod(mulmod((uint32_t)(sum % Q), half_b, Q), ones[k], Q);
+            dst[k] = cval ? Q - cval : 0;
+        }
+    });
     auto upload = [&](uint32_t **dst, const uint32_t *src, size_t words) {
         if (hipMalloc((void **)dst, words * 4) != hipSuccess) {
             *dst = nullptr;
@@ -112,6 +143,7 @@ void device_init(mm_ctx &c, int id)
     upload(&d->twf, twf.data(), N);
     upload(&d->twi, twi.data(), N);
     upload(&d->bsk, kb.data(), kb.size());
+    upload(&d->bsk_corr, corr.data(), corr.size());
     upload(&d->ksk, c.ksk.data(), c.ksk.size());
     HIPC(dev::init_kernel_attributes());
     HIPC(hipStreamCreateWithFlags(&d->own, hipStreamNonBlocking));
@@ -264,9 +296,10 @@ dev::BrArgs br_args(const mm_ctx &c, const Device &d)
     A.l = c.p.l;
     A.sg = c.sg;
     A.keys = c.keys;
-    A.goff = 0;
-    for (uint32_t u = 0; u + 1 < c.p.l; u++) A.goff += (1u << (c.p.log2_B - 1)) << (u * c.p.log2_B);
+    A.goff = 0;  // (B/2)(1 + B + ... + B^(l-1)): every digit becomes a non-negative bit field
+    for (uint32_t u = 0; u < c.p.l; u++) A.goff += (1u << (c.p.log2_B - 1)) << (u * c.p.log2_B);
     A.bsk = d.bsk;
+    A.bsk_corr = d.bsk_corr;
     A.twf = d.twf;
     A.twi = d.twi;
     A.tv = d.tv;

@@ -212,31 +212,54 @@ __device__ __forceinline__ uint32_t gadget_digit(int32_t y, uint32_t u, const Ga
     return min(v, v + Q);  // v < 0 as a signed value -> v + Q
 }
 
+// Bit field u of y'' = round(centred(x) / 2^sg) + (B/2)(1 + B + ... + B^(l-1)):
+// the balanced digit u plus B/2, in [0, B) below the top and in [0, B] at the
+// top (which keeps the final carry), so one extract per digit and no sign fix.
+__device__ __forceinline__ uint32_t gadget_field_start(uint32_t x, uint32_t off_all, const GadgetC &g, uint32_t Q)
+{
+    int32_t xc = (x > (Q - 1) / 2) ? (int32_t)(x - Q) : (int32_t)x;
+    if (g.sg) xc = (xc + (1 << (g.sg - 1))) >> g.sg;
+    return (uint32_t)xc + off_all;
+}
+
 // out += g^{-1}(Da, Db) x K in the NTT domain for one RLWE pair in phase-0
 // layout, K the RGSW key block [2l][2][N] in the NTT domain (Montgomery form,
 // 1/N folded in): digits of b meet rows u < l, digits of a meet rows l + u
-// (eq. def:gsw).  out stays in the last phase's layout.
-template <int N>
+// (eq. def:gsw).  out stays in the last phase's layout.  With OFF the digits
+// enter shifted by +B/2 (g.off then holds (B/2)(1 + ... + B^(l-1))) and the
+// caller starts out from minus (B/2) sum_rows K.
+template <int N, bool OFF = false>
 __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[Geo<N>::E], const uint32_t (&Db)[Geo<N>::E],
                                         const uint32_t *__restrict__ K, uint32_t *slot, const uint32_t *twf, int L,
                                         const ModQ &m, const GadgetC &g, uint32_t (&out)[2][Geo<N>::E])
 {
     using G = Geo<N>;
     constexpr int E = G::E;
-    int32_t ya[E], yb[E];
+    uint32_t ya[E], yb[E];
 #pragma unroll
     for (int k = 0; k < E; k++) {
-        ya[k] = gadget_start(Da[k], g, m.Q);
-        yb[k] = gadget_start(Db[k], g, m.Q);
+        if constexpr (OFF) {
+            ya[k] = gadget_field_start(Da[k], g.off, g, m.Q);
+            yb[k] = gadget_field_start(Db[k], g.off, g, m.Q);
+        } else {
+            ya[k] = (uint32_t)gadget_start(Da[k], g, m.Q);
+            yb[k] = (uint32_t)gadget_start(Db[k], g, m.Q);
+        }
     }
     for (uint32_t u = 0; u < g.l; u++) {
         // keep twiddle and key loads inside the iteration (register pressure)
         __asm__ volatile("" ::: "memory");
         uint32_t pd[2][E];
+        const uint32_t sh = u * g.log2B, wd = g.log2B + (u + 1 == g.l ? 1u : 0u);
 #pragma unroll
         for (int k = 0; k < E; k++) {
-            pd[0][k] = gadget_digit(yb[k], u, g, m.Q);
-            pd[1][k] = gadget_digit(ya[k], u, g, m.Q);
+            if constexpr (OFF) {
+                pd[0][k] = __builtin_amdgcn_ubfe(yb[k], sh, wd);
+                pd[1][k] = __builtin_amdgcn_ubfe(ya[k], sh, wd);
+            } else {
+                pd[0][k] = gadget_digit((int32_t)yb[k], u, g, m.Q);
+                pd[1][k] = gadget_digit((int32_t)ya[k], u, g, m.Q);
+            }
         }
         ntt_fwd<N, 2>(pd, slot, twf, L, m);
         // virtual lane L now holds NTT positions E L .. E L + E - 1

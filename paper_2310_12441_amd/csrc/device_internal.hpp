@@ -36,7 +36,7 @@ struct PinBuf {
 struct Device {
     int id = -1, num_cu = 0;
     uint32_t qn = 0, c_fix = 0;
-    uint32_t *bsk = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
+    uint32_t *bsk = nullptr, *bsk_corr = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
     size_t tv_words = 0, tables_uploaded = 0;
     DevBuf ws[WS_COUNT];
     PinBuf pin[2];
@@ -63,7 +63,7 @@ struct Device {
             if (b.p) hipHostFree(b.p);
             if (b.ev) hipEventDestroy(b.ev);
         }
-        for (void *p : {(void *)bsk, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
+        for (void *p : {(void *)bsk, (void *)bsk_corr, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
             if (p) hipFree(p);
         for (auto &e : tev)
             if (e) hipEventDestroy(e);

@@ -49,25 +49,29 @@ __device__ __forceinline__ void phi_row(uint32_t c, uint32_t r, uint32_t j, uint
     e = a + (j < b ? 1u : 0u);
 }
 
-// LDS per component slot: its accumulator pair (a, b), then an exchange slot
-// of two polys for the NTT relayouts.
+// LDS per component slot: two accumulator buffers, each a swizzled pair (a, b).
+// During a step one holds the current ACC (read by the rotations of every slot
+// of the ciphertext) and the other serves the slot's NTT relayouts, then
+// receives the updated ACC; the roles swap every step.
 template <int N>
 struct BrLds {
-    static constexpr int COMP_WORDS = 2 * Geo<N>::POLYW + Geo<N>::SLOTW;
+    static constexpr int BUF_WORDS = 2 * Geo<N>::POLYW;
+    static constexpr int COMP_WORDS = 2 * BUF_WORDS;
+    static_assert(BUF_WORDS == Geo<N>::SLOTW, "an accumulator buffer doubles as the exchange slot");
 };
 
 template <int N, int GW, int KEYS>
 __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N>;
+    using LD = BrLds<N>;
     constexpr int E = G::E, P = G::POLYW, WPP = G::WPP, LN = G::LANES;
     static_assert(GW % WPP == 0, "a group holds whole component slots");
     extern __shared__ uint32_t lds[];
     const int wave = threadIdx.x >> 6;
     const int cs = wave / WPP;                             // component slot
     const int L = (wave % WPP) * 64 + (threadIdx.x & 63);  // virtual lane of the slot
-    uint32_t *accl = lds + cs * BrLds<N>::COMP_WORDS;      // [a | b], swizzled
-    uint32_t *scr = accl + 2 * P;
+    uint32_t *const base = lds + cs * LD::COMP_WORDS;
     const ModQ m{A.Q, A.qn};
     const GadgetC g{A.log2B, A.l, A.sg, A.goff};
 
@@ -76,8 +80,10 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
         const bool has = T.ct >= 0;
         const uint32_t r = has ? T.r : 1u, M = 2u * N * r;
         const uint32_t *ct = A.ct_in + (size_t)(has ? T.ct : 0) * A.ct_stride;
+        __syncthreads();  // the previous group's last rotated reads are done
+        int cur = 0;      // buffer holding the current accumulator
 
-        // ---- accumulator: Phi(b') (0, V) or the stored state, into LDS
+        // ---- accumulator: Phi(b') (0, V) or the stored state, into buffer 0
         if (has && (T.flags & TASK_INIT)) {
             const uint32_t bq = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[A.n], T.q_in, M));
             uint32_t src, e;
@@ -88,29 +94,29 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
                 const uint32_t idx = LN * k + L;
                 const uint32_t i2 = (idx + 2 * N - (e % (2 * N))) % (2 * N);
                 const uint32_t v = V[i2 & (N - 1)];
-                accl[swz(idx)] = 0;
-                accl[P + swz(idx)] = (i2 >= N) ? (v ? A.Q - v : 0) : v;
+                base[swz(idx)] = 0;
+                base[P + swz(idx)] = (i2 >= N) ? (v ? A.Q - v : 0) : v;
             }
         } else if (has) {
             const uint32_t *S = A.acc_state + T.acc_off + (size_t)T.comp * 2 * N;
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                accl[swz(LN * k + L)] = S[LN * k + L];
-                accl[P + swz(LN * k + L)] = S[N + LN * k + L];
+                base[swz(LN * k + L)] = S[LN * k + L];
+                base[P + swz(LN * k + L)] = S[N + LN * k + L];
             }
         }
 
         // D = Phi(c) ACC - ACC for this slot's component: coefficient idx of x^e v is
         // v[(idx - e) mod 2N], negated when that index is >= N; a negated source enters
         // D as Q - v (Q is read as 0 by the decomposition)
-        auto rotated_diff = [&](uint32_t c, uint32_t (&D)[2][E]) {
+        auto rotated_diff = [&](uint32_t c, const uint32_t *accl, uint32_t(&D)[2][E]) {
             uint32_t src, e;
             phi_row(c, r, T.comp, src, e);
-            const uint32_t *sp = lds + (cs - (int)T.comp + (int)src) * BrLds<N>::COMP_WORDS;
-            const uint32_t base = (uint32_t)(L + 2 * N - (e % (2 * N)));
+            const uint32_t *sp = accl + ((int)src - (int)T.comp) * LD::COMP_WORDS;
+            const uint32_t rb = (uint32_t)(L + 2 * N - (e % (2 * N)));
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                const uint32_t i2 = (base + LN * k) & (2 * N - 1);
+                const uint32_t i2 = (rb + LN * k) & (2 * N - 1);
                 const int a = swz(i2 & (N - 1));
                 uint32_t va = sp[a], vb = sp[P + a];
                 if (i2 & N) {
@@ -124,52 +130,69 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
         };
 
         // ---- the CMux steps (eq. cmux:BP): the s+ term with Phi(-a'_i), and for a
-        // ternary secret the s- term with Phi(a'_i), both from the same accumulator.
+        // ternary secret the s- term with Phi(a'_i), both read from the current buffer,
+        // which no slot writes during the step, so one barrier per step suffices.
         // When a polynomial spans several waves its NTTs synchronise the whole
         // workgroup, so every wave runs them (idle slots on zeros, results dropped).
         for (int s = 0; s < A.steps; s++) {
             const uint32_t i = T.i0 + (uint32_t)s;
             const bool active = has && i < A.n;
             const bool run = active || WPP > 1;
-            __syncthreads();  // every accumulator of the group is up to date
+            uint32_t *const accl = base + cur * LD::BUF_WORDS;        // current ACC
+            uint32_t *const nxt = base + (cur ^ 1) * LD::BUF_WORDS;   // exchange slot, then next ACC
+            __syncthreads();  // every current accumulator is written
             uint32_t D[2][E];
             uint32_t ai = 0;
             if (active) {
                 ai = __builtin_amdgcn_readfirstlane(modswitch_dev(ct[i], T.q_in, M));
-                rotated_diff((M - ai) % M, D);  // -a'_i mod 2Nr
+                rotated_diff((M - ai) % M, accl, D);  // -a'_i mod 2Nr
             } else if (WPP > 1) {
 #pragma unroll
                 for (int k = 0; k < E; k++) D[0][k] = D[1][k] = 0;
             }
-            __syncthreads();  // every rotated read of this step is done
             uint32_t o[2][E];
-            const uint32_t *K = A.bsk + (size_t)(active ? i : 0u) * KEYS * (4u * A.l * N);
+            const uint32_t ik = active ? i : 0u;
+            const uint32_t *K = A.bsk + (size_t)ik * KEYS * (4u * A.l * N);
             if (run) {
+                // start from the digit-offset correction of coordinate i
+                const uint32_t *C0 = A.bsk_corr + (size_t)ik * 2 * N + L * E;
 #pragma unroll
-                for (int k = 0; k < E; k++) o[0][k] = o[1][k] = 0;
-                ext_mac<N>(D[0], D[1], K, scr, A.twf, L, m, g, o);
+                for (int k = 0; k < E; k++) {
+                    o[0][k] = C0[k];
+                    o[1][k] = C0[N + k];
+                }
+                ext_mac<N, true>(D[0], D[1], K, nxt, A.twf, L, m, g, o);
             }
             if (KEYS == 2) {
-                if (active) rotated_diff(ai, D);  // +a'_i: no accumulator has changed yet
-                __syncthreads();                  // every s- read is done before any update
-                if (run) ext_mac<N>(D[0], D[1], K + 4u * A.l * N, scr, A.twf, L, m, g, o);
+                if (active) rotated_diff(ai, accl, D);  // +a'_i from the same accumulator
+                if (run) ext_mac<N, true>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o);
             }
             if (run) {
                 __asm__ volatile("" ::: "memory");
-                ntt_inv<N, 2>(o, scr, A.twi, L, m);
+                ntt_inv<N, 2>(o, nxt, A.twi, L, m);
             }
+            if (WPP > 1) __syncthreads();  // every lane of the slot has left the exchange slot
             if (active) {
 #pragma unroll
                 for (int k = 0; k < E; k++) {
                     const int a = swz(LN * k + L);
-                    accl[a] = add_q(accl[a], o[0][k], A.Q);
-                    accl[P + a] = add_q(accl[P + a], o[1][k], A.Q);
+                    nxt[a] = add_q(accl[a], o[0][k], A.Q);
+                    nxt[P + a] = add_q(accl[P + a], o[1][k], A.Q);
+                }
+            } else if (has) {
+#pragma unroll
+                for (int k = 0; k < E; k++) {  // past step n: carry the accumulator over
+                    const int a = swz(LN * k + L);
+                    nxt[a] = accl[a];
+                    nxt[P + a] = accl[P + a];
                 }
             }
+            cur ^= 1;
         }
 
-        // ---- results (each slot reads back only its own accumulator)
+        // ---- results (each slot reads back only its own lanes of its accumulator)
         if (!has) continue;
+        const uint32_t *accl = base + cur * LD::BUF_WORDS;
         if (T.flags & TASK_STORE) {
             uint32_t *S = A.acc_state + T.acc_off + (size_t)T.comp * 2 * N;
 #pragma unroll

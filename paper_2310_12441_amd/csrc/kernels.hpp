@@ -36,9 +36,10 @@ struct BrArgs {
     int steps;                 // CMux steps per launch
     const uint32_t *ct_in;     // ciphertexts at their q_in
     uint32_t ct_stride;        // n + 1
-    uint32_t n, Q, qn, log2B, l, sg, goff;
+    uint32_t n, Q, qn, log2B, l, sg, goff;  // goff: (B/2)(1 + B + ... + B^(l-1))
     uint32_t keys;             // RGSW keys per coordinate (2 for a ternary secret)
     const uint32_t *bsk;       // [n][keys][2l][2][N], NTT domain, x 2^32 / N mod Q
+    const uint32_t *bsk_corr;  // [n][2][N]: -(B/2) sum_{key,row} BSK / N, the digit-offset correction
     const uint32_t *twf, *twi; // Montgomery-form twiddles
     const uint32_t *tv;        // test-vector arena
     uint32_t *acc_state;       // accumulators carried between launches
