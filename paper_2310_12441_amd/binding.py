@@ -137,6 +137,7 @@ class Context:
         p = Params(params.n, params.N, params.Q, params.log2_B, params.l, params.log2_Bks, params.l_ks,
                    1 if getattr(params, "ternary", False) else 0)
         self.params = params
+        self._lib = lib  # held so that close() still works while the interpreter shuts down
         self._keep = {k: (_i32(v) if k.endswith("_e") or k == "s" else _u32(v)) for k, v in draws.items()}
         d = KeyDraws(*(self._keep[k].ctypes.data_as(C.c_void_p) for k in ("s", "z", "bsk_a", "bsk_e", "ksk_a", "ksk_e")))
         h = C.c_void_p()
@@ -147,9 +148,10 @@ class Context:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
-            lib.mm_free(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            self._lib.mm_free(h)
 
     def __del__(self):
         self.close()

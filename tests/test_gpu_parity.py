@@ -413,3 +413,42 @@ def test_ternary_paper_shaped_single():
     want = oracle.bootstrap_many(case.p, 4, case.keys.bsk, case.keys.ksk, V, 8192, 8192, ct)
     np.testing.assert_array_equal(got, want)
     case.ctx.close()
+
+
+def test_full_batch_bench_configuration_sampled():
+    """The timed workload itself: 4096 paper-shaped ciphertexts (sigma = 3.2, the bench
+    seeds), autotuned schedule, one batched launch; sampled outputs equal the oracle's."""
+    b = _gpu()
+    p = PRESETS["paper_shaped"]["params"]
+    dr = key_draws(p, 1)
+    ctx = b.Context(p, dr)
+    ctx.device_init(0)
+    f = negacyclic_table(4096, 4096, 2)
+    tid = ctx.table_create(4096, 4096, 4, f)
+    m = messages(4096, 4096, 3)
+    ed = enc_draws(p.n, 8192, 4096, 4)
+    ct = ctx.encrypt(8192, 4096, m, ed["a"], ed["e"])
+    ids = np.full(4096, tid, np.int32)
+    say("bench configuration: autotune + batch of 4096")
+    ctx.autotune(ids, ct)
+    out = ctx.bootstrap(ids, ct)
+    keys = oracle.KeySet(p, dr)
+    V = oracle.test_vector(p.N, 4, Q, 4096, 4096, f)
+    pick = np.array([0, 1, 2, 1023, 2048, 3071, 4094, 4095])
+    say("oracle on", pick.size, "samples")
+    want = oracle.bootstrap_many(p, 4, keys.bsk, keys.ksk, V, 8192, 8192, ct[pick])
+    np.testing.assert_array_equal(out[pick], want)
+    ctx.close()
+
+
+def test_empty_and_ragged_batches(paper):
+    """count = 0 is a no-op; ragged batch sizes give the same bits as one larger batch."""
+    tid, f, V = paper.table(4096, 4096, 4, 15)
+    ct = paper.encrypt(8192, 4096, messages(4096, 131, 16), 17)
+    empty = paper.ctx.bootstrap(np.zeros(0, np.int32), ct[:0])
+    assert empty.shape == (0, paper.p.n + 1)
+    full = paper.ctx.bootstrap([tid] * 131, ct)
+    for cnt in (1, 3, 64, 129):
+        np.testing.assert_array_equal(paper.ctx.bootstrap([tid] * cnt, ct[:cnt]), full[:cnt], err_msg=f"count {cnt}")
+    np.testing.assert_array_equal(full[130], oracle.bootstrap(paper.p, 4, paper.keys.bsk, paper.keys.ksk, V, 8192,
+                                                              8192, ct[130]))
