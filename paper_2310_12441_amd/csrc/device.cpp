@@ -700,9 +700,9 @@ void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int 
     if (P) *P = (int)S.ks.P;
 }
 
-// Time every candidate schedule on this batch (one untimed run each, then the
-// blind rotation and the key switch measured separately) and remember the
-// fastest combination for the batch shape.
+// Time the group widths (with the default key switch) and the key-switch
+// tilings (with 8-wave groups) on this batch, one untimed run each first, and
+// remember the fastest combination for the batch shape.
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
 {
     MM_REQUIRE(check_ids(c, ids, count) == 0, "autotuning takes nega-cyclic tables");
@@ -718,11 +718,13 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
     if (!d.tev[0])
         for (auto &e : d.tev) HIPC(hipEventCreate(&e));
     d.timing = true;
-    // best blind rotation per group width, best key switch overall
     float best_br[2] = {1e30f, 1e30f}, best_ks = 1e30f;
     KsSched ks_best = cand[0].ks;
+    const KsSched ks0 = cand[0].ks;
     for (size_t k = 0; k < cand.size(); k++) {
         const Sched &S = cand[k];
+        const bool default_ks = S.ks.cpw == ks0.cpw && S.ks.P == ks0.P;
+        if (!default_ks && S.gw != 8) continue;  // each key-switch tiling is timed once
         bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
         HIPC(hipStreamSynchronize(st));
         bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
@@ -730,9 +732,8 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
         float br = 0, ks = 0;
         HIPC(hipEventElapsedTime(&br, d.tev[0], d.tev[1]));
         HIPC(hipEventElapsedTime(&ks, d.tev[1], d.tev[2]));
-        const int gi = S.gw == 4 ? 1 : 0;
-        best_br[gi] = std::min(best_br[gi], br);
-        if (ks < best_ks) {
+        if (default_ks) best_br[S.gw == 4 ? 1 : 0] = std::min(best_br[S.gw == 4 ? 1 : 0], br);
+        if (S.gw == 8 && ks < best_ks) {
             best_ks = ks;
             ks_best = S.ks;
         }

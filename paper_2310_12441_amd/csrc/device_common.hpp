@@ -123,7 +123,8 @@ __device__ __forceinline__ void relayout(uint32_t (&x)[NP][Geo<N>::E], uint32_t 
 
 // Forward negacyclic NTT (Cooley-Tukey, merged psi powers, natural order in,
 // bit-reversed order out) of NP polys held in phase-0 layout; returns them in
-// the last phase's layout.  twf[k] = psi^bitrev(k) 2^32 mod Q.
+// the last phase's layout, reduced to [0, Q) (inputs in [0, Q)).
+// twf[k] = psi^bitrev(k) 2^32 mod Q.
 template <int N, int NP>
 __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, const uint32_t *twf,
                                         int L, const ModQ &m)
@@ -142,12 +143,22 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *
                 if (k0 & (1 << kb)) continue;
                 const int k1 = k0 | (1 << kb);
                 const uint32_t w = twf[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
+                // Both outputs differ from each other only in bit b, so they agree on bit
+                // b - 1: when that bit is 1 (and lies in a register of this phase) both are
+                // multiplicands of the next stage, where any 32-bit value is a valid
+                // Montgomery input (x w < 2^32 Q); they stay unreduced in [0, 2Q).
+                const bool lazy = kb > 0 && ((k0 >> (kb - 1)) & 1);
 #pragma unroll
                 for (int q = 0; q < NP; q++) {
                     const uint32_t u = x[q][k0];
                     const uint32_t v = mont_mul(x[q][k1], w, m);
-                    x[q][k0] = add_q(u, v, m.Q);
-                    x[q][k1] = sub_q(u, v, m.Q);
+                    if (lazy) {
+                        x[q][k0] = u + v;
+                        x[q][k1] = u - v + m.Q;
+                    } else {
+                        x[q][k0] = add_q(u, v, m.Q);
+                        x[q][k1] = sub_q(u, v, m.Q);
+                    }
                 }
             }
         }
