@@ -49,6 +49,25 @@ __device__ __forceinline__ void phi_row(uint32_t c, uint32_t r, uint32_t j, uint
     e = a + (j < b ? 1u : 0u);
 }
 
+// A wave's task, every field moved to scalar registers (the same for all lanes),
+// so that the step index, key and ciphertext addresses derived from it stay
+// scalar and the per-lane part of each address is one 32-bit offset.
+__device__ __forceinline__ WaveTask uniform_task(const WaveTask &t)
+{
+    WaveTask u;
+    u.ct = __builtin_amdgcn_readfirstlane(t.ct);
+    u.comp = __builtin_amdgcn_readfirstlane(t.comp);
+    u.r = __builtin_amdgcn_readfirstlane(t.r);
+    u.tv_off = __builtin_amdgcn_readfirstlane(t.tv_off);
+    u.q_in = __builtin_amdgcn_readfirstlane(t.q_in);
+    u.i0 = __builtin_amdgcn_readfirstlane(t.i0);
+    u.flags = __builtin_amdgcn_readfirstlane(t.flags);
+    u.pad = 0;
+    u.acc_off = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t.acc_off >> 32)) << 32) |
+                __builtin_amdgcn_readfirstlane((uint32_t)t.acc_off);
+    return u;
+}
+
 // LDS per component slot: two accumulator buffers, each a swizzled pair (a, b).
 // During a step one holds the current ACC (read by the rotations of every slot
 // of the ciphertext) and the other serves the slot's NTT relayouts, then
@@ -68,7 +87,7 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
     constexpr int E = G::E, P = G::POLYW, WPP = G::WPP, LN = G::LANES;
     static_assert(GW % WPP == 0, "a group holds whole component slots");
     extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar from here on
     const int cs = wave / WPP;                             // component slot
     const int L = (wave % WPP) * 64 + (threadIdx.x & 63);  // virtual lane of the slot
     uint32_t *const base = lds + cs * LD::COMP_WORDS;
@@ -76,7 +95,7 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
     const GadgetC g{A.log2B, A.l, A.sg, A.goff};
 
     for (int grp = blockIdx.x; grp < A.num_groups; grp += gridDim.x) {
-        const WaveTask T = A.tasks[grp * GW + wave];
+        const WaveTask T = uniform_task(A.tasks[grp * GW + wave]);
         const bool has = T.ct >= 0;
         const uint32_t r = has ? T.r : 1u, M = 2u * N * r;
         const uint32_t *ct = A.ct_in + (size_t)(has ? T.ct : 0) * A.ct_stride;
