@@ -132,8 +132,18 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *
     using G = Geo<N>;
 #pragma unroll
     for (int p = 0; p < G::NPH; p++) {
-        if (p > 0) relayout<N, NP>(x, slot, L, p - 1, p);
         const int R = G::R(p);
+        if (p > 0) {
+            relayout<N, NP>(x, slot, L, p - 1, p);
+            // the previous phase left its last stage unreduced; reduce the values
+            // that are not multiplicands of this phase's first stage
+            const int kt = G::HI(p) - R;
+#pragma unroll
+            for (int k = 0; k < G::E; k++)
+                if (!((k >> kt) & 1))
+#pragma unroll
+                    for (int q = 0; q < NP; q++) x[q][k] = min(x[q][k], x[q][k] - m.Q);
+        }
         const int Lhi = (p == 0) ? 0 : (L >> R);
 #pragma unroll
         for (int b = G::HI(p); b >= R; b--) {
@@ -144,10 +154,12 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *
                 const int k1 = k0 | (1 << kb);
                 const uint32_t w = twf[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
                 // Both outputs differ from each other only in bit b, so they agree on bit
-                // b - 1: when that bit is 1 (and lies in a register of this phase) both are
-                // multiplicands of the next stage, where any 32-bit value is a valid
-                // Montgomery input (x w < 2^32 Q); they stay unreduced in [0, 2Q).
-                const bool lazy = kb > 0 && ((k0 >> (kb - 1)) & 1);
+                // b - 1: when that bit is 1 both are multiplicands of the next stage, where
+                // any 32-bit value is a valid Montgomery input (x w < 2^32 Q), and they
+                // stay unreduced in [0, 2Q).  In the last stage of a phase bit b - 1 is a
+                // lane bit, so all outputs stay unreduced and the next phase reduces its
+                // non-multiplicands after the relayout; the last phase ends reduced.
+                const bool lazy = kb > 0 ? ((k0 >> (kb - 1)) & 1) != 0 : p + 1 < G::NPH;
 #pragma unroll
                 for (int q = 0; q < NP; q++) {
                     const uint32_t u = x[q][k0];
