@@ -227,19 +227,26 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
 
 /* ---- serving: continuous batching ---- */
 
-/* Start a server on ctx.  It owns up to `slots` in-flight ciphertexts whose
- * device state (accumulators, inputs, outputs) fits in hbm_budget_bytes; each
- * launch advances every resident ciphertext by `chunk_steps` CMux steps, so a
- * request admitted while others run joins them at the next launch. */
+/* Start a server on ctx (one per context; MM_ESTATE if one runs).  It keeps as
+ * many in-flight ciphertexts as their device state (accumulators, inputs,
+ * outputs) fits in hbm_budget_bytes (MM_EINVAL below one 8-component group);
+ * chunk_steps in [1, n].  Each launch advances every resident ciphertext by
+ * chunk_steps CMux steps, so a request admitted while others run joins them at
+ * the next launch.  Tables of general f, or with r N/1024 > 8, are not served.
+ * The handle stays valid until mm_server_stop; mm_free of the context stops a
+ * running server too, after which the handle must not be used. */
 int mm_server_start(mm_ctx *ctx, size_t hbm_budget_bytes, uint32_t chunk_steps, mm_server **out);
 
 /* Queue one ciphertext (n+1 words at its table's q_in, host memory).  The
- * result is at the table's q_in.  MM_EBUSY when the queue is full.
+ * result is at the table's q_in.  MM_EBUSY when the queue is full, MM_EINVAL
+ * for a table the server does not take, MM_ESTATE once the serving loop has
+ * stopped after a device error (mm_last_error of the context says which).
  * *ticket identifies the request for mm_poll. */
 int mm_submit(mm_server *s, int table_id, const uint32_t *ct, uint64_t *ticket);
 
 /* Copy the result of `ticket` into ct_out (n+1 words) once ready; MM_EAGAIN
- * before that.  A ticket can be collected once. */
+ * before that, MM_ESTATE if the serving loop stopped before finishing it,
+ * MM_EINVAL for a ticket never issued.  A ticket can be collected once. */
 int mm_poll(mm_server *s, uint64_t ticket, uint32_t *ct_out);
 
 /* Latency percentiles (submit to result ready, ms) and completed bootstraps per

@@ -230,13 +230,22 @@ void server_stop(Server *s)
 uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *rc)
 {
     const size_t W = c->p.n + 1;
+    bool ok;
+    {
+        std::lock_guard<std::mutex> gc(c->lock);  // the table list may grow under this lock
+        ok = table >= 0 && (size_t)table < c->tables.size() && c->tables[table].g_id < 0 &&
+             c->tables[table].r * (uint32_t)dev::waves_per_poly(c->p.N) <= 8;
+    }
     std::lock_guard<std::mutex> g(mu);
-    if (table < 0 || (size_t)table >= c->tables.size() || c->tables[table].g_id >= 0 ||
-        c->tables[table].r * (uint32_t)dev::waves_per_poly(c->p.N) > 8) {
+    if (!ok) {
         *rc = MM_EINVAL;  // unknown table, a general table (two bootstraps; not served), or too wide a group
         return 0;
     }
-    if (pending.size() >= pending_cap || stop) {
+    if (stop) {
+        *rc = MM_ESTATE;  // the serving loop has stopped (a device error ends it; see mm_last_error)
+        return 0;
+    }
+    if (pending.size() >= pending_cap) {
         *rc = MM_EBUSY;
         return 0;
     }
@@ -281,6 +290,7 @@ void Server::launch(Part &p)
     const uint32_t N = c->p.N, W = c->p.n + 1, n = c->p.n;
     std::vector<Active> fresh;
     std::vector<Req> fresh_req;
+    std::lock_guard<std::mutex> dev_lock(c->lock);  // tables and device state; taken before mu
     {
         std::lock_guard<std::mutex> g(mu);
         while (!pending.empty() && !free_slots.empty()) {
@@ -296,7 +306,6 @@ void Server::launch(Part &p)
         }
     }
     if (fresh.empty() && p.active.empty()) return;
-    std::lock_guard<std::mutex> dev_lock(c->lock);
     Device &d = ensure_device(*c);
     if (!fresh.empty()) {
         p.stage.reserve(fresh.size() * W);
@@ -467,7 +476,10 @@ int mm_poll(mm_server *h, uint64_t ticket, uint32_t *ct_out)
     mm::Server &s = *h->s;
     std::lock_guard<std::mutex> g(s.mu);
     auto it = s.done.find(ticket);
-    if (it == s.done.end()) return (ticket > 0 && ticket < s.next_ticket) ? MM_EAGAIN : MM_EINVAL;
+    if (it == s.done.end()) {
+        if (ticket == 0 || ticket >= s.next_ticket) return MM_EINVAL;
+        return s.stop ? MM_ESTATE : MM_EAGAIN;  // a stopped loop will not finish it
+    }
     std::memcpy(ct_out, it->second.ct.data(), it->second.ct.size() * 4);
     s.done.erase(it);
     return MM_OK;

@@ -193,6 +193,27 @@ def test_serving_at_2048_matches_alone():
     np.testing.assert_array_equal(out, alone)
 
 
+@pytest.mark.parametrize("N,r", [(2048, 2), (4096, 1)])
+def test_ternary_at_large_ring(N, r):
+    """Ternary secret (two keys, both CMux terms per step) with polynomials spanning several waves."""
+    from dataclasses import replace
+    say("ternary N", N, "r", r)
+    p = replace(Params(n=10, N=N, log2_B=7, l=4), ternary=True)
+    c = Case(p, 950 + N)
+    t = 2 * N * r // 8
+    tid, f, V = c.table(t, t, r, 96)
+    q = 2 * N * r
+    ct = c.encrypt(q, t, messages(t, 3, 97), 98)
+    got = c.ctx.blind_rotate([tid] * 3, ct, 4)
+    size = r * 2 * N
+    for j in range(3):
+        want = oracle.blind_rotate(c.p, r, c.keys.bsk, V, ct[j], 4)
+        np.testing.assert_array_equal(got[j * size:(j + 1) * size].reshape(r, 2, N), want, err_msg=f"ct {j}")
+    out = c.ctx.bootstrap([tid] * 3, ct)
+    np.testing.assert_array_equal(out, oracle.bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    c.ctx.close()
+
+
 @pytest.fixture(scope="module")
 def tfhe_paper():
     pre = PRESETS["tfhe_shaped"]

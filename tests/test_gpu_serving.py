@@ -100,3 +100,13 @@ def test_server_errors(setup):
     with pytest.raises(b.MMError):
         ctx.server_start(64 << 20)  # one server per context
     srv.stop()
+
+
+def test_server_refuses_after_stop_and_tickets_never_issued(setup):
+    p, ctx, tabs, keys, b = setup
+    srv = ctx.server_start(64 << 20)
+    with pytest.raises(b.MMError):
+        srv.poll(12345)  # never issued
+    srv.stop()
+    with pytest.raises(Exception):
+        srv.submit(tabs[0][0], np.zeros(p.n + 1, np.uint32))
