@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=BATCH)
-    ap.add_argument("--plain", type=int, default=8, help="ciphertexts timed on the plain path")
+    ap.add_argument("--plain", type=int, default=20,
+                    help="single-ciphertext plain-path runs (latency = their median)")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: one per host thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--mixed", type=int, default=2048,
@@ -162,18 +163,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- plain path on the same GPU (one ciphertext at a time)
+    # ---- plain path on the same GPU: one ciphertext per call, latency = median of the runs
     P = min(args.plain, B)
-    plain_rate, plain_same = None, None
+    plain_rate, plain_same, plain_lat = None, None, []
     if P > 0:
         ctx.bootstrap(ids[:1], dev_in[:1], plain=True)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        plain_out = ctx.bootstrap(ids[:P], dev_in[:P], plain=True)
-        torch.cuda.synchronize()
-        plain_s = time.perf_counter() - t1
-        plain_rate = P / plain_s
-        plain_same = bool(np.array_equal(plain_out.cpu().numpy().view(np.uint32), batched_out[:P]))
+        plain_outs = []
+        for k in range(P):
+            t1 = time.perf_counter()
+            o = ctx.bootstrap(ids[k:k + 1], dev_in[k:k + 1], plain=True)
+            torch.cuda.synchronize()
+            plain_lat.append(time.perf_counter() - t1)
+            plain_outs.append(o)
+        plain_rate = 1.0 / float(np.median(plain_lat))
+        plain_out = torch.cat(plain_outs).cpu().numpy().view(np.uint32)
+        plain_same = bool(np.array_equal(plain_out, batched_out[:P]))
 
     # ---- roofline of the blind-rotation kernel
     br_avg = float(np.mean(br_ms)) * 1e-3
@@ -316,7 +321,10 @@ def main():
         t2 = time.perf_counter()
         want = oracle.bootstrap_many(p, r, keys.bsk, keys.ksk, V, q, q, ct[idx])
         cpu_s = time.perf_counter() - t2
+        cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")),
+                         None) if os.path.exists("/proc/cpuinfo") else None
         cpu = {"value": round(S / cpu_s, 4), "unit": "bootstraps/s", "cores": nthr, "kind": "oracle",
+               "cpu_model": cpu_model,
                "sample": f"{S} of the {B} ciphertexts (evenly spaced), one ciphertext per thread, schoolbook products",
                "seconds": round(cpu_s, 2), "parity_with_gpu": bool(np.array_equal(want, batched_out[idx]))}
 
@@ -337,6 +345,7 @@ def main():
                    "batch": B, "n": p.n, "N": p.N, "k": r, "t": t, "q": q, "Q": p.Q, "seeds": seeds},
         "plain_bootstraps_per_s": round(plain_rate, 3) if plain_rate else None,
         "plain_ms_per_bootstrap": round(1e3 / plain_rate, 3) if plain_rate else None,
+        "plain_runs": len(plain_lat),
         "batched_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
         "plain_equals_batched": plain_same,
         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
