@@ -209,10 +209,13 @@ static void finish_out(uint32_t *host, const uint32_t *dev, size_t words, bool d
 // waves per polynomial), first-fit over r descending, each ciphertext's
 // components on consecutive slots of one group.  cts[k] is the task of
 // ciphertext k with comp = 0; the result holds gw tasks per group, the wpp
-// waves of a slot carrying the same task.
-std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp)
+// waves of a slot carrying the same task.  With cap < slots a group takes at
+// most cap components (a wider ciphertext still gets a group of its own), so
+// that a small batch spreads over more compute units, one wave per SIMD.
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp, uint32_t cap)
 {
     const uint32_t slots = gw / wpp;
+    cap = std::max<uint32_t>(1, std::min(cap ? cap : slots, slots));
     for (auto &t : cts)
         MM_REQUIRE(t.r >= 1 && t.r <= slots,
                    "a ciphertext's r components times N/1024 waves each must fit one workgroup of 8 waves");
@@ -223,9 +226,9 @@ std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uin
     std::vector<uint32_t> used;  // slots used per group
     size_t first_open = 0;
     for (size_t o : order) {
-        const uint32_t r = cts[o].r;
+        const uint32_t r = cts[o].r, limit = std::max(cap, r);
         size_t g = first_open;
-        while (g < used.size() && used[g] + r > slots) g++;
+        while (g < used.size() && used[g] + r > limit) g++;
         if (g == used.size()) {
             used.push_back(0);
             dev::WaveTask idle{};
@@ -238,13 +241,23 @@ std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uin
             for (uint32_t v = 0; v < wpp; v++) tasks[g * gw + (used[g] + j) * wpp + v] = w;
         }
         used[g] += r;
-        while (first_open < used.size() && used[first_open] == slots) first_open++;
+        while (first_open < used.size() && used[first_open] >= cap) first_open++;
     }
     return tasks;
 }
 
-static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, size_t count, uint32_t flags,
-                                              uint32_t i0, const std::vector<uint64_t> &acc_off, uint32_t gw = 8)
+// Components per group for a batch of `comps` components: the full width,
+// or half of it when that still fits every group on its own compute unit.
+uint32_t spread_cap(const Device &d, uint64_t comps, uint32_t gw, uint32_t wpp)
+{
+    const uint32_t slots = gw / wpp;
+    if (slots >= 8 && comps <= (uint64_t)(slots / 2) * (uint64_t)d.num_cu) return slots / 2;
+    return slots;
+}
+
+static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const Device &d, const int *ids, size_t count,
+                                              uint32_t flags, uint32_t i0, const std::vector<uint64_t> &acc_off,
+                                              uint32_t gw = 8)
 {
     std::vector<dev::WaveTask> cts(count);
     for (size_t k = 0; k < count; k++) {
@@ -259,7 +272,10 @@ static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const int *ids, s
         w.flags = flags;
         w.acc_off = acc_off.empty() ? 0 : acc_off[k];
     }
-    return pack_tasks(cts, gw, (uint32_t)dev::waves_per_poly(c.p.N));
+    uint64_t comps = 0;
+    for (auto &t : cts) comps += t.r;
+    const uint32_t wpp = (uint32_t)dev::waves_per_poly(c.p.N);
+    return pack_tasks(cts, gw, wpp, spread_cap(d, comps, gw, wpp));
 }
 
 // Valid ids; returns how many name general (two-bootstrap) tables.
@@ -411,7 +427,7 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
 {
     const uint32_t N = c.p.N;
     const Sched S = force ? *force : schedule_for(c, d, ids, count);
-    auto tasks = pack_groups(c, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw);
+    auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw);
     const int groups = (int)(tasks.size() / S.gw);
     // per-ciphertext output modulus
     const uint32_t *qv = nullptr;
@@ -563,7 +579,7 @@ void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t c
     }
     const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * (c.p.n + 1), dptr, st);
     uint32_t *d_acc = stage_out(d, WS_ACC, acc_out, words, dptr);
-    auto tasks = pack_groups(c, ids, count, dev::TASK_INIT | dev::TASK_STORE, 0, off);
+    auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_STORE, 0, off);
     dev::WaveTask *dt = upload_tasks(d, tasks, st);
     dev::BrArgs A = br_args(c, d);
     A.tasks = dt;

@@ -87,7 +87,9 @@ struct Sched {
     KsSched ks;
 };
 
-std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp);
+std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp,
+                                      uint32_t cap = 0);
+uint32_t spread_cap(const Device &d, uint64_t comps, uint32_t gw, uint32_t wpp);
 KsSched ks_default(const mm_ctx &c, const Device &d, size_t count);
 size_t ks_part_words(const mm_ctx &c, const KsSched &k, size_t count);
 dev::BrArgs br_args(const mm_ctx &c, const Device &d);

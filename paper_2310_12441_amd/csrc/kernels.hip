@@ -62,7 +62,7 @@ __device__ __forceinline__ WaveTask uniform_task(const WaveTask &t)
     u.q_in = __builtin_amdgcn_readfirstlane(t.q_in);
     u.i0 = __builtin_amdgcn_readfirstlane(t.i0);
     u.flags = __builtin_amdgcn_readfirstlane(t.flags);
-    u.pad = 0;
+    u.steps = __builtin_amdgcn_readfirstlane(t.steps);
     u.acc_off = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t.acc_off >> 32)) << 32) |
                 __builtin_amdgcn_readfirstlane((uint32_t)t.acc_off);
     return u;
@@ -153,9 +153,10 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
         // which no slot writes during the step, so one barrier per step suffices.
         // When a polynomial spans several waves its NTTs synchronise the whole
         // workgroup, so every wave runs them (idle slots on zeros, results dropped).
+        const uint32_t lim = T.steps ? min(T.steps, (uint32_t)A.steps) : (uint32_t)A.steps;
         for (int s = 0; s < A.steps; s++) {
             const uint32_t i = T.i0 + (uint32_t)s;
-            const bool active = has && i < A.n;
+            const bool active = has && i < A.n && (uint32_t)s < lim;
             const bool run = active || WPP > 1;
             uint32_t *const accl = base + cur * LD::BUF_WORDS;        // current ACC
             uint32_t *const nxt = base + (cur ^ 1) * LD::BUF_WORDS;   // exchange slot, then next ACC
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
                 S[N + LN * k + L] = accl[P + swz(LN * k + L)];
             }
         }
-        if ((T.flags & TASK_EXTRACT) && T.comp == 0 && T.i0 + (uint32_t)A.steps >= A.n) {
+        if ((T.flags & TASK_EXTRACT) && T.comp == 0 && T.i0 + lim >= A.n) {
             // (A_0, -A_{N-1}, ..., -A_1; B_0) (eq. equ-sam-extr)
             uint32_t *o = A.ext_out + (size_t)T.ct * (N + 1);
 #pragma unroll

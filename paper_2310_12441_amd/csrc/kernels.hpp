@@ -26,7 +26,7 @@ struct WaveTask {
     uint32_t q_in;     // ciphertext modulus
     uint32_t i0;       // first CMux step of this launch
     uint32_t flags;    // TASK_*
-    uint32_t pad;
+    uint32_t steps;    // CMux steps of this task in the launch (0: the launch's step count)
     uint64_t acc_off;  // word offset of the ciphertext's accumulator state (r x 2 x N)
 };
 

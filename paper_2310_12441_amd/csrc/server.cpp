@@ -319,7 +319,17 @@ void Server::launch(Part &p)
         dev::launch_scatter_rows(p.stage.d, d_ct, p.stage_rows.d, fresh.size(), W, p.st);
         p.active.insert(p.active.end(), fresh.begin(), fresh.end());
     }
-    // one task per resident ciphertext, packed into 8-wave groups
+    // one task per resident ciphertext, packed into 8-wave groups; under light
+    // load the groups hold at most 4 components (one wave per SIMD), and a
+    // ciphertext that still needs all 8 slots (two waves per SIMD, about 1.5x
+    // slower per step) advances 2/3 of the steps, so its group does not set the
+    // length of the tick for the others
+    const uint32_t wpp = (uint32_t)dev::waves_per_poly(c->p.N);
+    uint64_t comps = 0;
+    for (auto &a : p.active) comps += c->tables[a.table].r;
+    const uint32_t cap = spread_cap(d, comps, 8, wpp);
+    const uint32_t wide_chunk = std::max<uint32_t>(1, chunk * 2 / 3);
+    auto steps_of = [&](const Active &a) { return c->tables[a.table].r > cap ? wide_chunk : chunk; };
     std::vector<dev::WaveTask> cts(p.active.size());
     for (size_t k = 0; k < p.active.size(); k++) {
         const Active &a = p.active[k];
@@ -330,10 +340,11 @@ void Server::launch(Part &p)
         w.tv_off = (uint32_t)t.dev_offset;
         w.q_in = t.q_in;
         w.i0 = a.step;
+        w.steps = steps_of(a);
         w.flags = (a.step == 0 ? dev::TASK_INIT : 0u) | dev::TASK_STORE | dev::TASK_EXTRACT;
         w.acc_off = (uint64_t)a.unit * 2 * N;
     }
-    auto tasks = pack_tasks(cts, 8, (uint32_t)dev::waves_per_poly(c->p.N));
+    auto tasks = pack_tasks(cts, 8, wpp, cap);
     p.tasks.reserve(tasks.size());
     std::memcpy(p.tasks.h, tasks.data(), tasks.size() * sizeof(dev::WaveTask));
     SRV_HIP(hipMemcpyAsync(p.tasks.d, p.tasks.h, tasks.size() * sizeof(dev::WaveTask), hipMemcpyHostToDevice, p.st));
@@ -350,9 +361,10 @@ void Server::launch(Part &p)
     std::vector<Active> keep;
     p.finishing.clear();
     for (auto &a : p.active) {
-        if (a.step + chunk >= n) p.finishing.push_back(a);
+        const uint32_t st = steps_of(a);
+        if (a.step + st >= n) p.finishing.push_back(a);
         else {
-            a.step += chunk;
+            a.step += st;
             keep.push_back(a);
         }
     }
