@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) k_keyswitch(KsArgs A)
 // registers) and every wave adds, for each of its CPW ciphertexts, the l_ks rows
 // its digits select.  KSK traffic: one read of the column slice per ciphertext
 // tile.  Partial sums over the i-split blockIdx.z go to part (reduced mod Q).
-template <int CPW>
+template <int CPW, bool L8>
 __global__ void __launch_bounds__(256) k_keyswitch_tiled(KsArgs A)
 {
     constexpr int ROWS = KS_TILED_MAX_ROWS;  // l_ks * B_ks <= 128
@@ -417,16 +417,35 @@ __global__ void __launch_bounds__(256) k_keyswitch_tiled(KsArgs A)
     for (uint32_t i = i_begin; i < i_end; i++) {
         if (i + 1 < i_end) fetch(i + 1);
         const uint32_t mine = my_ok ? my_src[i] : 0u;
+        if constexpr (L8) {
+            // eight digits of log2Bks bits: unrolled, one scalar extract per row
+            const uint32_t *tl = &tile[b][lane];
 #pragma unroll
-        for (int q = 0; q < CPW; q++) {
-            const uint32_t a = __builtin_amdgcn_readlane(mine, q);
-            uint32_t s = 0;
-            for (uint32_t j = 0; j < A.l_ks; j++) {
-                const uint32_t sh = j * A.log2Bks;
-                const uint32_t d = sh < 32 ? (a >> sh) & (Bks - 1) : 0u;
-                s = add_q(s, tile[b][(j * Bks + d) * 64 + lane], A.Q);
+            for (int q = 0; q < CPW; q++) {
+                uint32_t a = __builtin_amdgcn_readlane(mine, q);
+                __asm__ volatile("" : "+s"(a) :: "memory");  // one ciphertext at a time
+                uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    const uint32_t d0 = (a >> (j * A.log2Bks)) & (Bks - 1);
+                    const uint32_t d1 = (a >> ((j + 1) * A.log2Bks)) & (Bks - 1);
+                    s0 = add_q(s0, tl[((uint32_t)j * Bks + d0) * 64], A.Q);
+                    s1 = add_q(s1, tl[((uint32_t)(j + 1) * Bks + d1) * 64], A.Q);
+                }
+                acc[q] = add_q(acc[q], add_q(s0, s1, A.Q), A.Q);
             }
-            acc[q] = add_q(acc[q], s, A.Q);
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPW; q++) {
+                const uint32_t a = __builtin_amdgcn_readlane(mine, q);
+                uint32_t s = 0;
+                for (uint32_t j = 0; j < A.l_ks; j++) {
+                    const uint32_t sh = j * A.log2Bks;
+                    const uint32_t d = sh < 32 ? (a >> sh) & (Bks - 1) : 0u;
+                    s = add_q(s, tile[b][(j * Bks + d) * 64 + lane], A.Q);
+                }
+                acc[q] = add_q(acc[q], s, A.Q);
+            }
         }
         __syncthreads();
         if (i + 1 < i_end) put(b ^ 1);
@@ -699,10 +718,20 @@ void launch_keyswitch_tiled(const KsArgs &A, int cpw, uint32_t splits, hipStream
     const uint32_t W = A.n + 1;
     const uint32_t cts_per_block = 4u * cpw;
     dim3 grid((W + 63) / 64, (uint32_t)((A.count + cts_per_block - 1) / cts_per_block), splits);
+    const bool l8 = A.l_ks == 8 && 8 * A.log2Bks <= 32;  // eight digits, all inside the word
     switch (cpw) {
-    case 16: hipLaunchKernelGGL(k_keyswitch_tiled<16>, grid, dim3(256), 0, st, A); break;
-    case 32: hipLaunchKernelGGL(k_keyswitch_tiled<32>, grid, dim3(256), 0, st, A); break;
-    default: hipLaunchKernelGGL(k_keyswitch_tiled<64>, grid, dim3(256), 0, st, A); break;
+    case 16:
+        if (l8) hipLaunchKernelGGL((k_keyswitch_tiled<16, true>), grid, dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_keyswitch_tiled<16, false>), grid, dim3(256), 0, st, A);
+        break;
+    case 32:
+        if (l8) hipLaunchKernelGGL((k_keyswitch_tiled<32, true>), grid, dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_keyswitch_tiled<32, false>), grid, dim3(256), 0, st, A);
+        break;
+    default:
+        if (l8) hipLaunchKernelGGL((k_keyswitch_tiled<64, true>), grid, dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_keyswitch_tiled<64, false>), grid, dim3(256), 0, st, A);
+        break;
     }
 }
 
