@@ -16,9 +16,14 @@ __all__ = [
     "encrypt", "decrypt", "lwe_phase", "external_product", "blind_rotate", "sample_extract",
     "keyswitch", "bootstrap", "bootstrap_many", "KeySet", "bsk_bytes", "ksk_bytes",
     "general_tables", "bootstrap_general",
+    "w_poly_mul", "w_rotate", "w_test_vector", "w_gadget_shift", "w_gadget", "w_decompose", "w_keygen_bsk",
+    "w_external_product", "w_blind_rotate", "w_modswitch", "w_sample_extract", "w_bootstrap", "w_bootstrap_many",
+    "KeySetWide",
 ]
 
 _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _u32 = C.c_uint32
 _u64 = C.c_uint64
@@ -56,6 +61,22 @@ def lib():
             "orc_general_tables": (None, [_u32, _u32, _u32p, _u32p, _u32p]),
             "orc_bootstrap_general": (None, [_u32] * 9 + [_u32p, _u32p, _u32p, _u32p, _u32, _u32, _u32,
                                                          _u32p, _u32p]),
+            "orc_w_poly_mul": (None, [_u32, _u64, _u64p, _u64p, _u64p]),
+            "orc_w_rotate": (None, [_u32, _u32, _u64, _u64, _u64p, _u64p]),
+            "orc_w_test_vector": (None, [_u32, _u32, _u64, _u32, _u32, _u32p, _u64p]),
+            "orc_w_gadget_shift": (_u32, [_u64, _u32, _u32]),
+            "orc_w_gadget": (_u64, [_u64, _u32, _u32, _u32]),
+            "orc_w_decompose": (None, [_u64, _u32, _u32, _u64, _i64p]),
+            "orc_w_keygen_bsk": (None, [_u32, _u32, _u64, _u32, _u32, _u32, _i32p, _u32p, _u64p, _i32p, _u64p]),
+            "orc_w_external_product": (None, [_u32, _u64, _u32, _u32, _u64p, _u64p, _u64p]),
+            "orc_w_blind_rotate": (None, [_u32, _u32, _u64, _u32, _u32, _u32, _u32, _u64p, _u64p, _u32p, _u32,
+                                          _u64p]),
+            "orc_w_modswitch": (_u64, [_u64, _u64, _u64]),
+            "orc_w_sample_extract": (None, [_u32, _u64, _u64p, _u64p]),
+            "orc_w_bootstrap": (None, [_u32, _u32, _u64, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u64p, _u32p,
+                                       _u64p, _u32, _u32, _u32p, _u32p, C.c_void_p]),
+            "orc_w_bootstrap_many": (None, [_u32, _u32, _u64, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u64p,
+                                            _u32p, _u64p, _u32, _u32, _u32p, _u64, _u32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -268,3 +289,114 @@ def bsk_bytes(n: int, N: int, l: int, word_bytes: int, keys_per_coord: int) -> i
 def ksk_bytes(n: int, N: int, B_ks: int, l_ks: int, word_bytes: int) -> int:
     """LWE_{n,Q}(v z_i B_ks^j) for v < B_ks, i < N, j < l_ks (Sec. 5 item (2))."""
     return N * B_ks * l_ks * (n + 1) * word_bytes
+
+
+# ---------------------------------------------------------------- wide ring modulus
+# The same steps with the accumulator and the bootstrapping key modulo Q_w =
+# p.Q_ring (up to 2^62, one uint64 per coefficient); the key switch stays at p.Q.
+
+
+def _w(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint64)
+
+
+def w_poly_mul(a, b, Q: int) -> np.ndarray:
+    a, b = _w(a), _w(b)
+    out = np.empty_like(a)
+    lib().orc_w_poly_mul(a.size, Q, a, b, out)
+    return out
+
+
+def w_rotate(v, c: int, Q: int) -> np.ndarray:
+    v = _w(v)
+    r, N = v.shape
+    out = np.empty_like(v)
+    lib().orc_w_rotate(N, r, Q, c % (2 * N * r), v, out)
+    return out
+
+
+def w_test_vector(N: int, r: int, Q: int, t: int, t_out: int, f) -> np.ndarray:
+    V = np.empty((r, N), dtype=np.uint64)
+    lib().orc_w_test_vector(N, r, Q, t, t_out, _u(f), V)
+    return V
+
+
+def w_gadget_shift(Q: int, log2_B: int, l: int) -> int:
+    return int(lib().orc_w_gadget_shift(Q, log2_B, l))
+
+
+def w_gadget(Q: int, log2_B: int, l: int) -> list:
+    return [int(lib().orc_w_gadget(Q, log2_B, l, u)) for u in range(l)]
+
+
+def w_decompose(x: int, Q: int, log2_B: int, l: int) -> np.ndarray:
+    d = np.empty(l, dtype=np.int64)
+    lib().orc_w_decompose(Q, log2_B, l, int(x), d)
+    return d
+
+
+def w_keygen_bsk(p, draws) -> np.ndarray:
+    """[n * K][2l][2][N] uint64 at p.Q_ring."""
+    K = _keys(p)
+    out = np.empty((p.n * K, 2 * p.l, 2, p.N), dtype=np.uint64)
+    lib().orc_w_keygen_bsk(p.n, p.N, p.Q_ring, p.log2_B, p.l, K, _i(draws["s"]), _u(draws["z"]),
+                           _w(draws["bsk_a"]), _i(draws["bsk_e"]), out)
+    return out
+
+
+def w_external_product(rgsw, rlwe, Q: int, log2_B: int, l: int) -> np.ndarray:
+    rgsw, rlwe = _w(rgsw), _w(rlwe)
+    N = rlwe.shape[-1]
+    out = np.empty((2, N), dtype=np.uint64)
+    lib().orc_w_external_product(N, Q, log2_B, l, rgsw, rlwe, out)
+    return out
+
+
+def w_blind_rotate(p, r: int, bsk, V, ct_ms, steps=None) -> np.ndarray:
+    acc = np.empty((r, 2, p.N), dtype=np.uint64)
+    steps = p.n if steps is None else steps
+    lib().orc_w_blind_rotate(p.n, p.N, p.Q_ring, p.log2_B, p.l, r, _keys(p), _w(bsk), _w(V), _u(ct_ms),
+                             steps, acc)
+    return acc
+
+
+def w_modswitch(x, Q_from: int, q_to: int) -> np.ndarray:
+    x = _w(np.atleast_1d(x))
+    return np.array([lib().orc_w_modswitch(int(v), Q_from, q_to) for v in x.reshape(-1)],
+                    dtype=np.uint64).reshape(x.shape)
+
+
+def w_sample_extract(rlwe, Q: int) -> np.ndarray:
+    rlwe = _w(rlwe)
+    N = rlwe.shape[-1]
+    out = np.empty(N + 1, dtype=np.uint64)
+    lib().orc_w_sample_extract(N, Q, rlwe, out)
+    return out
+
+
+def w_bootstrap(p, r: int, bsk, ksk, V, q_in: int, q_out: int, ct, ext_out=False):
+    """One ciphertext; with ext_out also the extracted sample after the switch to p.Q."""
+    out = np.empty(p.n + 1, dtype=np.uint32)
+    ext = np.empty(p.N + 1, dtype=np.uint32) if ext_out else None
+    lib().orc_w_bootstrap(p.n, p.N, p.Q_ring, p.log2_B, p.l, p.Q, p.log2_Bks, p.l_ks, r, _keys(p), _w(bsk),
+                          _u(ksk), _w(V), q_in, q_out, _u(ct), out, _ptr(ext))
+    return (out, ext) if ext_out else out
+
+
+def w_bootstrap_many(p, r: int, bsk, ksk, V, q_in: int, q_out: int, cts) -> np.ndarray:
+    cts = _u(cts).reshape(-1, p.n + 1)
+    out = np.empty_like(cts)
+    lib().orc_w_bootstrap_many(p.n, p.N, p.Q_ring, p.log2_B, p.l, p.Q, p.log2_Bks, p.l_ks, r, _keys(p),
+                               _w(bsk), _u(ksk), _w(V), q_in, q_out, cts, cts.shape[0], out)
+    return out
+
+
+class KeySetWide:
+    """Keys at the wide ring modulus p.Q_ring (BSK) and at p.Q (KSK), built from the shared draws."""
+
+    def __init__(self, p, draws):
+        self.p = p
+        self.s = _i(draws["s"])
+        self.z = _u(draws["z"])
+        self.bsk = w_keygen_bsk(p, draws)
+        self.ksk = keygen_ksk(p, draws)

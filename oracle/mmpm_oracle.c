@@ -586,3 +586,315 @@ void orc_bootstrap_general(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, u
     free(ctg);
     free(ct2);
 }
+
+/* ----------------------------------------------------------------------- */
+/* A wide ring modulus (Sec. 5 experiments: log Q = 54, B = 2^15)          */
+/* ----------------------------------------------------------------------- */
+
+/* The same steps with the ring modulus Q_w up to 2^62 held as one uint64 per
+ * coefficient (no residue-number split here: Q_w is a single integer).  The
+ * LWE side stays 32-bit: after extraction each coefficient is switched from
+ * Q_w to the key-switch modulus Q_ks (< 2^31) by rounding, then the key switch
+ * and the final switch are the functions above.  Products are reduced with
+ * 128-bit integers. */
+
+typedef unsigned __int128 w_u128;
+typedef __int128 w_i128;
+
+static uint64_t w_mod(w_i128 x, uint64_t Q)
+{
+    w_i128 r = x % (w_i128)Q;
+    return (uint64_t)(r < 0 ? r + (w_i128)Q : r);
+}
+
+static uint64_t w_neg(uint64_t x, uint64_t Q) { return x ? Q - x : 0; }
+
+static uint32_t w_bits(uint64_t Q)
+{
+    uint32_t b = 0;
+    while (b < 64 && (Q >> b)) b++;
+    return b;
+}
+
+/* out = a * b in Z_Q[x]/(x^N+1), every product reduced mod Q. */
+void orc_w_poly_mul(uint32_t N, uint64_t Q, const uint64_t *a, const uint64_t *b, uint64_t *out)
+{
+    for (uint32_t k = 0; k < N; k++) {
+        w_u128 pos = 0, neg = 0;
+        for (uint32_t j = 0; j <= k; j++) pos += (w_u128)a[j] * b[k - j] % Q;
+        for (uint32_t j = k + 1; j < N; j++) neg += (w_u128)a[j] * b[N + k - j] % Q;
+        out[k] = w_mod((w_i128)(pos % Q) - (w_i128)(neg % Q), Q);
+    }
+}
+
+/* acc += small * big in Z[x]/(x^N+1) with 128-bit accumulators (|small| < 2^31). */
+static void w_nega_mac_small(w_i128 *acc, const int64_t *small, const uint64_t *big, uint32_t N)
+{
+    for (uint32_t j = 0; j < N; j++) {
+        const w_i128 d = small[j];
+        if (d == 0) continue;
+        for (uint32_t k = j; k < N; k++) acc[k] += d * (w_i128)big[k - j];
+        for (uint32_t k = 0; k < j; k++) acc[k] -= d * (w_i128)big[N + k - j];
+    }
+}
+
+static void w_monomial_mul(uint64_t e, const uint64_t *p, uint64_t *out, uint32_t N, uint64_t Q)
+{
+    const uint64_t twoN = 2ull * N;
+    for (uint32_t i = 0; i < N; i++) {
+        uint64_t m = ((uint64_t)i + e) % twoN;
+        if (m < N) out[m] = p[i];
+        else out[m - N] = w_neg(p[i], Q);
+    }
+}
+
+/* out = Phi(c) v, the rows of (ex1:BPc) as in orc_rotate. */
+void orc_w_rotate(uint32_t N, uint32_t r, uint64_t Q, uint64_t c, const uint64_t *v, uint64_t *out)
+{
+    for (uint32_t j = 0; j < r; j++) {
+        uint64_t e;
+        uint32_t col = phi_row(r, c, N, j, &e);
+        w_monomial_mul(e, v + (size_t)col * N, out + (size_t)j * N, N, Q);
+    }
+}
+
+/* V = v_test * floor(Q / t') (eq. equ:test-use) at the wide modulus. */
+void orc_w_test_vector(uint32_t N, uint32_t r, uint64_t Q, uint32_t t, uint32_t t_out,
+                       const uint32_t *f, uint64_t *V)
+{
+    const uint64_t M = 2ull * N * r;
+    const uint64_t dq = Q / t_out;
+    for (uint32_t b = 0; b < r; b++)
+        for (uint32_t a = 0; a < N; a++) {
+            const uint64_t p = (uint64_t)a * r + b;
+            const uint32_t val = f_ext((M - p) % M, f, t, M) % t_out;
+            V[(size_t)b * N + a] = (uint64_t)((w_u128)dq * val % Q);
+        }
+}
+
+uint32_t orc_w_gadget_shift(uint64_t Q, uint32_t log2B, uint32_t l)
+{
+    const uint32_t used = l * log2B, bq = w_bits(Q);
+    return bq > used ? bq - used : 0;
+}
+
+/* g_u = 2^(sg + u log2B) mod Q */
+uint64_t orc_w_gadget(uint64_t Q, uint32_t log2B, uint32_t l, uint32_t u)
+{
+    const uint32_t e = orc_w_gadget_shift(Q, log2B, l) + u * log2B;
+    uint64_t g = 1 % Q;
+    for (uint32_t i = 0; i < e; i++) g = (uint64_t)((w_u128)g * 2 % Q);
+    return g;
+}
+
+/* Signed digits of x in [0, Q): the centred lift rounded to a multiple of
+ * 2^sg, then l balanced base-B digits, the top one keeping the carry. */
+void orc_w_decompose(uint64_t Q, uint32_t log2B, uint32_t l, uint64_t x, int64_t *d)
+{
+    const uint32_t sg = orc_w_gadget_shift(Q, log2B, l);
+    const w_i128 B = (w_i128)1 << log2B;
+    const w_i128 xc = (x > (Q - 1) / 2) ? (w_i128)x - (w_i128)Q : (w_i128)x;
+    w_i128 y = xc;
+    if (sg) {
+        const w_i128 den = (w_i128)1 << sg, num = xc + ((w_i128)1 << (sg - 1));
+        y = num / den;
+        if (num % den != 0 && num < 0) y -= 1; /* floor */
+    }
+    for (uint32_t u = 0; u + 1 < l; u++) {
+        w_i128 dig = ((y % B) + B) % B;
+        y = (y - dig) / B;
+        if (dig >= B / 2) {
+            dig -= B;
+            y += 1;
+        }
+        d[u] = (int64_t)dig;
+    }
+    d[l - 1] = (int64_t)y;
+}
+
+/* RGSW_z(m), m in {0,1}, rows as in rgsw_encrypt, at the wide modulus. */
+static void w_rgsw_encrypt(uint32_t N, uint64_t Q, uint32_t log2B, uint32_t l, uint32_t m,
+                           const int64_t *z, const uint64_t *a, const int32_t *e, uint64_t *out)
+{
+    w_i128 *acc = (w_i128 *)malloc(sizeof(w_i128) * N);
+    for (uint32_t row = 0; row < 2 * l; row++) {
+        const uint64_t *ar = a + (size_t)row * N;
+        const int32_t *er = e + (size_t)row * N;
+        uint64_t *oa = out + ((size_t)row * 2 + 0) * N;
+        uint64_t *ob = out + ((size_t)row * 2 + 1) * N;
+        const uint64_t g = orc_w_gadget(Q, log2B, l, row % l);
+        for (uint32_t k = 0; k < N; k++) acc[k] = er[k];
+        w_nega_mac_small(acc, z, ar, N);
+        for (uint32_t k = 0; k < N; k++) {
+            oa[k] = ar[k];
+            ob[k] = w_mod(acc[k], Q);
+        }
+        if (m) {
+            if (row < l) ob[0] = (uint64_t)(((w_u128)ob[0] + g) % Q);
+            else oa[0] = (uint64_t)(((w_u128)oa[0] + g) % Q);
+        }
+    }
+    free(acc);
+}
+
+/* Bootstrapping keys at the wide modulus, same layout and key rule as
+ * orc_keygen_bsk: bsk[i][key][row][part][N], masks bsk_a in [0, Q). */
+void orc_w_keygen_bsk(uint32_t n, uint32_t N, uint64_t Q, uint32_t log2B, uint32_t l, uint32_t keys,
+                      const int32_t *s, const uint32_t *z, const uint64_t *bsk_a, const int32_t *bsk_e,
+                      uint64_t *bsk)
+{
+    int64_t *zi = (int64_t *)malloc(sizeof(int64_t) * N);
+    for (uint32_t k = 0; k < N; k++) zi[k] = (int64_t)z[k];
+    const size_t per = (size_t)2 * l * N;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t ik = 0; ik < (int64_t)n * keys; ik++) {
+        const int64_t i = ik / keys, key = ik % keys;
+        const uint32_t m = key == 0 ? (s[i] > 0 ? (uint32_t)s[i] : 0u) : (s[i] < 0 ? (uint32_t)(-s[i]) : 0u);
+        w_rgsw_encrypt(N, Q, log2B, l, m, zi, bsk_a + (size_t)ik * per, bsk_e + (size_t)ik * per,
+                       bsk + (size_t)ik * per * 2);
+    }
+    free(zi);
+}
+
+/* out = g^{-1}(in) * C (eq. def:gsw) at the wide modulus. */
+void orc_w_external_product(uint32_t N, uint64_t Q, uint32_t log2B, uint32_t l,
+                            const uint64_t *rgsw, const uint64_t *in, uint64_t *out)
+{
+    int64_t *dig = (int64_t *)malloc(sizeof(int64_t) * (size_t)2 * l * N);
+    w_i128 *acc = (w_i128 *)calloc((size_t)2 * N, sizeof(w_i128));
+    int64_t tmp[64];
+    for (uint32_t k = 0; k < N; k++) {
+        orc_w_decompose(Q, log2B, l, in[N + k], tmp);
+        for (uint32_t u = 0; u < l; u++) dig[(size_t)u * N + k] = tmp[u];
+        orc_w_decompose(Q, log2B, l, in[k], tmp);
+        for (uint32_t u = 0; u < l; u++) dig[(size_t)(l + u) * N + k] = tmp[u];
+    }
+    for (uint32_t row = 0; row < 2 * l; row++)
+        for (uint32_t part = 0; part < 2; part++)
+            w_nega_mac_small(acc + (size_t)part * N, dig + (size_t)row * N,
+                             rgsw + ((size_t)row * 2 + part) * N, N);
+    for (uint32_t k = 0; k < 2 * N; k++) out[k] = w_mod(acc[k], Q);
+    free(dig);
+    free(acc);
+}
+
+/* The blind rotation of Alg. 1 at the wide modulus (as blind_rotate above). */
+static void w_blind_rotate(uint32_t n, uint32_t N, uint64_t Q, uint32_t log2B, uint32_t l,
+                           uint32_t r, uint32_t keys, const uint64_t *bsk, const uint64_t *V,
+                           const uint32_t *ct_ms, uint32_t steps, uint64_t *acc, int parallel)
+{
+    const uint64_t M = 2ull * N * r;
+    const size_t comp = (size_t)2 * N;
+    uint64_t *rv = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)r * N);
+    uint64_t *ra = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)r * N);
+    uint64_t *rb = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)r * N);
+    uint64_t *D = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)keys * r * comp);
+
+    orc_w_rotate(N, r, Q, ct_ms[n] % M, V, rv);
+    for (uint32_t j = 0; j < r; j++) {
+        memset(acc + j * comp, 0, sizeof(uint64_t) * N);
+        memcpy(acc + j * comp + N, rv + (size_t)j * N, sizeof(uint64_t) * N);
+    }
+    for (uint32_t i = 0; i < steps && i < n; i++) {
+        for (uint32_t key = 0; key < keys; key++) {
+            const uint64_t a = ct_ms[i] % M;
+            const uint64_t c = key == 0 ? (M - a) % M : a;
+            for (uint32_t j = 0; j < r; j++) memcpy(rv + (size_t)j * N, acc + j * comp, sizeof(uint64_t) * N);
+            orc_w_rotate(N, r, Q, c, rv, ra);
+            for (uint32_t j = 0; j < r; j++) memcpy(rv + (size_t)j * N, acc + j * comp + N, sizeof(uint64_t) * N);
+            orc_w_rotate(N, r, Q, c, rv, rb);
+            uint64_t *Dk = D + (size_t)key * r * comp;
+            for (uint32_t j = 0; j < r; j++)
+                for (uint32_t k = 0; k < N; k++) {
+                    Dk[j * comp + k] = w_mod((w_i128)ra[(size_t)j * N + k] - (w_i128)acc[j * comp + k], Q);
+                    Dk[j * comp + N + k] = w_mod((w_i128)rb[(size_t)j * N + k] - (w_i128)acc[j * comp + N + k], Q);
+                }
+        }
+#pragma omp parallel for schedule(static) if (parallel)
+        for (int64_t j = 0; j < (int64_t)r; j++) {
+            uint64_t *prod = (uint64_t *)malloc(sizeof(uint64_t) * comp);
+            for (uint32_t key = 0; key < keys; key++) {
+                const uint64_t *rgsw = bsk + ((size_t)i * keys + key) * 2 * l * 2 * N;
+                orc_w_external_product(N, Q, log2B, l, rgsw, D + (size_t)key * r * comp + j * comp, prod);
+                for (uint32_t k = 0; k < 2 * N; k++)
+                    acc[j * comp + k] = (uint64_t)(((w_u128)acc[j * comp + k] + prod[k]) % Q);
+            }
+            free(prod);
+        }
+    }
+    free(rv);
+    free(ra);
+    free(rb);
+    free(D);
+}
+
+void orc_w_blind_rotate(uint32_t n, uint32_t N, uint64_t Q, uint32_t log2B, uint32_t l, uint32_t r,
+                        uint32_t keys, const uint64_t *bsk, const uint64_t *V, const uint32_t *ct_ms,
+                        uint32_t steps, uint64_t *acc)
+{
+    w_blind_rotate(n, N, Q, log2B, l, r, keys, bsk, V, ct_ms, steps, acc, 1);
+}
+
+/* round(x q_to / Q_from), half up (Sec. 2 item (9)), for Q_from up to 2^62. */
+uint64_t orc_w_modswitch(uint64_t x, uint64_t Q_from, uint64_t q_to)
+{
+    const w_u128 num = (w_u128)2 * x * q_to + Q_from;
+    return (uint64_t)((num / ((w_u128)2 * Q_from)) % q_to);
+}
+
+/* Constant-term extraction (eq. equ-sam-extr) of a wide RLWE pair. */
+void orc_w_sample_extract(uint32_t N, uint64_t Q, const uint64_t *rlwe, uint64_t *lwe)
+{
+    lwe[0] = rlwe[0];
+    for (uint32_t k = 1; k < N; k++) lwe[k] = w_neg(rlwe[N - k], Q);
+    lwe[N] = rlwe[N];
+}
+
+/* BootMMPM(ct, f) with the wide ring modulus: modulus switch q_in -> 2Nr; ACC
+ * init; n CMux steps at Q_w; extraction; each coefficient switched Q_w -> Q_ks;
+ * key switch at Q_ks; switch Q_ks -> q_out (skipped when q_out == Q_ks). */
+static void w_bootstrap_one(uint32_t n, uint32_t N, uint64_t Qw, uint32_t log2B, uint32_t l, uint32_t Qks,
+                            uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint64_t *bsk,
+                            const uint32_t *ksk, const uint64_t *V, uint32_t q_in, uint32_t q_out,
+                            const uint32_t *ct, uint32_t *out, uint32_t *ext_out, int parallel)
+{
+    const uint32_t M = 2u * N * r;
+    uint32_t *ms = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    uint64_t *acc = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)r * 2 * N);
+    uint64_t *ext = (uint64_t *)malloc(sizeof(uint64_t) * (N + 1));
+    uint32_t *ext32 = (uint32_t *)malloc(sizeof(uint32_t) * (N + 1));
+    uint32_t *ks = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+    orc_modswitch_vec(ct, n + 1, q_in, M, ms);
+    w_blind_rotate(n, N, Qw, log2B, l, r, keys, bsk, V, ms, n, acc, parallel);
+    orc_w_sample_extract(N, Qw, acc, ext);
+    for (uint32_t k = 0; k <= N; k++) ext32[k] = (uint32_t)orc_w_modswitch(ext[k], Qw, Qks);
+    orc_keyswitch(n, N, Qks, log2Bks, lks, ksk, ext32, ks);
+    if (q_out == Qks) memcpy(out, ks, sizeof(uint32_t) * (n + 1));
+    else orc_modswitch_vec(ks, n + 1, Qks, q_out, out);
+    if (ext_out) memcpy(ext_out, ext32, sizeof(uint32_t) * (N + 1));
+    free(ms);
+    free(acc);
+    free(ext);
+    free(ext32);
+    free(ks);
+}
+
+void orc_w_bootstrap(uint32_t n, uint32_t N, uint64_t Qw, uint32_t log2B, uint32_t l, uint32_t Qks,
+                     uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint64_t *bsk,
+                     const uint32_t *ksk, const uint64_t *V, uint32_t q_in, uint32_t q_out,
+                     const uint32_t *ct, uint32_t *out, uint32_t *ext_out)
+{
+    w_bootstrap_one(n, N, Qw, log2B, l, Qks, log2Bks, lks, r, keys, bsk, ksk, V, q_in, q_out, ct, out,
+                    ext_out, 1);
+}
+
+void orc_w_bootstrap_many(uint32_t n, uint32_t N, uint64_t Qw, uint32_t log2B, uint32_t l, uint32_t Qks,
+                          uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint64_t *bsk,
+                          const uint32_t *ksk, const uint64_t *V, uint32_t q_in, uint32_t q_out,
+                          const uint32_t *ct, uint64_t count, uint32_t *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < (int64_t)count; c++)
+        w_bootstrap_one(n, N, Qw, log2B, l, Qks, log2Bks, lks, r, keys, bsk, ksk, V, q_in, q_out,
+                        ct + (size_t)c * (n + 1), out + (size_t)c * (n + 1), NULL, 0);
+}

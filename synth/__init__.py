@@ -8,6 +8,7 @@ on their own.
 """
 from .draws import (  # noqa: F401
     Q_DEFAULT,
+    Q2_DEFAULT,
     CLASS_MIX,
     Params,
     PRESETS,

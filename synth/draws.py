@@ -27,6 +27,9 @@ import numpy as np
 # 2^31 - 2^17 + 1: prime, = 1 mod 2^17, so it carries negacyclic NTTs of every
 # power-of-two degree up to 2^16.
 Q_DEFAULT = 2147352577
+# 2^23 - 2^13 + 1: prime, = 1 mod 2^13; with Q_DEFAULT a ring modulus of 54 bits
+# for negacyclic NTTs up to degree 4096.
+Q2_DEFAULT = 8380417
 
 _TAGS = {
     "s": 1, "z": 2, "bsk_a": 3, "bsk_e": 4, "ksk_a": 5, "ksk_e": 6,
@@ -52,10 +55,16 @@ class Params:
     sigma: float = 3.2
     sigma_ks: float = 3.2
     ternary: bool = False  # s in {-1, 0, 1}^n with two RGSW keys per coordinate
+    Q2: int = 0       # nonzero: the blind rotation runs at the ring modulus Q * Q2
 
     @property
     def B_ks(self) -> int:
         return 1 << self.log2_Bks
+
+    @property
+    def Q_ring(self) -> int:
+        """Modulus of the accumulator and of the bootstrapping key."""
+        return self.Q * self.Q2 if self.Q2 else self.Q
 
     @property
     def keys_per_coord(self) -> int:
@@ -73,6 +82,11 @@ PRESETS = {
     "tiny": dict(params=Params(n=64, N=256, log2_B=8, l=3), t=16, t_out=16, r=2),
     "paper_shaped": dict(params=Params(n=630, N=1024, log2_B=7, l=4), t=4096, t_out=4096, r=4),
     "tfhe_shaped": dict(params=Params(n=630, N=4096, log2_B=7, l=4), t=4096, t_out=4096, r=1),
+    # The parameters of the experiments in Sec. 5: log n = 9, log N = 11, a ring
+    # modulus of 54 bits (2147352577 x 8380417), gadget 2^15 x 4, q = 2Nr with
+    # 2Nr / t = 128 (so r = t / 32, log r = log t - 5 as in Tables 1-2); t = 2^12
+    # needs r = 128.
+    "paper_margin": dict(params=Params(n=512, N=2048, log2_B=15, l=4, Q2=Q2_DEFAULT), t=4096, t_out=4096, r=128),
 }
 
 # (t, r) classes of the uneven batch and of the serving trace: q = 2Nr each.
@@ -93,7 +107,8 @@ def discrete_gaussian(rng: np.random.Generator, sigma: float, size) -> np.ndarra
 def key_draws(p: Params, seed: int) -> dict:
     """All random material of one key set.
 
-    Shapes: s (n,) int32, z (N,), bsk_a (n * K, 2l, N), bsk_e (n * K, 2l, N) with K
+    Shapes: s (n,) int32, z (N,), bsk_a (n * K, 2l, N) (uint64 in [0, Q Q2) when Q2
+    is set), bsk_e (n * K, 2l, N) with K
     keys per coordinate (1 binary, 2 ternary; key k of coordinate i at row i K + k),
     ksk_a (N, l_ks, B_ks, n), ksk_e (N, l_ks, B_ks).
     """
@@ -103,7 +118,8 @@ def key_draws(p: Params, seed: int) -> dict:
     out = {
         "s": _rng(seed, "s").integers(lo, 2, size=n).astype(np.int32),
         "z": _rng(seed, "z").integers(0, 2, size=N, dtype=np.uint32),
-        "bsk_a": _rng(seed, "bsk_a").integers(0, Q, size=(n * K, 2 * l, N), dtype=np.uint32),
+        "bsk_a": _rng(seed, "bsk_a").integers(0, p.Q_ring, size=(n * K, 2 * l, N),
+                                              dtype=np.uint64 if p.Q2 else np.uint32),
         "bsk_e": discrete_gaussian(_rng(seed, "bsk_e"), p.sigma, (n * K, 2 * l, N)),
         "ksk_a": _rng(seed, "ksk_a").integers(0, Q, size=(N, p.l_ks, p.B_ks, n), dtype=np.uint32),
         "ksk_e": discrete_gaussian(_rng(seed, "ksk_e"), p.sigma_ks, (N, p.l_ks, p.B_ks)),
