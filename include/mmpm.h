@@ -61,9 +61,26 @@ typedef struct mm_server mm_server;
  * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact; ternary: 0 for
  * a binary LWE secret (one RGSW key and one external product per step), 1 for a
  * ternary one (keys for s+ and s-, two external products per step, Alg. 1 as
- * printed).  K = 1 + ternary keys per coordinate. */
+ * printed).  K = 1 + ternary keys per coordinate.
+ *
+ * Q2 = 0 is the default.  Q2 != 0 selects a wide ring modulus Q_w = Q Q2 for
+ * the blind rotation (the parameter regime of the experiments in Sec. 5, where
+ * log Q = 54 and the gadget base is 2^15): Q2 is a second odd prime, Q2 != Q,
+ * Q2 = 1 mod 2N, Q2 < 2^31; the accumulator and the bootstrapping key hold two
+ * residues per coefficient (mod Q and mod Q2); the gadget needs log2_B <= 16,
+ * l <= 8, l * log2_B <= 62 and sg = max(0, bits(Q_w) - l log2_B).  Everything
+ * on the LWE side stays at Q: after sample extraction every coefficient is
+ * switched Q_w -> Q by rounding (round(x / Q2), Sec. 2 item (9)), then the key
+ * switch and the final switch run at Q as in the default mode.  Tables may then
+ * have r up to 1024, because the accumulator of a ciphertext lives in device
+ * memory, one (ciphertext, component) pair per workgroup and one launch per
+ * CMux step.  In this mode mm_external_product, the schedule calls
+ * (mm_autotune, mm_schedule_*) and the server return MM_EINVAL; mm_export_bsk,
+ * mm_table_export and mm_blind_rotate give uint64 values in [0, Q_w) (two
+ * words each, the low word first). */
 typedef struct {
     uint32_t n, N, Q, log2_B, l, log2_Bks, l_ks, ternary;
+    uint32_t Q2;
 } mm_params;
 
 /* The random material of a key set, drawn by the caller (host memory, read
@@ -73,13 +90,16 @@ typedef struct {
  *   bsk_a  n * K * 2l * N in [0, Q)    RGSW masks, [i][key][row][coeff]
  *   bsk_e  n * K * 2l * N small ints   RGSW errors, same layout
  *   ksk_a  N * l_ks * B_ks * n in [0,Q) key-switch masks, [i][j][v][k]
- *   ksk_e  N * l_ks * B_ks small ints  key-switch errors, [i][j][v]  */
+ *   ksk_e  N * l_ks * B_ks small ints  key-switch errors, [i][j][v]
+ *   bsk_a_wide  with Q2 != 0 only: n * K * 2l * N uint64 in [0, Q Q2), the
+ *          RGSW masks at the wide modulus (bsk_a is then not read)  */
 typedef struct {
     const int32_t *s;
     const uint32_t *z, *bsk_a;
     const int32_t *bsk_e;
     const uint32_t *ksk_a;
     const int32_t *ksk_e;
+    const uint64_t *bsk_a_wide;
 } mm_key_draws;
 
 /* Build a key set (host only; no GPU needed).
@@ -101,7 +121,8 @@ const char *mm_last_error(const mm_ctx *ctx);
 int mm_get_params(const mm_ctx *ctx, mm_params *out);
 
 /* Coefficient-form keys, for checking: bsk as [n][K][2l][2][N] (part 0 = a),
- * ksk as [N][l_ks][B_ks][n+1].  `words` is the capacity of out. */
+ * ksk as [N][l_ks][B_ks][n+1].  `words` is the capacity of out (with Q2 != 0
+ * the bsk entries are uint64 at Q Q2, two words each). */
 int mm_export_bsk(const mm_ctx *ctx, uint32_t *out, size_t words);
 int mm_export_ksk(const mm_ctx *ctx, uint32_t *out, size_t words);
 
@@ -135,7 +156,8 @@ int mm_table_info(const mm_ctx *ctx, int id, uint32_t *t, uint32_t *t_out, uint3
  * vector length r. */
 int mm_table_create_general(mm_ctx *ctx, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in,
                             const uint32_t *f, int *id);
-/* The scaled test vector of table id as [r][N]. */
+/* The scaled test vector of table id as [r][N] (uint64 at Q Q2, two words
+ * per entry, when Q2 != 0). */
 int mm_table_export(const mm_ctx *ctx, int id, uint32_t *V, size_t words);
 
 /* LWE encryption under s (Sec. 2 item (8)): ct_c = (a_c, <a_c, s> + m_c floor(q/t)
@@ -170,7 +192,8 @@ int mm_modswitch(mm_ctx *ctx, const uint32_t *in, size_t count, uint32_t q_from,
 /* Blind rotation only: for ciphertext c (at its table's q_in), the accumulator
  * after the modulus switch, the initialisation and the first `steps` CMux steps
  * (steps <= n).  acc_out receives, for each c in order, r_c x 2 x N words
- * ([component][part][coeff], part 0 = a). */
+ * ([component][part][coeff], part 0 = a); with Q2 != 0 each entry is a uint64
+ * at Q Q2 (two words, so 2 r_c x 2 x N words per ciphertext). */
 int mm_blind_rotate(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
                     uint32_t steps, uint32_t *acc_out, uint32_t flags, void *stream);
 

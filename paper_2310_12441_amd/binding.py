@@ -36,12 +36,12 @@ class MMError(RuntimeError):
 
 
 class Params(C.Structure):
-    _fields_ = [(f, C.c_uint32) for f in ("n", "N", "Q", "log2_B", "l", "log2_Bks", "l_ks", "ternary")]
+    _fields_ = [(f, C.c_uint32) for f in ("n", "N", "Q", "log2_B", "l", "log2_Bks", "l_ks", "ternary", "Q2")]
 
 
 class KeyDraws(C.Structure):
     _fields_ = [("s", C.c_void_p), ("z", C.c_void_p), ("bsk_a", C.c_void_p), ("bsk_e", C.c_void_p),
-                ("ksk_a", C.c_void_p), ("ksk_e", C.c_void_p)]
+                ("ksk_a", C.c_void_p), ("ksk_e", C.c_void_p), ("bsk_a_wide", C.c_void_p)]
 
 
 def _load():
@@ -134,12 +134,20 @@ class Context:
     """One key set (mm_ctx)."""
 
     def __init__(self, params, draws):
+        self.wide = bool(getattr(params, "Q2", 0))
         p = Params(params.n, params.N, params.Q, params.log2_B, params.l, params.log2_Bks, params.l_ks,
-                   1 if getattr(params, "ternary", False) else 0)
+                   1 if getattr(params, "ternary", False) else 0, getattr(params, "Q2", 0))
         self.params = params
         self._lib = lib  # held so that close() still works while the interpreter shuts down
-        self._keep = {k: (_i32(v) if k.endswith("_e") or k == "s" else _u32(v)) for k, v in draws.items()}
-        d = KeyDraws(*(self._keep[k].ctypes.data_as(C.c_void_p) for k in ("s", "z", "bsk_a", "bsk_e", "ksk_a", "ksk_e")))
+        keep = {}
+        for k, v in draws.items():
+            if k == "bsk_a" and self.wide:
+                keep["bsk_a_wide"] = np.ascontiguousarray(v, dtype=np.uint64)
+            else:
+                keep[k] = _i32(v) if k.endswith("_e") or k == "s" else _u32(v)
+        self._keep = keep
+        ptr = lambda k: keep[k].ctypes.data_as(C.c_void_p) if k in keep else None
+        d = KeyDraws(*(ptr(k) for k in ("s", "z", "bsk_a", "bsk_e", "ksk_a", "ksk_e", "bsk_a_wide")))
         h = C.c_void_p()
         rc = lib.mm_keygen(C.byref(p), C.byref(d), C.byref(h))
         self._keep = None
@@ -164,8 +172,8 @@ class Context:
     def export_bsk(self):
         p = self.params
         K = 2 if getattr(p, "ternary", False) else 1
-        out = np.empty((p.n * K, 2 * p.l, 2, p.N), dtype=np.uint32)
-        self._check(lib.mm_export_bsk(self.h, out.ctypes.data_as(C.c_void_p), out.size))
+        out = np.empty((p.n * K, 2 * p.l, 2, p.N), dtype=np.uint64 if self.wide else np.uint32)
+        self._check(lib.mm_export_bsk(self.h, out.ctypes.data_as(C.c_void_p), out.nbytes // 4))
         return out
 
     def export_ksk(self):
@@ -197,8 +205,8 @@ class Context:
 
     def table_export(self, tid):
         r = self.table_info(tid)[2]
-        V = np.empty((r, self.params.N), dtype=np.uint32)
-        self._check(lib.mm_table_export(self.h, tid, V.ctypes.data_as(C.c_void_p), V.size))
+        V = np.empty((r, self.params.N), dtype=np.uint64 if self.wide else np.uint32)
+        self._check(lib.mm_table_export(self.h, tid, V.ctypes.data_as(C.c_void_p), V.nbytes // 4))
         return V
 
     def encrypt(self, q, t, m, mask, err):
@@ -252,9 +260,13 @@ class Context:
         ids = _i32(np.atleast_1d(table_ids))
         steps = self.params.n if steps is None else steps
         words = sum(self.table_info(int(t))[2] * 2 * self.params.N for t in ids)
+        if self.wide:
+            words *= 2  # uint64 entries
         i, o, flags, st = self._io(ct, (words,), out)
         self._check(lib.mm_blind_rotate(self.h, ids.ctypes.data_as(C.c_void_p), i.ptr, ids.size, steps, o.ptr,
                                         flags, st))
+        if self.wide and not o.dev:
+            return o.arr.view(np.uint64)
         return o.arr
 
     def external_product(self, i_key, rlwe, out=None):

@@ -70,7 +70,19 @@ int mm_export_bsk(const mm_ctx *ctx, uint32_t *out, size_t words)
 {
     if (!ctx || !out) return MM_EINVAL;
     if (words < ctx->bsk.size()) return MM_EINVAL;
-    std::memcpy(out, ctx->bsk.data(), ctx->bsk.size() * 4);
+    if (!ctx->wide) {
+        std::memcpy(out, ctx->bsk.data(), ctx->bsk.size() * 4);
+        return MM_OK;
+    }
+    // [ik][limb][row][part][N] residues -> [ik][row][part][N] uint64 at Q Q2
+    const size_t N = ctx->p.N, per = (size_t)2 * ctx->p.l * 2 * N;  // words of one limb of one key
+    const size_t keys = ctx->bsk.size() / (2 * per);
+    for (size_t ik = 0; ik < keys; ik++)
+        for (size_t w = 0; w < per; w++) {
+            const uint64_t v = mm::crt2(ctx->bsk[(ik * 2 + 0) * per + w], ctx->bsk[(ik * 2 + 1) * per + w],
+                                        ctx->p.Q, ctx->p.Q2);
+            std::memcpy(out + 2 * (ik * per + w), &v, 8);
+        }
     return MM_OK;
 }
 
@@ -120,7 +132,16 @@ int mm_table_export(const mm_ctx *ctx, int id, uint32_t *V, size_t words)
     if (!ctx || !V || id < 0 || (size_t)id >= ctx->tables.size()) return MM_EINVAL;
     const mm::Table &tb = ctx->tables[id];
     if (tb.V.empty() || words < tb.V.size()) return MM_EINVAL;
-    std::memcpy(V, tb.V.data(), tb.V.size() * 4);
+    if (!ctx->wide) {
+        std::memcpy(V, tb.V.data(), tb.V.size() * 4);
+        return MM_OK;
+    }
+    const size_t N = ctx->p.N;  // [r][limb][N] -> [r][N] uint64
+    for (size_t b = 0; b < tb.r; b++)
+        for (size_t a = 0; a < N; a++) {
+            const uint64_t v = mm::crt2(tb.V[(b * 2 + 0) * N + a], tb.V[(b * 2 + 1) * N + a], ctx->p.Q, ctx->p.Q2);
+            std::memcpy(V + 2 * (b * N + a), &v, 8);
+        }
     return MM_OK;
 }
 

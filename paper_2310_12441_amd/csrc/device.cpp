@@ -68,6 +68,55 @@ static uint32_t neg_inv_2_32(uint32_t Q)
 
 static uint32_t to_mont(uint32_t x, uint32_t Q) { return (uint32_t)(((uint64_t)x << 32) % Q); }
 
+// BSK in the NTT domain for one prime, times 2^32 / N (Montgomery form with the
+// inverse NTT's 1/N folded in), and its digit-offset correction: the blind
+// rotation feeds the gadget digits shifted by +B/2 (non-negative, one bit-field
+// extract each), i.e. each digit polynomial gains (B/2)(1 + x + ... + x^(N-1));
+// in the NTT domain that adds (B/2) NTT(1 + ... + x^(N-1)) sum_{key,row} K/N to
+// each output part, and the accumulator starts from minus that sum.
+// coeff is [n][K][2l][2][N]; kb has the same layout, corr is [n][2][N].
+static void ntt_domain_keys(const mm_ctx &c, const NttTables &T, const uint32_t *coeff, std::vector<uint32_t> &kb,
+                            std::vector<uint32_t> &corr)
+{
+    const mm_params &p = c.p;
+    const uint32_t N = p.N, Q = T.Q;
+    const size_t polys = (size_t)p.n * c.keys * 2 * p.l * 2;
+    kb.assign(polys * N, 0);
+    const uint32_t scale = to_mont(T.n_inv, Q);
+    parallel_for((int64_t)polys, [&](int64_t t) {
+        uint32_t *dst = &kb[(size_t)t * N];
+        std::memcpy(dst, coeff + (size_t)t * N, sizeof(uint32_t) * N);
+        T.forward(dst);
+        for (uint32_t k = 0; k < N; k++) dst[k] = mulmod(dst[k], scale, Q);
+    });
+    const uint32_t K = c.keys, rows = 2 * p.l;
+    corr.assign((size_t)p.n * 2 * N, 0);
+    const uint32_t inv_r = [&] {  // 2^-32 mod Q
+        uint64_t x = to_mont(1, Q), e = Q - 2, r = 1;
+        while (e) {
+            if (e & 1) r = mulmod((uint32_t)r, (uint32_t)x, Q);
+            x = mulmod((uint32_t)x, (uint32_t)x, Q);
+            e >>= 1;
+        }
+        return (uint32_t)r;
+    }();
+    const uint32_t half_b = mulmod(1u << (p.log2_B - 1), inv_r, Q);
+    std::vector<uint32_t> ones(N, 1u);
+    T.forward(ones.data());
+    parallel_for((int64_t)p.n * 2, [&](int64_t ip) {
+        const size_t i = (size_t)ip / 2, part = (size_t)ip % 2;
+        uint32_t *dst = &corr[(i * 2 + part) * N];
+        for (uint32_t k = 0; k < N; k++) {
+            uint64_t sum = 0;
+            for (uint32_t key = 0; key < K; key++)
+                for (uint32_t row = 0; row < rows; row++)
+                    sum += kb[((((size_t)i * K + key) * rows + row) * 2 + part) * N + k];
+            const uint32_t cval = mulmod(mulmod((uint32_t)(sum % Q), half_b, Q), ones[k], Q);
+            dst[k] = cval ? Q - cval : 0;
+        }
+    });
+}
+
 void device_init(mm_ctx &c, int id)
 {
     if (c.dev && c.dev->id == id) return;
@@ -83,56 +132,19 @@ void device_init(mm_ctx &c, int id)
     const mm_params &p = c.p;
     const uint32_t N = p.N, Q = p.Q;
     MM_REQUIRE(dev::device_supports_n(N), "device path supports N in {256, 512, ..., 8192}");
+    MM_REQUIRE(!c.wide || N <= 4096, "the wide-modulus path supports N in {256, ..., 4096}");
     d->qn = neg_inv_2_32(Q);
     // 2^64 / N mod Q, for the pointwise product of two forward NTTs
     d->c_fix = mulmod(to_mont(to_mont(1, Q), Q), c.ntt.n_inv, Q);
 
-    std::vector<uint32_t> twf(N), twi(N);
-    for (uint32_t k = 0; k < N; k++) {
-        twf[k] = to_mont(c.ntt.fwd[k], Q);
-        twi[k] = to_mont(c.ntt.inv[k], Q);
-    }
-    // BSK in the NTT domain, times 2^32 / N (Montgomery form with the inverse NTT's 1/N folded in)
-    const size_t polys = (size_t)p.n * c.keys * 2 * p.l * 2;
-    std::vector<uint32_t> kb(polys * N);
-    const uint32_t scale = to_mont(c.ntt.n_inv, Q);
-    parallel_for((int64_t)polys, [&](int64_t t) {
-        uint32_t *dst = &kb[(size_t)t * N];
-        std::memcpy(dst, &c.bsk[(size_t)t * N], sizeof(uint32_t) * N);
-        c.ntt.forward(dst);
-        for (uint32_t k = 0; k < N; k++) dst[k] = mulmod(dst[k], scale, Q);
-    });
-    // Digit-offset correction per coordinate i: the blind rotation feeds the
-    // gadget digits shifted by +B/2 (non-negative, one bit-field extract each),
-    // i.e. each digit polynomial gains (B/2)(1 + x + ... + x^(N-1)); in the NTT
-    // domain that adds (B/2) NTT(1 + ... + x^(N-1)) sum_{key,row} K/N to each
-    // output part, and the accumulator starts from minus that sum.
-    const uint32_t K = c.keys, rows = 2 * p.l;
-    std::vector<uint32_t> corr((size_t)p.n * 2 * N);
-    const uint32_t inv_r = [&] {  // 2^-32 mod Q
-        uint64_t x = to_mont(1, Q), e = Q - 2, r = 1;
-        while (e) {
-            if (e & 1) r = mulmod((uint32_t)r, (uint32_t)x, Q);
-            x = mulmod((uint32_t)x, (uint32_t)x, Q);
-            e >>= 1;
-        }
-        return (uint32_t)r;
-    }();
-    const uint32_t half_b = mulmod(1u << (p.log2_B - 1), inv_r, Q);
-    std::vector<uint32_t> ones(N, 1u);
-    c.ntt.forward(ones.data());
-    parallel_for((int64_t)p.n * 2, [&](int64_t ip) {
-        const size_t i = (size_t)ip / 2, part = (size_t)ip % 2;
-        uint32_t *dst = &corr[(i * 2 + part) * N];
+    auto twiddles = [&](const NttTables &T, std::vector<uint32_t> &twf, std::vector<uint32_t> &twi) {
+        twf.resize(N);
+        twi.resize(N);
         for (uint32_t k = 0; k < N; k++) {
-            uint64_t sum = 0;
-            for (uint32_t key = 0; key < K; key++)
-                for (uint32_t row = 0; row < rows; row++)
-                    sum += kb[((((size_t)i * K + key) * rows + row) * 2 + part) * N + k];
-            const uint32_t cval = mulmod(mulmod((uint32_t)(sum % Q), half_b, Q), ones[k], Q);
-            dst[k] = cval ? Q - cval : 0;
+            twf[k] = to_mont(T.fwd[k], T.Q);
+            twi[k] = to_mont(T.inv[k], T.Q);
         }
-    });
+    };
     auto upload = [&](uint32_t **dst, const uint32_t *src, size_t words) {
         if (hipMalloc((void **)dst, words * 4) != hipSuccess) {
             *dst = nullptr;
@@ -140,8 +152,33 @@ void device_init(mm_ctx &c, int id)
         }
         HIPC(hipMemcpy(*dst, src, words * 4, hipMemcpyHostToDevice));
     };
+    std::vector<uint32_t> twf, twi;
+    twiddles(c.ntt, twf, twi);
     upload(&d->twf, twf.data(), N);
     upload(&d->twi, twi.data(), N);
+    std::vector<uint32_t> kb, corr;
+    if (!c.wide) {
+        ntt_domain_keys(c, c.ntt, c.bsk.data(), kb, corr);
+    } else {
+        // two primes: [n][K][prime][2l][2][N] keys, [n][prime][2][N] corrections
+        const size_t per = (size_t)2 * p.l * 2 * N, nk = (size_t)p.n * c.keys;
+        std::vector<uint32_t> one(nk * per), kbp, corrp;
+        kb.assign(nk * 2 * per, 0);
+        corr.assign((size_t)p.n * 2 * 2 * N, 0);
+        const NttTables *T[2] = {&c.ntt, &c.ntt2};
+        for (size_t pr = 0; pr < 2; pr++) {
+            for (size_t ik = 0; ik < nk; ik++)
+                std::memcpy(&one[ik * per], &c.bsk[(ik * 2 + pr) * per], per * 4);
+            ntt_domain_keys(c, *T[pr], one.data(), kbp, corrp);
+            for (size_t ik = 0; ik < nk; ik++) std::memcpy(&kb[(ik * 2 + pr) * per], &kbp[ik * per], per * 4);
+            for (size_t i = 0; i < p.n; i++)
+                std::memcpy(&corr[(i * 2 + pr) * 2 * N], &corrp[i * 2 * N], 2 * N * 4);
+        }
+        twiddles(c.ntt2, twf, twi);
+        upload(&d->twf2, twf.data(), N);
+        upload(&d->twi2, twi.data(), N);
+        d->qn2 = neg_inv_2_32(p.Q2);
+    }
     upload(&d->bsk, kb.data(), kb.size());
     upload(&d->bsk_corr, corr.data(), corr.size());
     upload(&d->ksk, c.ksk.data(), c.ksk.size());
@@ -421,31 +458,95 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
 
 static int br_grid(const Device &d, int groups, int gw) { return std::min(groups, d.num_cu * (gw == 4 ? 2 : 1)); }
 
+// Output modulus per ciphertext: q_out, or each table's q_in when q_out = 0
+// (a scalar when they agree, else a device vector written on st).
+static const uint32_t *resolve_q_out(const mm_ctx &c, Device &d, const int *ids, size_t count, uint32_t &q_out,
+                                     hipStream_t st)
+{
+    if (q_out != 0) return nullptr;
+    bool same = true;
+    for (size_t i = 1; i < count; i++) same &= c.tables[ids[i]].q_in == c.tables[ids[0]].q_in;
+    if (same) {
+        q_out = c.tables[ids[0]].q_in;
+        return nullptr;
+    }
+    uint32_t *h = (uint32_t *)pinned(d, 1, count * 4);
+    for (size_t i = 0; i < count; i++) h[i] = c.tables[ids[i]].q_in;
+    uint32_t *dq = (uint32_t *)ws(d, WS_QOUT, count * 4);
+    HIPC(hipMemcpyAsync(dq, h, count * 4, hipMemcpyHostToDevice, st));
+    HIPC(hipEventRecord(d.pin[1].ev, st));
+    return dq;
+}
+
+// The instantiated graph of a launch sequence, captured on first use of its key.
+static hipGraphExec_t graph_for(Device &d, const std::string &k, const std::function<void(hipStream_t)> &body)
+{
+    for (auto &g : d.graphs)
+        if (g.key == k) return g.exec;
+    hipGraph_t graph;
+    hipGraphExec_t exec = nullptr;
+    HIPC(hipStreamBeginCapture(d.own, hipStreamCaptureModeThreadLocal));
+    body(d.own);
+    HIPC(hipStreamEndCapture(d.own, &graph));
+    HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    HIPC(hipGraphDestroy(graph));
+    if (d.graphs.size() >= 12) {
+        hipGraphExecDestroy(d.graphs.front().exec);
+        d.graphs.erase(d.graphs.begin());
+    }
+    d.graphs.push_back({k, exec});
+    return exec;
+}
+
+// Run a blind-rotation part and a key-switch part on st: eager, one graph, or
+// (with timing on) two graphs with HIP events around each.
+static void run_sequence(Device &d, const std::string &key, bool use_graph, hipStream_t st,
+                         const std::function<void(hipStream_t)> &br, const std::function<void(hipStream_t)> &ks)
+{
+    const bool timed = d.timing;
+    if (!use_graph) {
+        if (timed) HIPC(hipEventRecord(d.tev[0], st));
+        br(st);
+        if (timed) HIPC(hipEventRecord(d.tev[1], st));
+        ks(st);
+        if (timed) HIPC(hipEventRecord(d.tev[2], st));
+        HIPC(hipGetLastError());
+        return;
+    }
+    if (!timed) {
+        hipGraphExec_t g = graph_for(d, key + "/all", [&](hipStream_t s) {
+            br(s);
+            ks(s);
+        });
+        HIPC(hipGraphLaunch(g, st));
+    } else {
+        hipGraphExec_t g1 = graph_for(d, key + "/br", br);
+        hipGraphExec_t g2 = graph_for(d, key + "/ks", ks);
+        HIPC(hipEventRecord(d.tev[0], st));
+        HIPC(hipGraphLaunch(g1, st));
+        HIPC(hipEventRecord(d.tev[1], st));
+        HIPC(hipGraphLaunch(g2, st));
+        HIPC(hipEventRecord(d.tev[2], st));
+    }
+}
+
+static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
+                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st);
+
 // The batched path for ciphertexts already on the device.
 static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
                             uint32_t q_out, bool use_graph, hipStream_t st, const Sched *force = nullptr)
 {
+    if (c.wide) {
+        bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st);
+        return;
+    }
     const uint32_t N = c.p.N;
     const Sched S = force ? *force : schedule_for(c, d, ids, count);
     auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw);
     const int groups = (int)(tasks.size() / S.gw);
-    // per-ciphertext output modulus
-    const uint32_t *qv = nullptr;
     uint32_t q_scalar = q_out;
-    if (q_out == 0) {
-        bool same = true;
-        for (size_t i = 1; i < count; i++) same &= c.tables[ids[i]].q_in == c.tables[ids[0]].q_in;
-        if (same) {
-            q_scalar = c.tables[ids[0]].q_in;
-        } else {
-            uint32_t *h = (uint32_t *)pinned(d, 1, count * 4);
-            for (size_t i = 0; i < count; i++) h[i] = c.tables[ids[i]].q_in;
-            uint32_t *dq = (uint32_t *)ws(d, WS_QOUT, count * 4);
-            HIPC(hipMemcpyAsync(dq, h, count * 4, hipMemcpyHostToDevice, st));
-            HIPC(hipEventRecord(d.pin[1].ev, st));
-            qv = dq;
-        }
-    }
+    const uint32_t *qv = resolve_q_out(c, d, ids, count, q_scalar, st);
     // allocate every buffer before a capture
     uint32_t *ext = (uint32_t *)ws(d, WS_EXT, count * (N + 1) * 4);
     uint64_t *part = (uint64_t *)ws(d, WS_PART, ks_part_words(c, S.ks, count) * 8);
@@ -460,59 +561,148 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
     A.acc_state = nullptr;
     const int grid = br_grid(d, groups, S.gw);
 
-    const bool timed = d.timing;
-    auto enqueue_br = [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s); };
-    auto enqueue_ks = [&](hipStream_t s) {
-        enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, S.ks, part, s);
-    };
-    if (!use_graph) {
-        if (timed) HIPC(hipEventRecord(d.tev[0], st));
-        enqueue_br(st);
-        if (timed) HIPC(hipEventRecord(d.tev[1], st));
-        enqueue_ks(st);
-        if (timed) HIPC(hipEventRecord(d.tev[2], st));
-        HIPC(hipGetLastError());
-        return;
-    }
     const std::string key = std::to_string(count) + "/" + std::to_string(groups) + "/" + std::to_string(S.gw) + "/" +
                             std::to_string(S.ks.cpw) + "/" + std::to_string(S.ks.P) + "/" + std::to_string(q_scalar) +
                             "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
                             std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
-    // One graph holds the whole launch sequence; with timing on, the blind
-    // rotation and the key switch are two graphs so that events can sit
-    // between them on the stream.
-    auto get_graph = [&](const std::string &k, const std::function<void(hipStream_t)> &body) {
-        for (auto &g : d.graphs)
-            if (g.key == k) return g.exec;
-        hipGraph_t graph;
-        hipGraphExec_t exec = nullptr;
-        HIPC(hipStreamBeginCapture(d.own, hipStreamCaptureModeThreadLocal));
-        body(d.own);
-        HIPC(hipStreamEndCapture(d.own, &graph));
-        HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        HIPC(hipGraphDestroy(graph));
-        if (d.graphs.size() >= 12) {
-            hipGraphExecDestroy(d.graphs.front().exec);
-            d.graphs.erase(d.graphs.begin());
-        }
-        d.graphs.push_back({k, exec});
-        return exec;
-    };
-    if (!timed) {
-        hipGraphExec_t g = get_graph(key + "/all", [&](hipStream_t s) {
-            enqueue_br(s);
-            enqueue_ks(s);
-        });
-        HIPC(hipGraphLaunch(g, st));
-    } else {
-        hipGraphExec_t g1 = get_graph(key + "/br", enqueue_br);
-        hipGraphExec_t g2 = get_graph(key + "/ks", enqueue_ks);
-        HIPC(hipEventRecord(d.tev[0], st));
-        HIPC(hipGraphLaunch(g1, st));
-        HIPC(hipEventRecord(d.tev[1], st));
-        HIPC(hipGraphLaunch(g2, st));
-        HIPC(hipEventRecord(d.tev[2], st));
+    run_sequence(
+        d, key, use_graph, st, [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s); },
+        [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, S.ks, part, s); });
+}
+
+// ------------------------------------------------------------------ wide ring modulus
+
+static dev::WideArgs wide_args(const mm_ctx &c, const Device &d)
+{
+    const mm_params &p = c.p;
+    dev::WideArgs A{};
+    A.ct_stride = p.n + 1;
+    A.Q[0] = p.Q;
+    A.Q[1] = p.Q2;
+    A.qn[0] = d.qn;
+    A.qn[1] = d.qn2;
+    A.log2B = p.log2_B;
+    A.l = p.l;
+    A.sg = c.sg;
+    A.crt_cq = (p.Q + p.Q2 - 1) / p.Q2 * p.Q2;
+    A.crt_inv = to_mont(powmod(p.Q % p.Q2, p.Q2 - 2, p.Q2), p.Q2);
+    A.Qw = c.Qw;
+    A.goff = 0;
+    for (uint32_t u = 0; u < p.l; u++) A.goff += (uint64_t)(1u << (p.log2_B - 1)) << (u * p.log2_B);
+    A.bsk = d.bsk;
+    A.bsk_corr = d.bsk_corr;
+    A.twf0 = d.twf;
+    A.twi0 = d.twi;
+    A.twf1 = d.twf2;
+    A.twi1 = d.twi2;
+    A.tv = d.tv;
+    return A;
+}
+
+// One task per (ciphertext, component); accumulators of 4N words per component
+// laid out ciphertext after ciphertext.  Returns the total accumulator words.
+static uint64_t wide_tasks(const mm_ctx &c, const int *ids, size_t count, std::vector<dev::WideTask> &tasks,
+                           std::vector<uint64_t> &offs)
+{
+    const uint64_t N = c.p.N;
+    uint64_t words = 0;
+    tasks.clear();
+    offs.resize(count);
+    for (size_t i = 0; i < count; i++) {
+        const Table &tb = c.tables[ids[i]];
+        offs[i] = words;
+        for (uint32_t j = 0; j < tb.r; j++)
+            tasks.push_back({(int32_t)i, j, tb.r, tb.q_in, (uint32_t)tb.dev_offset, 0, words});
+        words += (uint64_t)tb.r * 4 * N;
     }
+    return words;
+}
+
+// Upload the task list and the per-ciphertext offsets through pinned staging.
+static void upload_wide(Device &d, const std::vector<dev::WideTask> &tasks, const std::vector<uint64_t> &offs,
+                        dev::WideTask **dt, uint64_t **doff, hipStream_t st)
+{
+    const size_t tb = tasks.size() * sizeof(dev::WideTask), ob = offs.size() * 8;
+    char *h = (char *)pinned(d, 0, tb + ob);
+    std::memcpy(h, tasks.data(), tb);
+    std::memcpy(h + tb, offs.data(), ob);
+    *dt = (dev::WideTask *)ws(d, WS_TASKS, tb);
+    *doff = (uint64_t *)ws(d, WS_WOFF, std::max<size_t>(ob, 8));
+    HIPC(hipMemcpyAsync(*dt, h, tb, hipMemcpyHostToDevice, st));
+    if (ob) HIPC(hipMemcpyAsync(*doff, h + tb, ob, hipMemcpyHostToDevice, st));
+    HIPC(hipEventRecord(d.pin[0].ev, st));
+}
+
+// ACC init and `steps` CMux launches; returns the buffer holding the result.
+static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_t *buf0, uint32_t *buf1,
+                                       uint32_t num_tasks, uint32_t steps, hipStream_t s)
+{
+    const uint32_t N = c.p.N;
+    uint32_t *buf[2] = {buf0, buf1};
+    A.acc_wr = buf[0];
+    dev::launch_wide_init(N, A, num_tasks, s);
+    for (uint32_t i = 0; i < steps; i++) {
+        A.step = i;
+        A.acc_rd = buf[i & 1];
+        A.acc_wr = buf[(i + 1) & 1];
+        dev::launch_wide_step(N, c.keys, A, num_tasks, s);
+    }
+    return buf[steps & 1];
+}
+
+static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
+                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st)
+{
+    const uint32_t N = c.p.N;
+    std::vector<dev::WideTask> tasks;
+    std::vector<uint64_t> offs;
+    const uint64_t words = wide_tasks(c, ids, count, tasks, offs);
+    uint32_t q_scalar = q_out;
+    const uint32_t *qv = resolve_q_out(c, d, ids, count, q_scalar, st);
+    const KsSched ks = ks_default(c, d, count);
+    uint32_t *ext = (uint32_t *)ws(d, WS_EXT, count * (N + 1) * 4);
+    uint64_t *part = (uint64_t *)ws(d, WS_PART, ks_part_words(c, ks, count) * 8);
+    uint32_t *acc0 = (uint32_t *)ws(d, WS_ACC, words * 4);
+    uint32_t *acc1 = (uint32_t *)ws(d, WS_ACC2, words * 4);
+    dev::WideTask *dt;
+    uint64_t *doff;
+    upload_wide(d, tasks, offs, &dt, &doff, st);
+    dev::WideArgs A = wide_args(c, d);
+    A.tasks = dt;
+    A.ct_in = d_in;
+    const uint32_t nt = (uint32_t)tasks.size();
+    const std::string key = "wide/" + std::to_string(count) + "/" + std::to_string(nt) + "/" +
+                            std::to_string(ks.cpw) + "/" + std::to_string(ks.P) + "/" + std::to_string(q_scalar) +
+                            "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
+                            std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
+    run_sequence(
+        d, key, use_graph, st,
+        [&](hipStream_t s) {
+            dev::WideArgs B = A;
+            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s);
+            dev::launch_wide_extract(N, B, doff, count, ext, s);
+        },
+        [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, ks, part, s); });
+}
+
+static void blind_rotate_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
+                              uint32_t steps, uint32_t *d_acc, hipStream_t st)
+{
+    std::vector<dev::WideTask> tasks;
+    std::vector<uint64_t> offs;
+    const uint64_t words = wide_tasks(c, ids, count, tasks, offs);
+    uint32_t *acc0 = (uint32_t *)ws(d, WS_ACC, words * 4);
+    uint32_t *acc1 = (uint32_t *)ws(d, WS_ACC2, words * 4);
+    dev::WideTask *dt;
+    uint64_t *doff;
+    upload_wide(d, tasks, offs, &dt, &doff, st);
+    dev::WideArgs A = wide_args(c, d);
+    A.tasks = dt;
+    A.ct_in = d_in;
+    const uint32_t nt = (uint32_t)tasks.size();
+    A.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, steps, st);
+    dev::launch_wide_export(c.p.N, A, nt, d_acc, st);
+    HIPC(hipGetLastError());
 }
 
 void run_bootstrap(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count, uint32_t *ct_out, uint32_t q_out,
@@ -578,6 +768,12 @@ void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t c
         words += (uint64_t)c.tables[ids[i]].r * 2 * N;
     }
     const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * (c.p.n + 1), dptr, st);
+    if (c.wide) {  // uint64 entries: two words each
+        uint32_t *d_out = stage_out(d, WS_OUT, acc_out, 2 * words, dptr);
+        blind_rotate_wide(c, d, ids, d_in, count, steps, d_out, st);
+        finish_out(acc_out, d_out, 2 * words, dptr, st);
+        return;
+    }
     uint32_t *d_acc = stage_out(d, WS_ACC, acc_out, words, dptr);
     auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_STORE, 0, off);
     dev::WaveTask *dt = upload_tasks(d, tasks, st);
@@ -595,6 +791,7 @@ void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t c
 void run_external_product(mm_ctx &c, uint32_t i, const uint32_t *in, size_t count, uint32_t *out, uint32_t flags,
                           void *stream)
 {
+    MM_REQUIRE(!c.wide, "mm_external_product is not available with a wide ring modulus");
     MM_REQUIRE(i < c.p.n * c.keys, "key index must be < K n");
     if (count == 0) return;
     Device &d = ensure_device(c);
@@ -692,6 +889,7 @@ void last_timing(mm_ctx &c, float *br_ms, float *ks_ms)
 
 int schedule_count(mm_ctx &c, const int *ids, size_t count)
 {
+    MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no schedule calls)");
     MM_REQUIRE(check_ids(c, ids, count) == 0, "schedules are per nega-cyclic table batch");
     MM_REQUIRE(count > 0, "empty batch");
     Device &d = ensure_device(c);
@@ -721,6 +919,7 @@ void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int 
 // remember the fastest combination for the batch shape.
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
 {
+    MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no autotuning)");
     MM_REQUIRE(check_ids(c, ids, count) == 0, "autotuning takes nega-cyclic tables");
     MM_REQUIRE(count > 0, "empty batch");
     Device &d = ensure_device(c);

@@ -20,7 +20,11 @@ namespace mm {
             throw ::mm::Error(MM_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
     } while (0)
 
-enum WsSlot { WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_GEN1, WS_GEN2, WS_GENQ, WS_COUNT };
+enum WsSlot {
+    WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_GEN1, WS_GEN2, WS_GENQ,
+    WS_ACC2, WS_WOFF,  // wide modulus: second accumulator buffer, per-ciphertext accumulator offsets
+    WS_COUNT
+};
 
 struct DevBuf {
     void *p = nullptr;
@@ -37,6 +41,7 @@ struct Device {
     int id = -1, num_cu = 0;
     uint32_t qn = 0, c_fix = 0;
     uint32_t *bsk = nullptr, *bsk_corr = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
+    uint32_t *twf2 = nullptr, *twi2 = nullptr, qn2 = 0;  // second prime of a wide ring modulus
     size_t tv_words = 0, tables_uploaded = 0;
     DevBuf ws[WS_COUNT];
     PinBuf pin[2];
@@ -63,7 +68,8 @@ struct Device {
             if (b.p) hipHostFree(b.p);
             if (b.ev) hipEventDestroy(b.ev);
         }
-        for (void *p : {(void *)bsk, (void *)bsk_corr, (void *)ksk, (void *)twf, (void *)twi, (void *)tv})
+        for (void *p : {(void *)bsk, (void *)bsk_corr, (void *)ksk, (void *)twf, (void *)twi, (void *)tv,
+                        (void *)twf2, (void *)twi2})
             if (p) hipFree(p);
         for (auto &e : tev)
             if (e) hipEventDestroy(e);

@@ -58,6 +58,13 @@ uint32_t bitrev(uint32_t x, uint32_t bits)
     return r;
 }
 
+uint64_t crt2(uint32_t x1, uint32_t x2, uint32_t Q1, uint32_t Q2)
+{
+    const uint32_t inv = powmod(Q1 % Q2, Q2 - 2, Q2);  // Q1^-1 mod Q2
+    const uint32_t d = submod(x2, x1 % Q2, Q2);
+    return (uint64_t)x1 + (uint64_t)Q1 * mulmod(d, inv, Q2);
+}
+
 void NttTables::build(uint32_t N_, uint32_t Q_)
 {
     N = N_;
@@ -114,8 +121,20 @@ void validate_params(const mm_params &p)
     MM_REQUIRE(p.Q > 2 && p.Q < (1u << 31), "Q must be below 2^31");
     MM_REQUIRE((p.Q - 1) % (2 * p.N) == 0, "Q must be 1 mod 2N");
     MM_REQUIRE(is_prime(p.Q), "Q must be prime");
-    MM_REQUIRE(p.log2_B >= 1 && p.log2_B <= 15 && p.l >= 1 && p.l * p.log2_B <= 32 && p.l <= 8,
-               "gadget needs 1 <= log2_B <= 15, 1 <= l <= 8, l*log2_B <= 32");
+    if (p.Q2 == 0) {
+        MM_REQUIRE(p.log2_B >= 1 && p.log2_B <= 15 && p.l >= 1 && p.l * p.log2_B <= 32 && p.l <= 8,
+                   "gadget needs 1 <= log2_B <= 15, 1 <= l <= 8, l*log2_B <= 32");
+    } else {
+        MM_REQUIRE(p.Q2 > 2 && p.Q2 < (1u << 31) && p.Q2 != p.Q, "Q2 must be below 2^31 and differ from Q");
+        MM_REQUIRE((p.Q2 - 1) % (2 * p.N) == 0, "Q2 must be 1 mod 2N");
+        MM_REQUIRE(is_prime(p.Q2), "Q2 must be prime");
+        MM_REQUIRE(p.log2_B >= 1 && p.log2_B <= 16 && p.l >= 1 && p.l * p.log2_B <= 62 && p.l <= 8,
+                   "wide gadget needs 1 <= log2_B <= 16, 1 <= l <= 8, l*log2_B <= 62");
+        // the device joins residues through d1 + c Q2 - d0 in 32 bits, and every
+        // digit field (at most B + 1) must be a residue of both primes
+        MM_REQUIRE((uint64_t)p.Q + 2ull * p.Q2 < (1ull << 32), "wide mode needs Q + 2 Q2 < 2^32");
+        MM_REQUIRE((2ull << p.log2_B) < p.Q2, "wide mode needs 2B < Q2");
+    }
     MM_REQUIRE(p.log2_Bks >= 1 && p.log2_Bks <= 8, "log2_Bks must be in [1, 8]");
     MM_REQUIRE(p.l_ks * p.log2_Bks >= bit_length(p.Q) && p.l_ks <= 32,
                "l_ks * log2_Bks must cover bits(Q) (exact key-switch digits)");
@@ -139,14 +158,78 @@ static uint32_t lift_err(int32_t e, uint32_t Q)
     return (uint32_t)(v < 0 ? v + Q : v);
 }
 
+static uint32_t bit_length64(uint64_t x)
+{
+    uint32_t b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+// BSK_{i,k} = RGSW_z(m_{i,k}) at Q_w = Q Q2, built limb by limb: row masks are
+// the caller's uint64 draws reduced mod each prime, a z is taken through that
+// prime's NTT, and g_u = 2^(sg + u log2_B) mod Q_w.  [i][k][limb][row][part][N].
+static void keygen_bsk_wide(mm_ctx &c, const mm_key_draws &d)
+{
+    const mm_params &p = c.p;
+    const uint32_t N = p.N, l = p.l, n = p.n, K = c.keys;
+    MM_REQUIRE(d.bsk_a_wide, "null wide key draw (bsk_a_wide)");
+    const size_t bsk_in = (size_t)n * K * 2 * l * N;
+    for (size_t k = 0; k < bsk_in; k++) MM_REQUIRE(d.bsk_a_wide[k] < c.Qw, "bsk_a_wide out of range");
+    c.ntt2.build(N, p.Q2);
+    const NttTables *T[2] = {&c.ntt, &c.ntt2};
+    std::vector<uint32_t> z_ntt[2];
+    for (int j = 0; j < 2; j++) {
+        z_ntt[j] = c.z;
+        T[j]->forward(z_ntt[j].data());
+    }
+    std::vector<uint64_t> g(l);
+    for (uint32_t u = 0; u < l; u++) {
+        uint64_t v = 1 % c.Qw;
+        for (uint32_t e = 0; e < c.sg + u * p.log2_B; e++) v = (uint64_t)((unsigned __int128)v * 2 % c.Qw);
+        g[u] = v;
+    }
+    c.bsk.assign(bsk_in * 2 * 2, 0);
+    parallel_for((int64_t)n * K, [&](int64_t ik) {
+        const int64_t i = ik / K, key = ik % K;
+        const int32_t si = c.s[i];
+        const uint32_t m = key == 0 ? (uint32_t)std::max(si, 0) : (uint32_t)std::max(-si, 0);
+        std::vector<uint32_t> a(N);
+        for (uint32_t j = 0; j < 2; j++) {
+            const uint32_t Qj = T[j]->Q;
+            for (uint32_t row = 0; row < 2 * l; row++) {
+                const size_t in_off = ((size_t)ik * 2 * l + row) * N;
+                uint32_t *oa = &c.bsk[((((size_t)ik * 2 + j) * 2 * l + row) * 2 + 0) * N];
+                uint32_t *ob = oa + N;
+                for (uint32_t k = 0; k < N; k++) oa[k] = (uint32_t)(d.bsk_a_wide[in_off + k] % Qj);
+                mul_by_secret(*T[j], oa, z_ntt[j], ob);
+                for (uint32_t k = 0; k < N; k++) ob[k] = addmod(ob[k], lift_err(d.bsk_e[in_off + k], Qj), Qj);
+                if (m) {
+                    const uint32_t gj = (uint32_t)(g[row % l] % Qj);
+                    if (row < l) ob[0] = addmod(ob[0], gj, Qj);
+                    else oa[0] = addmod(oa[0], gj, Qj);
+                }
+            }
+        }
+    });
+}
+
+static void keygen_bsk(mm_ctx &c, const mm_key_draws &d, const std::vector<uint32_t> &z_ntt);
+static void keygen_ksk(mm_ctx &c, const mm_key_draws &d);
+
 void keygen(mm_ctx &c, const mm_key_draws &d)
 {
     const mm_params &p = c.p;
-    MM_REQUIRE(d.s && d.z && d.bsk_a && d.bsk_e && d.ksk_a && d.ksk_e, "null key draw");
-    const uint32_t N = p.N, Q = p.Q, l = p.l, n = p.n, Bks = 1u << p.log2_Bks;
-    c.sg = bit_length(Q) > l * p.log2_B ? bit_length(Q) - l * p.log2_B : 0;
+    c.wide = p.Q2 != 0;
+    MM_REQUIRE(d.s && d.z && (c.wide || d.bsk_a) && d.bsk_e && d.ksk_a && d.ksk_e, "null key draw");
+    const uint32_t N = p.N, Q = p.Q, l = p.l, n = p.n;
+    c.Qw = c.wide ? (uint64_t)Q * p.Q2 : Q;
+    const uint32_t bq = bit_length64(c.Qw);
+    c.sg = bq > l * p.log2_B ? bq - l * p.log2_B : 0;
     c.gadget.resize(l);
-    for (uint32_t u = 0; u < l; u++) c.gadget[u] = powmod(2, c.sg + u * p.log2_B, Q);
+    for (uint32_t u = 0; u < l; u++) c.gadget[u] = c.wide ? 0 : powmod(2, c.sg + u * p.log2_B, Q);
     c.keys = 1 + p.ternary;
     c.s.assign(d.s, d.s + n);
     c.z.assign(d.z, d.z + N);
@@ -157,8 +240,16 @@ void keygen(mm_ctx &c, const mm_key_draws &d)
     std::vector<uint32_t> z_ntt(c.z);
     c.ntt.forward(z_ntt.data());
 
-    // BSK_{i,k} = RGSW_z(m_{i,k}), [i][k][row][part][N]
-    const uint32_t K = c.keys;
+    // BSK_{i,k} = RGSW_z(m_{i,k}); KSK at Q
+    if (c.wide) keygen_bsk_wide(c, d);
+    else keygen_bsk(c, d, z_ntt);
+    keygen_ksk(c, d);
+}
+
+static void keygen_bsk(mm_ctx &c, const mm_key_draws &d, const std::vector<uint32_t> &z_ntt)
+{
+    const mm_params &p = c.p;
+    const uint32_t N = p.N, Q = p.Q, l = p.l, n = p.n, K = c.keys;
     const size_t bsk_in = (size_t)n * K * 2 * l * N;
     for (size_t k = 0; k < bsk_in; k++) MM_REQUIRE(d.bsk_a[k] < Q, "bsk_a out of range");
     c.bsk.assign(bsk_in * 2, 0);
@@ -180,8 +271,13 @@ void keygen(mm_ctx &c, const mm_key_draws &d)
             }
         }
     });
+}
 
-    // KSK[i][j][v] = (alpha, <alpha, s> + e + v z_i B_ks^j), [i][j][v][n+1]
+// KSK[i][j][v] = (alpha, <alpha, s> + e + v z_i B_ks^j), [i][j][v][n+1], at Q
+static void keygen_ksk(mm_ctx &c, const mm_key_draws &d)
+{
+    const mm_params &p = c.p;
+    const uint32_t N = p.N, Q = p.Q, n = p.n, Bks = 1u << p.log2_Bks;
     const size_t ksk_rows = (size_t)N * p.l_ks * Bks;
     for (size_t k = 0; k < ksk_rows * n; k++) MM_REQUIRE(d.ksk_a[k] < Q, "ksk_a out of range");
     c.ksk.assign(ksk_rows * (n + 1), 0);
@@ -251,8 +347,9 @@ void decrypt(const mm_ctx &c, uint32_t q, uint32_t t, const uint32_t *ct, size_t
 int table_create(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in, const uint32_t *f)
 {
     const uint32_t N = c.p.N;
-    MM_REQUIRE(r >= 1 && r <= 8, "r must be in [1, 8]");
+    MM_REQUIRE(r >= 1 && r <= (c.wide ? 1024u : 8u), c.wide ? "r must be in [1, 1024]" : "r must be in [1, 8]");
     const uint64_t M = 2ull * N * r;
+    MM_REQUIRE(M <= (1ull << 31), "2Nr must be <= 2^31");
     MM_REQUIRE(t >= 2 && t % 2 == 0 && M % t == 0, "t must be even and divide 2Nr");
     MM_REQUIRE(t_out >= 2 && t_out % 2 == 0 && t_out <= c.p.Q / 2, "t' must be even and below Q/2");
     if (q_in == 0) q_in = (uint32_t)M;
@@ -261,13 +358,20 @@ int table_create(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_i
     for (uint32_t m = 0; m < t / 2; m++)
         MM_REQUIRE((f[m] + f[m + t / 2]) % t_out == 0, "table is not nega-cyclic");
     Table tb{t, t_out, r, q_in, {}, 0};
-    tb.V.resize((size_t)r * N);
-    const uint64_t delta = M / t, dq = c.p.Q / t_out;
+    const uint32_t limbs = c.wide ? 2 : 1;
+    tb.V.resize((size_t)r * limbs * N);
+    const uint64_t delta = M / t, dq = c.Qw / t_out;
     for (uint32_t b = 0; b < r; b++)
         for (uint32_t a = 0; a < N; a++) {
             const uint64_t x = (M - ((uint64_t)a * r + b) % M) % M;  // -(a r + b) mod 2Nr
             const uint64_t m = ((x + delta / 2) / delta) % t;       // nearest multiple of 2Nr/t
-            tb.V[(size_t)b * N + a] = (uint32_t)(dq * f[m] % c.p.Q);
+            const uint64_t v = (uint64_t)((unsigned __int128)dq * f[m] % c.Qw);
+            if (!c.wide) {
+                tb.V[(size_t)b * N + a] = (uint32_t)v;
+            } else {
+                tb.V[((size_t)b * 2 + 0) * N + a] = (uint32_t)(v % c.p.Q);
+                tb.V[((size_t)b * 2 + 1) * N + a] = (uint32_t)(v % c.p.Q2);
+            }
         }
     c.tables.push_back(std::move(tb));
     return (int)c.tables.size() - 1;

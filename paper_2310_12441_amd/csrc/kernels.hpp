@@ -46,6 +46,39 @@ struct BrArgs {
     uint32_t *ext_out;         // [ct][N + 1] extracted samples
 };
 
+// One (ciphertext, component) pair of the wide-modulus blind rotation: a
+// workgroup of N / LANES... waves owns it for one CMux step.
+struct WideTask {
+    int32_t ct;        // ciphertext index
+    uint32_t comp;     // component j
+    uint32_t r;        // vector length of the ciphertext's table
+    uint32_t q_in;     // ciphertext modulus
+    uint32_t tv_off;   // word offset of the table's test vector ([r][2][N]) in the arena
+    uint32_t pad;
+    uint64_t acc_off;  // word offset of the ciphertext's component 0; a component is [2 parts][2 primes][N]
+};
+
+// The wide-modulus blind rotation: ring modulus Q_w = Q[0] Q[1], every
+// coefficient held as its two residues.
+struct WideArgs {
+    const WideTask *tasks;
+    const uint32_t *ct_in;     // ciphertexts at their q_in
+    uint32_t ct_stride;        // n + 1
+    uint32_t step;             // CMux step i of this launch
+    uint32_t Q[2], qn[2];      // the two primes and -Q^-1 mod 2^32
+    uint32_t log2B, l, sg;
+    uint32_t crt_cq;           // the smallest multiple of Q[1] that is >= Q[0]
+    uint32_t crt_inv;          // Q[0]^-1 mod Q[1], times 2^32 mod Q[1]
+    uint32_t pad;
+    uint64_t Qw, goff;         // Q[0] Q[1]; (B/2)(1 + B + ... + B^(l-1))
+    const uint32_t *bsk;       // [n][keys][prime][2l][2][N], NTT domain, x 2^32 / N mod that prime
+    const uint32_t *bsk_corr;  // [n][prime][2][N]: the digit-offset correction, summed over keys
+    const uint32_t *twf0, *twi0, *twf1, *twi1;
+    const uint32_t *tv;        // test-vector arena
+    const uint32_t *acc_rd;    // accumulators after step i (read)
+    uint32_t *acc_wr;          // accumulators after step i + 1 (written)
+};
+
 constexpr int KS_CTS_PER_WAVE = 4;
 constexpr int KS_TILED_MAX_ROWS = 128;  // l_ks * B_ks handled by the LDS-tiled key switch
 
@@ -66,6 +99,15 @@ void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, 
 void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,
                          hipStream_t st);
 void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st);
+// wide modulus: ACC = Phi(b')(0, V) into A.acc_wr; one CMux step (A.step) from
+// A.acc_rd into A.acc_wr; extraction of component 0 switched to Q[0]
+// (ext[c] from the component at acc_off[c]); the accumulator as uint64 values
+// [component][part][N] at the same word offsets.
+void launch_wide_init(uint32_t N, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
+void launch_wide_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
+void launch_wide_extract(uint32_t N, const WideArgs &A, const uint64_t *acc_off, size_t count, uint32_t *ext,
+                         hipStream_t st);
+void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st);
 size_t br_lds_bytes(uint32_t N, int gw);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
                              const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,

@@ -1,0 +1,264 @@
+// HIP kernels of the blind rotation at a wide ring modulus Q_w = Q0 Q1 (two
+// primes below 2^31, e.g. a 54-bit Q_w as in the experiments of Sec. 5).
+//
+// The accumulator of a ciphertext can be far larger than a workgroup (r up to
+// 1024 components), so it lives in device memory as [component][part][prime][N]
+// residues, double-buffered, and every CMux step is one launch over all
+// (ciphertext, component) pairs: the launch boundary is the barrier between
+// steps.  Workgroup k_wide_step owns one pair for one step:
+//   1. reads its own component and the one that Phi(-a'_i) brings to it (index
+//      and sign remap of the source, eq. ex1:BPc), both primes, and forms
+//      D = Phi(-a'_i) ACC_j - ACC_j;
+//   2. joins the two residues of each coefficient into one integer in [0, Q_w)
+//      (Chinese remainders), centres it and cuts it into l digit fields of the
+//      signed gadget (offset by B/2, Sec. 2 item (10));
+//   3. for each prime: forward NTT of every digit polynomial, product with
+//      BSK_i in the NTT domain (eq. def:gsw), inverse NTT;
+//   4. writes ACC_j + D x BSK_i into the other buffer.
+// A ternary secret adds the second term of Alg. 1 (Phi(+a'_i), BSK_i^-) from
+// the same ACC before step 3's inverse NTT.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace mm {
+namespace dev {
+
+// a' = round(x M / q) (Sec. 2 item (9)), ties upward.
+__device__ __forceinline__ uint32_t wide_modswitch(uint32_t x, uint32_t q, uint32_t M)
+{
+    return (uint32_t)(((2ull * x * M + q) / (2ull * q)) % M);
+}
+
+// Row j of Phi(c) for c = a r + b (eq. ex1:BPc): source component (j - b) mod r
+// and monomial x^(a + [j < b]), returned as a shift e in [0, N) and a sign.
+struct WideRow {
+    uint32_t src, e;
+    bool neg;
+};
+
+__device__ __forceinline__ WideRow wide_row(uint32_t c, uint32_t r, uint32_t j, uint32_t N)
+{
+    const uint32_t a = c / r, b = c - a * r;
+    WideRow w;
+    w.src = j >= b ? j - b : j + r - b;
+    uint32_t e = (a + (j < b ? 1u : 0u)) % (2 * N);
+    w.neg = e >= N;
+    w.e = w.neg ? e - N : e;
+    return w;
+}
+
+// Coefficient idx of x^e p (negacyclic, e < N): p[idx - e], negated when the
+// index wraps; `neg` folds in a further x^N = -1.
+__device__ __forceinline__ uint32_t wide_rot_load(const uint32_t *p, uint32_t idx, const WideRow &w, uint32_t N,
+                                                  uint32_t Q)
+{
+    const uint32_t v = p[(idx - w.e) & (N - 1)];
+    const bool flip = (idx < w.e) != w.neg;
+    return (flip && v) ? Q - v : v;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
+{
+    const WideTask T = A.tasks[blockIdx.x];
+    const uint32_t M = 2u * N * T.r;
+    const uint32_t *ct = A.ct_in + (size_t)T.ct * A.ct_stride;
+    const uint32_t b = wide_modswitch(ct[A.ct_stride - 1], T.q_in, M);
+    const WideRow w = wide_row(b, T.r, T.comp, N);
+    uint32_t *acc = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
+    for (uint32_t idx = threadIdx.x; idx < (uint32_t)N; idx += blockDim.x) {
+#pragma unroll
+        for (int pr = 0; pr < 2; pr++) {
+            const uint32_t *v = A.tv + T.tv_off + ((size_t)w.src * 2 + pr) * N;
+            acc[pr * N + idx] = 0;                                          // part a
+            acc[2 * N + pr * N + idx] = wide_rot_load(v, idx, w, N, A.Q[pr]);  // part b
+        }
+    }
+}
+
+template <int N, int KEYS>
+__global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
+{
+    using G = Geo<N>;
+    constexpr int E = G::E;
+    __shared__ uint32_t slot[G::SLOTW];
+    const WideTask T = A.tasks[blockIdx.x];
+    const int L = threadIdx.x;
+    const uint32_t M = 2u * N * T.r;
+    const uint32_t am = wide_modswitch(A.ct_in[(size_t)T.ct * A.ct_stride + A.step], T.q_in, M);
+    const ModQ m[2] = {{A.Q[0], A.qn[0]}, {A.Q[1], A.qn[1]}};
+    const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * 4 * N;
+    const uint32_t *twf[2] = {A.twf0, A.twf1}, *twi[2] = {A.twi0, A.twi1};
+
+    // NTT-domain outputs per prime, started at the digit-offset correction
+    uint32_t out[2][2][E];
+    const uint32_t *corr = A.bsk_corr + (size_t)A.step * 4 * N;
+#pragma unroll
+    for (int pr = 0; pr < 2; pr++)
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int k = 0; k < E; k++) out[pr][part][k] = corr[(pr * 2 + part) * N + L * E + k];
+
+    const uint64_t half = (A.Qw - 1) / 2;
+    for (int key = 0; key < KEYS; key++) {
+        const uint32_t c = key == 0 ? (M - am) % M : am;
+        const WideRow w = wide_row(c, T.r, T.comp, N);
+        const uint32_t *src = A.acc_rd + T.acc_off + (size_t)w.src * 4 * N;
+        // digit fields y'' = round(centred(D) / 2^sg) + goff, parts a (0) and b (1)
+        uint64_t y[2][E];
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint32_t idx = G::LANES * k + L;
+                const uint32_t *o = own + part * 2 * N, *s = src + part * 2 * N;
+                const uint32_t d0 = sub_q(wide_rot_load(s, idx, w, N, A.Q[0]), o[idx], A.Q[0]);
+                const uint32_t d1 = sub_q(wide_rot_load(s + N, idx, w, N, A.Q[1]), o[N + idx], A.Q[1]);
+                // x = d0 + Q0 ((d1 - d0) Q0^-1 mod Q1), in [0, Q0 Q1)
+                const uint32_t kk = mont_mul(d1 + A.crt_cq - d0, A.crt_inv, m[1]);
+                const uint64_t x = d0 + (uint64_t)A.Q[0] * kk;
+                int64_t xc = x > half ? (int64_t)(x - A.Qw) : (int64_t)x;
+                if (A.sg) xc = (xc + (1ll << (A.sg - 1))) >> A.sg;
+                y[part][k] = (uint64_t)xc + A.goff;
+            }
+        const uint32_t *K = A.bsk + ((size_t)A.step * KEYS + key) * 2 * (2 * A.l * 2 * N);
+#pragma unroll
+        for (int pr = 0; pr < 2; pr++) {
+            const uint32_t *Kp = K + (size_t)pr * (2 * A.l * 2 * N);
+            for (uint32_t u = 0; u < A.l; u++) {
+                __asm__ volatile("" ::: "memory");
+                const uint32_t sh = u * A.log2B;
+                const uint64_t mask = u + 1 == A.l ? ~0ull : (1ull << A.log2B) - 1;
+                uint32_t pd[2][E];
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    pd[0][k] = (uint32_t)((y[1][k] >> sh) & mask);  // digit of b meets rows u
+                    pd[1][k] = (uint32_t)((y[0][k] >> sh) & mask);  // digit of a meets rows l + u
+                }
+                ntt_fwd<N, 2>(pd, slot, twf[pr], L, m[pr]);
+                const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N + L * E;
+                const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N + L * E;
+                const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N + L * E;
+                const uint32_t *ka_b = Kp + ((size_t)(A.l + u) * 2 + 1) * N + L * E;
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
+                    const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
+                    out[pr][0][k] = add_q(out[pr][0][k], redc(xa, m[pr]), m[pr].Q);
+                    out[pr][1][k] = add_q(out[pr][1][k], redc(xb, m[pr]), m[pr].Q);
+                }
+            }
+        }
+    }
+    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
+#pragma unroll
+    for (int pr = 0; pr < 2; pr++) {
+        __asm__ volatile("" ::: "memory");
+        ntt_inv<N, 2>(out[pr], slot, twi[pr], L, m[pr]);
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint32_t idx = G::LANES * k + L;
+                const size_t at = (size_t)part * 2 * N + pr * N + idx;
+                wr[at] = add_q(out[pr][part][k], own[at], m[pr].Q);
+            }
+    }
+}
+
+__device__ __forceinline__ uint64_t wide_join(uint32_t d0, uint32_t d1, const WideArgs &A)
+{
+    const ModQ m1{A.Q[1], A.qn[1]};
+    return d0 + (uint64_t)A.Q[0] * mont_mul(d1 + A.crt_cq - d0, A.crt_inv, m1);
+}
+
+// Extraction of component 0 (eq. equ-sam-extr), then round(x Q0 / Q_w) =
+// floor((2 x + Q1) / (2 Q1)) mod Q0 for each coefficient.
+template <int N>
+__global__ __launch_bounds__(256) void k_wide_extract(WideArgs A, const uint64_t *__restrict__ acc_off,
+                                                      uint32_t *__restrict__ ext)
+{
+    const uint32_t *acc = A.acc_rd + acc_off[blockIdx.x];
+    uint32_t *o = ext + (size_t)blockIdx.x * (N + 1);
+    const uint64_t den = 2ull * A.Q[1];
+    for (uint32_t k = threadIdx.x; k <= (uint32_t)N; k += blockDim.x) {
+        uint64_t x;
+        if (k == N) {
+            x = wide_join(acc[2 * N], acc[3 * N], A);  // b_0
+        } else {
+            const uint32_t src = k ? N - k : 0;
+            x = wide_join(acc[src], acc[N + src], A);
+            if (k && x) x = A.Qw - x;                  // -a_{N-k}
+        }
+        o[k] = (uint32_t)(((2 * x + A.Q[1]) / den) % A.Q[0]);
+    }
+}
+
+// The accumulator as uint64 values: component j of a task -> [part][N] at the
+// same word offset (a component is 4N words in both layouts).
+template <int N>
+__global__ __launch_bounds__(256) void k_wide_export(WideArgs A, uint32_t *__restrict__ out)
+{
+    const WideTask T = A.tasks[blockIdx.x];
+    const size_t base = T.acc_off + (size_t)T.comp * 4 * N;
+    const uint32_t *acc = A.acc_rd + base;
+    for (uint32_t t = threadIdx.x; t < 2u * N; t += blockDim.x) {
+        const uint32_t part = t / N, idx = t % N;
+        const uint64_t x = wide_join(acc[part * 2 * N + idx], acc[part * 2 * N + N + idx], A);
+        out[base + 2 * t] = (uint32_t)x;
+        out[base + 2 * t + 1] = (uint32_t)(x >> 32);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define WIDE_DISPATCH(N_, CALL)             \
+    switch (N_) {                           \
+    case 256: CALL(256); break;             \
+    case 512: CALL(512); break;             \
+    case 1024: CALL(1024); break;           \
+    case 2048: CALL(2048); break;           \
+    case 4096: CALL(4096); break;           \
+    default: break;                         \
+    }
+
+void launch_wide_init(uint32_t N, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
+{
+#define C_(n) hipLaunchKernelGGL(k_wide_init<n>, dim3(num_tasks), dim3(256), 0, st, A)
+    WIDE_DISPATCH(N, C_)
+#undef C_
+}
+
+void launch_wide_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
+{
+#define C_(n)                                                                                              \
+    if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2>), dim3(num_tasks), dim3(64 * Geo<n>::WPP), 0, st, A); \
+    else hipLaunchKernelGGL((k_wide_step<n, 1>), dim3(num_tasks), dim3(64 * Geo<n>::WPP), 0, st, A)
+    WIDE_DISPATCH(N, C_)
+#undef C_
+}
+
+void launch_wide_extract(uint32_t N, const WideArgs &A, const uint64_t *acc_off, size_t count, uint32_t *ext,
+                         hipStream_t st)
+{
+#define C_(n) hipLaunchKernelGGL(k_wide_extract<n>, dim3((uint32_t)count), dim3(256), 0, st, A, acc_off, ext)
+    WIDE_DISPATCH(N, C_)
+#undef C_
+}
+
+void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st)
+{
+#define C_(n) hipLaunchKernelGGL(k_wide_export<n>, dim3(num_tasks), dim3(256), 0, st, A, out)
+    WIDE_DISPATCH(N, C_)
+#undef C_
+}
+
+#undef WIDE_DISPATCH
+
+}  // namespace dev
+}  // namespace mm

@@ -35,6 +35,8 @@ bool is_prime(uint32_t q);
 void parallel_for(int64_t n, const std::function<void(int64_t)> &fn);
 uint32_t bit_length(uint32_t x);
 uint32_t bitrev(uint32_t x, uint32_t bits);
+// x in [0, Q1 Q2) from its residues mod the primes Q1 and Q2 (Chinese remainders)
+uint64_t crt2(uint32_t x1, uint32_t x2, uint32_t Q1, uint32_t Q2);
 
 // Negacyclic NTT tables for Z_Q[x]/(x^N+1): psi a primitive 2N-th root of unity.
 // fwd[k] = psi^bitrev(k), inv[k] = psi^-bitrev(k) (k < N), the Cooley-Tukey /
@@ -49,7 +51,7 @@ struct NttTables {
 
 struct Table {
     uint32_t t, t_out, r, q_in;
-    std::vector<uint32_t> V;  // [r][N] scaled test vector (empty for a general table)
+    std::vector<uint32_t> V;  // [r][N] scaled test vector, wide: [r][limb][N] (empty for a general table)
     size_t dev_offset = 0;    // word offset in the device test-vector arena
     int g_id = -1, F_id = -1; // general f: the sign table and the extended-f table it runs
 };
@@ -69,9 +71,12 @@ struct mm_ctx {
     std::vector<int32_t> s;          // LWE secret in {0,1} or {-1,0,1}
     std::vector<uint32_t> z;         // RLWE secret (host)
     uint32_t keys = 1;               // RGSW keys per LWE coordinate (2 for a ternary secret)
-    std::vector<uint32_t> bsk;       // [n][keys][2l][2][N] coefficient form
+    bool wide = false;               // Q2 != 0: blind rotation at Q_w = Q Q2, two residues per coefficient
+    uint64_t Qw = 0;                 // ring modulus of the blind rotation (Q Q2 or Q)
+    std::vector<uint32_t> bsk;       // [n][keys][2l][2][N] coefficient form; wide: [n][keys][limb][2l][2][N]
     std::vector<uint32_t> ksk;       // [N][l_ks][B_ks][n+1]
     mm::NttTables ntt;
+    mm::NttTables ntt2;              // tables mod Q2 (wide mode)
     std::vector<mm::Table> tables;
     std::string err;
     std::unique_ptr<mm::Device, mm::DeviceDeleter> dev;

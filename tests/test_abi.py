@@ -148,3 +148,38 @@ def test_ring_degree_limits():
         with pytest.raises(b.MMError) as e:
             b.Context(p, key_draws(p, 1))
         assert e.value.code == b.MM_EINVAL
+
+
+@pytest.mark.parametrize("N,ternary", [(256, False), (2048, True)])
+def test_wide_keygen_and_test_vector_match_oracle(N, ternary):
+    """A 54-bit ring modulus Q Q2: the library keeps two residues per coefficient
+    and exports uint64 values equal to the oracle's."""
+    from synth import Q2_DEFAULT
+    b = _binding()
+    p = Params(n=3, N=N, log2_B=15, l=4, Q2=Q2_DEFAULT, ternary=ternary)
+    dr = key_draws(p, 23)
+    ctx = b.Context(p, dr)
+    np.testing.assert_array_equal(ctx.export_bsk(), oracle.w_keygen_bsk(p, dr))
+    np.testing.assert_array_equal(ctx.export_ksk(), oracle.keygen_ksk(p, dr))
+    for t, r in ((16, 1), (4096, 128), (24, 3)):
+        f = negacyclic_table(t, t, 24 + r)
+        tid = ctx.table_create(t, t, r, f)
+        assert ctx.table_info(tid) == (t, t, r, 2 * N * r)
+        np.testing.assert_array_equal(ctx.table_export(tid), oracle.w_test_vector(N, r, p.Q_ring, t, t, f))
+
+
+def test_wide_parameter_limits():
+    from dataclasses import replace
+    from synth import Q2_DEFAULT
+    b = _binding()
+    p = Params(n=3, N=256, log2_B=15, l=4, Q2=Q2_DEFAULT)
+    dr = key_draws(p, 25)
+    bad = [dict(Q2=p.Q), dict(Q2=Q2_DEFAULT - 1), dict(Q2=2013265921),  # Q + 2 Q2 >= 2^32
+           dict(log2_B=17), dict(l=5, log2_B=13), dict(Q2=12289, log2_B=15)]  # 2B >= Q2
+    for kw in bad:
+        with pytest.raises(b.MMError) as e:
+            b.Context(replace(p, **kw), dr)
+        assert e.value.code == b.MM_EINVAL, kw
+    ctx = b.Context(p, dr)
+    with pytest.raises(b.MMError):
+        ctx.table_create(8, 8, 2048, np.zeros(8, np.uint32))

@@ -1,0 +1,200 @@
+"""GPU parity of the blind rotation at a wide ring modulus Q Q2 (54 bits, gadget
+2^15 x 4: the parameters of the experiments in Sec. 5), bit-exact against the
+oracle's uint64 statement of the same steps.
+
+The accumulator lives in device memory and each CMux step is one launch, so r
+is no longer bounded by a workgroup: the cases cover r from 1 to 128, mixed r
+in one call, N from 256 to 2048 (one polynomial over two waves at 2048), both
+secret types, the plain and the batched path, and, at the full paper-margin
+size (n = 512, N = 2048, r = 128, t = 2^12), the first steps against the oracle
+and correct decryption of noisy inputs for a whole batch.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import PRESETS, Q2_DEFAULT, Params, enc_draws, key_draws, messages, negacyclic_table
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_12441_amd import binding
+    return binding
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+class WideCase:
+    def __init__(self, p, seed):
+        b = _gpu()
+        self.p = p
+        self.draws = key_draws(p, seed)
+        self.ctx = b.Context(p, self.draws)
+        self.keys = oracle.KeySetWide(p, self.draws)
+        self.ctx.device_init(0)
+
+    def table(self, t, r, seed):
+        f = negacyclic_table(t, t, seed)
+        tid = self.ctx.table_create(t, t, r, f)
+        return tid, f, oracle.w_test_vector(self.p.N, r, self.p.Q_ring, t, t, f)
+
+    def encrypt(self, q, t, m, seed, sigma=3.2):
+        ed = enc_draws(self.p.n, q, len(m), seed, sigma)
+        return oracle.encrypt(self.p.n, q, t, self.keys.s, m, ed["a"], ed["e"])
+
+
+_cases = {}
+
+
+def case(N, n, ternary=False):
+    key = (N, n, ternary)
+    if key not in _cases:
+        say("wide keygen N", N, "n", n, "ternary", ternary)
+        p = Params(n=n, N=N, log2_B=15, l=4, Q2=Q2_DEFAULT, ternary=ternary)
+        _cases[key] = WideCase(p, 1300 + N + n + ternary)
+    return _cases[key]
+
+
+@pytest.mark.parametrize("N,rs,steps", [(256, (1, 3, 8), 3), (256, (64,), 2), (512, (2, 5), 4),
+                                        (1024, (4,), 2), (2048, (1, 2), 2)])
+def test_wide_blind_rotate_steps(N, rs, steps):
+    say("wide blind_rotate N", N, "rs", rs, "steps", steps)
+    c = case(N, 8)
+    ids, cts, Vs, rr = [], [], [], []
+    for k, r in enumerate(rs):
+        t = max(2, 2 * N * r // 128)
+        tid, f, V = c.table(t, r, 40 + k)
+        ct = c.encrypt(2 * N * r, t, messages(t, 2, 50 + k), 60 + k)
+        for j in range(2):
+            ids.append(tid)
+            cts.append(ct[j])
+            Vs.append(V)
+            rr.append(r)
+    got = c.ctx.blind_rotate(ids, np.array(cts), steps)
+    off = 0
+    for j in range(len(ids)):
+        r = rr[j]
+        size = r * 2 * N
+        want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, Vs[j], cts[j], steps)
+        np.testing.assert_array_equal(got[off:off + size].reshape(r, 2, N), want, err_msg=f"ct {j} r {r}")
+        off += size
+    assert off == got.size
+
+
+@pytest.mark.parametrize("N,r", [(256, 4), (256, 1), (512, 2)])
+def test_wide_bootstrap_matches_oracle_and_decrypts(N, r):
+    say("wide bootstrap N", N, "r", r)
+    c = case(N, 16)
+    t = 2 * N * r // 128
+    q = 2 * N * r
+    tid, f, V = c.table(t, r, 70 + r)
+    m = np.arange(t, dtype=np.uint32)
+    ct = c.encrypt(q, t, m, 71 + r)
+    got = c.ctx.bootstrap([tid] * t, ct)
+    want = oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, t, c.keys.s, got), f[m])
+    np.testing.assert_array_equal(c.ctx.bootstrap([tid] * t, ct, plain=True), got)
+
+
+def test_wide_bootstrap_mixed_r_and_q_out():
+    c = case(256, 16)
+    rs = (1, 2, 8)
+    tids, cts, want = [], [], []
+    for k, r in enumerate(rs):
+        t = 2 * 256 * r // 128
+        q = 2 * 256 * r
+        tid, f, V = c.table(t, r, 80 + k)
+        ct = c.encrypt(q, t, messages(t, 2, 81 + k), 82 + k)
+        tids += [tid] * 2
+        cts.append(ct)
+        want.append(oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, c.p.Q, ct))
+    got = c.ctx.bootstrap(tids, np.concatenate(cts), q_out=c.p.Q)
+    np.testing.assert_array_equal(got, np.concatenate(want))
+
+
+def test_wide_ternary():
+    c = case(512, 6, ternary=True)
+    r, t = 2, 16
+    q = 2 * 512 * r
+    tid, f, V = c.table(t, r, 90)
+    ct = c.encrypt(q, t, messages(t, 3, 91), 92)
+    got = c.ctx.blind_rotate([tid] * 3, ct, 3)
+    for j in range(3):
+        want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, V, ct[j], 3)
+        np.testing.assert_array_equal(got[j * r * 2 * 512:(j + 1) * r * 2 * 512].reshape(r, 2, 512), want)
+    out = c.ctx.bootstrap([tid] * 3, ct)
+    np.testing.assert_array_equal(out, oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+
+
+def test_wide_bootstrap_2048():
+    c = case(2048, 8)
+    r = 2
+    t = 2 * 2048 * r // 128
+    q = 2 * 2048 * r
+    tid, f, V = c.table(t, r, 95)
+    ct = c.encrypt(q, t, messages(t, 2, 96), 97)
+    got = c.ctx.bootstrap([tid] * 2, ct)
+    np.testing.assert_array_equal(got, oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+
+
+def test_wide_empty_and_rejected_calls():
+    b = _gpu()
+    c = case(256, 8)
+    tid, f, V = c.table(8, 4, 99)
+    assert c.ctx.bootstrap(np.zeros(0, np.int32), np.zeros((0, 9), np.uint32)).shape == (0, 9)
+    with pytest.raises(b.MMError):
+        c.ctx.table_create(8, 8, 2048, np.zeros(8, np.uint32))  # r above 1024
+    with pytest.raises(b.MMError):
+        c.ctx.external_product(0, np.zeros((1, 2, 256), np.uint32))
+    with pytest.raises(b.MMError):
+        c.ctx.server_start(64 << 20)
+    with pytest.raises(b.MMError):
+        c.ctx.schedule_count([tid])
+
+
+@pytest.fixture(scope="module")
+def margin():
+    pre = PRESETS["paper_margin"]
+    say("paper-margin keygen (n = 512, N = 2048)")
+    return WideCase(pre["params"], 21), pre
+
+
+def test_paper_margin_first_step_sampled(margin):
+    """n = 512, N = 2048, r = 128: the accumulator after the initialisation and one
+    CMux step, against the oracle, for one ciphertext."""
+    c, pre = margin
+    t, r = pre["t"], pre["r"]
+    q = 2 * c.p.N * r
+    tid, f, V = c.table(t, r, 22)
+    ct = c.encrypt(q, t, messages(t, 1, 23), 24)
+    got = c.ctx.blind_rotate([tid], ct, 1).reshape(r, 2, c.p.N)
+    say("oracle, one step at r = 128")
+    want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, V, ct[0], 1)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_paper_margin_noisy_batch_decrypts_at_t_4096(margin):
+    """A batch of noisy encryptions (sigma 3.2) at t = 2^12, 2Nr/t = 128: every
+    output decrypts to f(m), with the output noise well inside Delta/2."""
+    c, pre = margin
+    t, r = pre["t"], pre["r"]
+    q = 2 * c.p.N * r
+    tid, f, V = c.table(t, r, 25)
+    m = messages(t, 64, 26)
+    ct = c.encrypt(q, t, m, 27)
+    say("paper-margin bootstrap of 64")
+    out = c.ctx.bootstrap([tid] * 64, ct)
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, t, c.keys.s, out), f[m])
+    ph = oracle.lwe_phase(c.p.n, q, c.keys.s, out).astype(np.int64)
+    err = (ph - f[m].astype(np.int64) * (q // t)) % q
+    err = np.where(err > q // 2, err - q, err)
+    assert np.max(np.abs(err)) < 32
