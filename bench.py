@@ -52,6 +52,13 @@ def ops_per_bootstrap(n, N, l, r):
     return n * r * per_comp
 
 
+def ops_per_bootstrap_wide(n, N, l, r):
+    """The same op model at a ring modulus of two primes: every NTT, product and
+    accumulation runs once per prime.  Joining the residues, the decomposition,
+    the rotation and data movement are not counted."""
+    return 2 * ops_per_bootstrap(n, N, l, r)
+
+
 def source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -103,6 +110,9 @@ def main():
                     help="batch of the MMPM vs TFHE-shaped comparison per class (0: no comparison leg)")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
+    ap.add_argument("--margin", type=int, default=16384,
+                    help="ring components per batch of the paper-margin sweep (0: no such leg)")
+    ap.add_argument("--margin-logt", default="5,6,7,8,9,10,11,12", help="log2 t of the paper-margin sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -309,6 +319,13 @@ def main():
                 alone = ctx.bootstrap(s_ids, s_ct)
                 serving["identical_to_alone"] = bool(np.array_equal(out_s, alone))
 
+    # ---- the parameters of the experiments in Sec. 5 (Tables 1-2): n = 512, N = 2048,
+    # ring modulus of 54 bits (two primes), gadget 2^15 x 4, q = 2Nr = 128 t, the
+    # identity function on Z_t by two bootstraps (plaintext modulus 2t), noisy inputs
+    margin = None
+    if args.margin > 0:
+        margin = margin_leg(args, binding, torch)
+
     # ---- CPU oracle on the host cores, on a bounded sample of the same batch
     cpu = None
     if not args.no_cpu:
@@ -355,8 +372,89 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "paper_margin": margin,
     }
     print(json.dumps(line), flush=True)
+
+
+def margin_leg(args, binding, torch):
+    """Per log t: batched throughput of one nega-cyclic bootstrap and of the
+    identity function (two bootstraps), the plain latency of the identity for one
+    ciphertext, the blind-rotation / key-switch split and correct decryption."""
+    from synth import PRESETS, enc_draws, key_draws, messages, negacyclic_table
+
+    pre = PRESETS["paper_margin"]
+    pw = pre["params"]
+    seed = 31
+    mctx = binding.Context(pw, key_draws(pw, seed))
+    mctx.device_init(0)
+    mctx.set_timing(True)
+    rows = []
+    for logt in [int(x) for x in args.margin_logt.split(",") if x]:
+        t = 1 << logt
+        r = max(1, t * 128 // (2 * pw.N))  # q = 2Nr = 128 t
+        q = 2 * pw.N * r
+        Bm = max(8, min(4096, args.margin // r))
+        row = {"log_t": logt, "r": r, "log_q": int(np.log2(q)), "batch": Bm}
+        # one nega-cyclic bootstrap (2Nr / t = 128)
+        tid = mctx.table_create(t, t, r, negacyclic_table(t, t, 500 + logt))
+        edn = enc_draws(pw.n, q, Bm, 600 + logt)
+        mn = messages(t, Bm, 700 + logt)
+        ctn = mctx.encrypt(q, t, mn, edn["a"], edn["e"])
+        din = torch.from_numpy(ctn.view(np.int32)).cuda()
+        dout = torch.empty_like(din)
+        ids = np.full(Bm, tid, np.int32)
+        mctx.bootstrap(ids, din, out=dout)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        br_ms, ks_ms = [], []
+        for _ in range(reps):
+            mctx.bootstrap(ids, din, out=dout)
+            a_, b_ = mctx.last_timing()
+            br_ms.append(a_)
+            ks_ms.append(b_)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        row["bootstraps_per_s"] = round(Bm / dt, 1)
+        row["blind_rotation_ms"] = round(float(np.mean(br_ms)), 3)
+        row["keyswitch_ms"] = round(float(np.mean(ks_ms)), 3)
+        ops = ops_per_bootstrap_wide(pw.n, pw.N, pw.l, r) * Bm
+        row["blind_rotation_tops"] = round(ops / (row["blind_rotation_ms"] * 1e-3) / 1e12, 3)
+        # the identity on Z_t: plaintext modulus 2t, two bootstraps
+        ident = mctx.table_create_general(t, t, r, np.arange(t, dtype=np.uint32))
+        mi = messages(t, Bm, 800 + logt)
+        edi = enc_draws(pw.n, q, Bm, 900 + logt)
+        cti = mctx.encrypt(q, 2 * t, mi, edi["a"], edi["e"])
+        iin = torch.from_numpy(cti.view(np.int32)).cuda()
+        iout = torch.empty_like(iin)
+        iids = np.full(Bm, ident, np.int32)
+        mctx.bootstrap(iids, iin, out=iout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mctx.bootstrap(iids, iin, out=iout)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        row["identity_per_s"] = round(Bm / dt, 1)
+        outn = dout.cpu().numpy().view(np.uint32)
+        outi = iout.cpu().numpy().view(np.uint32)
+        row["correct"] = bool(np.array_equal(mctx.decrypt(q, t, outi), mi) and
+                              np.array_equal(mctx.decrypt(q, t, outn), negacyclic_table(t, t, 500 + logt)[mn]))
+        lat = []
+        for k in range(3):
+            t0 = time.perf_counter()
+            mctx.bootstrap([ident], cti[k:k + 1], plain=True)
+            lat.append(time.perf_counter() - t0)
+        row["identity_plain_ms"] = round(float(np.median(lat)) * 1e3, 3)
+        rows.append(row)
+        print(json.dumps({"paper_margin_row": row}), file=sys.stderr, flush=True)
+    mctx.close()
+    return {"params": {"n": pw.n, "N": pw.N, "log2_Q": int(pw.Q_ring).bit_length(), "Q": [pw.Q, pw.Q2],
+                       "log2_B": pw.log2_B, "l": pw.l, "log2_Bks": pw.log2_Bks, "l_ks": pw.l_ks, "secret": "binary",
+                       "sigma": pw.sigma},
+            "bsk_bytes": 2 * pw.n * 2 * pw.l * 2 * pw.N * 4, "ksk_bytes": ksk_bytes(pw.n, pw.N, pw),
+            "rows": rows}
 
 
 if __name__ == "__main__":

@@ -18,7 +18,7 @@ __all__ = [
     "general_tables", "bootstrap_general",
     "w_poly_mul", "w_rotate", "w_test_vector", "w_gadget_shift", "w_gadget", "w_decompose", "w_keygen_bsk",
     "w_external_product", "w_blind_rotate", "w_modswitch", "w_sample_extract", "w_bootstrap", "w_bootstrap_many",
-    "KeySetWide",
+    "KeySetWide", "w_bootstrap_general",
 ]
 
 _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
@@ -77,6 +77,8 @@ def lib():
                                        _u64p, _u32, _u32, _u32p, _u32p, C.c_void_p]),
             "orc_w_bootstrap_many": (None, [_u32, _u32, _u64, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u64p,
                                             _u32p, _u64p, _u32, _u32, _u32p, _u64, _u32p]),
+            "orc_w_bootstrap_general": (None, [_u32, _u32, _u64, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u64p,
+                                               _u32p, _u64p, _u64p, _u32, _u32, _u32, _u32p, _u64, _u32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -388,6 +390,15 @@ def w_bootstrap_many(p, r: int, bsk, ksk, V, q_in: int, q_out: int, cts) -> np.n
     out = np.empty_like(cts)
     lib().orc_w_bootstrap_many(p.n, p.N, p.Q_ring, p.log2_B, p.l, p.Q, p.log2_Bks, p.l_ks, r, _keys(p),
                                _w(bsk), _u(ksk), _w(V), q_in, q_out, cts, cts.shape[0], out)
+    return out
+
+
+def w_bootstrap_general(p, r: int, bsk, ksk, Vg, VF, q: int, t: int, q_out: int, cts) -> np.ndarray:
+    """f(m) from Enc_{2t}(m + b t) by two bootstraps at the wide ring modulus."""
+    cts = _u(cts).reshape(-1, p.n + 1)
+    out = np.empty_like(cts)
+    lib().orc_w_bootstrap_general(p.n, p.N, p.Q_ring, p.log2_B, p.l, p.Q, p.log2_Bks, p.l_ks, r, _keys(p),
+                                  _w(bsk), _u(ksk), _w(Vg), _w(VF), q, t, q_out, cts, cts.shape[0], out)
     return out
 
 

@@ -898,3 +898,27 @@ void orc_w_bootstrap_many(uint32_t n, uint32_t N, uint64_t Qw, uint32_t log2B, u
         w_bootstrap_one(n, N, Qw, log2B, l, Qks, log2Bks, lks, r, keys, bsk, ksk, V, q_in, q_out,
                         ct + (size_t)c * (n + 1), out + (size_t)c * (n + 1), NULL, 0);
 }
+
+/* f not nega-cyclic at the wide ring modulus: the two bootstraps of
+ * orc_bootstrap_general (sign table g, then the extension F), each through
+ * w_bootstrap_one; the LWE arithmetic between them is at q. */
+void orc_w_bootstrap_general(uint32_t n, uint32_t N, uint64_t Qw, uint32_t log2B, uint32_t l, uint32_t Qks,
+                             uint32_t log2Bks, uint32_t lks, uint32_t r, uint32_t keys, const uint64_t *bsk,
+                             const uint32_t *ksk, const uint64_t *Vg, const uint64_t *VF, uint32_t q, uint32_t t,
+                             uint32_t q_out, const uint32_t *ct, uint64_t count, uint32_t *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < (int64_t)count; c++) {
+        const uint32_t *ci = ct + (size_t)c * (n + 1);
+        uint32_t *ctg = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+        uint32_t *ct2 = (uint32_t *)malloc(sizeof(uint32_t) * (n + 1));
+        w_bootstrap_one(n, N, Qw, log2B, l, Qks, log2Bks, lks, r, keys, bsk, ksk, Vg, q, q, ci, ctg, NULL, 0);
+        const uint64_t shift = (uint64_t)(t / 2) * (q / (2 * t)) % q;
+        for (uint32_t k = 0; k <= n; k++) ct2[k] = (uint32_t)(((uint64_t)ci[k] + ctg[k]) % q);
+        ct2[n] = (uint32_t)(((uint64_t)ct2[n] + q - shift) % q);
+        w_bootstrap_one(n, N, Qw, log2B, l, Qks, log2Bks, lks, r, keys, bsk, ksk, VF, q, q_out, ct2,
+                        out + (size_t)c * (n + 1), NULL, 0);
+        free(ctg);
+        free(ct2);
+    }
+}

@@ -94,23 +94,14 @@ __global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
     const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * 4 * N;
     const uint32_t *twf[2] = {A.twf0, A.twf1}, *twi[2] = {A.twi0, A.twi1};
 
-    // NTT-domain outputs per prime, started at the digit-offset correction
-    uint32_t out[2][2][E];
-    const uint32_t *corr = A.bsk_corr + (size_t)A.step * 4 * N;
-#pragma unroll
-    for (int pr = 0; pr < 2; pr++)
-#pragma unroll
-        for (int part = 0; part < 2; part++)
-#pragma unroll
-            for (int k = 0; k < E; k++) out[pr][part][k] = corr[(pr * 2 + part) * N + L * E + k];
-
+    // y'' = round(centred(D) / 2^sg) + goff per coefficient of parts a (0) and b
+    // (1), D = Phi(c) ACC_j - ACC_j joined from its two residues
     const uint64_t half = (A.Qw - 1) / 2;
-    for (int key = 0; key < KEYS; key++) {
+    uint64_t y[2][E];
+    auto digit_fields = [&](int key) {
         const uint32_t c = key == 0 ? (M - am) % M : am;
         const WideRow w = wide_row(c, T.r, T.comp, N);
         const uint32_t *src = A.acc_rd + T.acc_off + (size_t)w.src * 4 * N;
-        // digit fields y'' = round(centred(D) / 2^sg) + goff, parts a (0) and b (1)
-        uint64_t y[2][E];
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
@@ -126,10 +117,22 @@ __global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
                 if (A.sg) xc = (xc + (1ll << (A.sg - 1))) >> A.sg;
                 y[part][k] = (uint64_t)xc + A.goff;
             }
-        const uint32_t *K = A.bsk + ((size_t)A.step * KEYS + key) * 2 * (2 * A.l * 2 * N);
+    };
+    if constexpr (KEYS == 1) digit_fields(0);
+    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
+    // one prime at a time: NTT-domain output from the digit-offset correction,
+    // the products with BSK_i, inverse NTT, accumulate and store
 #pragma unroll
-        for (int pr = 0; pr < 2; pr++) {
-            const uint32_t *Kp = K + (size_t)pr * (2 * A.l * 2 * N);
+    for (int pr = 0; pr < 2; pr++) {
+        uint32_t out[2][E];
+        const uint32_t *corr = A.bsk_corr + ((size_t)A.step * 2 + pr) * 2 * N + L * E;
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int k = 0; k < E; k++) out[part][k] = corr[part * N + k];
+        for (int key = 0; key < KEYS; key++) {
+            if constexpr (KEYS == 2) digit_fields(key);
+            const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * 2 + pr) * (2 * A.l * 2 * N);
             for (uint32_t u = 0; u < A.l; u++) {
                 __asm__ volatile("" ::: "memory");
                 const uint32_t sh = u * A.log2B;
@@ -149,24 +152,20 @@ __global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
                 for (int k = 0; k < E; k++) {
                     const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
                     const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
-                    out[pr][0][k] = add_q(out[pr][0][k], redc(xa, m[pr]), m[pr].Q);
-                    out[pr][1][k] = add_q(out[pr][1][k], redc(xb, m[pr]), m[pr].Q);
+                    out[0][k] = add_q(out[0][k], redc(xa, m[pr]), m[pr].Q);
+                    out[1][k] = add_q(out[1][k], redc(xb, m[pr]), m[pr].Q);
                 }
             }
         }
-    }
-    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
-#pragma unroll
-    for (int pr = 0; pr < 2; pr++) {
         __asm__ volatile("" ::: "memory");
-        ntt_inv<N, 2>(out[pr], slot, twi[pr], L, m[pr]);
+        ntt_inv<N, 2>(out, slot, twi[pr], L, m[pr]);
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
             for (int k = 0; k < E; k++) {
                 const uint32_t idx = G::LANES * k + L;
                 const size_t at = (size_t)part * 2 * N + pr * N + idx;
-                wr[at] = add_q(out[pr][part][k], own[at], m[pr].Q);
+                wr[at] = add_q(out[part][k], own[at], m[pr].Q);
             }
     }
 }

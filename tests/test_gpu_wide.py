@@ -146,6 +146,25 @@ def test_wide_bootstrap_2048():
     np.testing.assert_array_equal(got, oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
 
 
+@pytest.mark.parametrize("N,r", [(256, 4), (2048, 2)])
+def test_wide_identity_function_two_bootstraps(N, r):
+    """f(x) = x, not nega-cyclic: the sign bootstrap, the top-bit removal and the
+    second bootstrap, at the wide modulus, against the oracle; noisy inputs decrypt."""
+    c = case(N, 16)
+    t = 2 * N * r // 128 // 2
+    q = 2 * N * r
+    f = np.arange(t, dtype=np.uint32)
+    tid = c.ctx.table_create_general(t, t, r, f)
+    g, F = oracle.general_tables(t, t, f)
+    Vg = oracle.w_test_vector(N, r, c.p.Q_ring, 2 * t, 2 * t, g)
+    VF = oracle.w_test_vector(N, r, c.p.Q_ring, 2 * t, t, F)
+    m = messages(t, 16 if N <= 512 else 4, 110 + r)
+    ct = c.encrypt(q, 2 * t, m, 111 + r)
+    got = c.ctx.bootstrap([tid] * len(m), ct)
+    np.testing.assert_array_equal(got, oracle.w_bootstrap_general(c.p, r, c.keys.bsk, c.keys.ksk, Vg, VF, q, t, q, ct))
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, t, c.keys.s, got), m)
+
+
 def test_wide_empty_and_rejected_calls():
     b = _gpu()
     c = case(256, 8)

@@ -272,3 +272,40 @@ def test_w_bootstrap_single_equals_many_and_extracts_at_q():
         one, ext = oracle.w_bootstrap(p, r, keys.bsk, keys.ksk, V, q, q, ct[k], ext_out=True)
         np.testing.assert_array_equal(one, many[k])
         assert ext.max() < Q
+
+
+def test_w_general_equals_the_32bit_general_below_2_31():
+    p = Params(n=8, N=32, log2_B=7, l=4)
+    dr = key_draws(p, 40)
+    keys = oracle.KeySet(p, dr)
+    bskw = oracle.w_keygen_bsk(p, dict(dr, bsk_a=dr["bsk_a"].astype(np.uint64)))
+    r, t = 2, 8
+    q = 2 * p.N * r
+    f = np.arange(t, dtype=np.uint32)[::-1].copy()
+    g, F = oracle.general_tables(t, t, f)
+    Vg, VF = oracle.test_vector(p.N, r, Q, 2 * t, 2 * t, g), oracle.test_vector(p.N, r, Q, 2 * t, t, F)
+    ed = enc_draws(p.n, q, 3, 41)
+    ct = oracle.encrypt(p.n, q, 2 * t, keys.s, messages(t, 3, 42), ed["a"], ed["e"])
+    want = np.stack([oracle.bootstrap_general(p, r, keys.bsk, keys.ksk, Vg, VF, q, t, q, ct[k]) for k in range(3)])
+    got = oracle.w_bootstrap_general(p, r, bskw, keys.ksk, Vg.astype(np.uint64), VF.astype(np.uint64), q, t, q, ct)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_w_identity_function_by_two_bootstraps_decrypts_at_delta_128():
+    """The workload of the experiments in Sec. 5: f(x) = x (not nega-cyclic), two
+    bootstraps; noisy inputs at plaintext modulus 2t with 2Nr/(2t) = 128."""
+    p = wide(24, 256)
+    r = 4
+    t = 2 * p.N * r // 128 // 2  # the input carries m + b t in Z_2t
+    q = 2 * p.N * r
+    dr = key_draws(p, 43)
+    keys = oracle.KeySetWide(p, dr)
+    f = np.arange(t, dtype=np.uint32)
+    g, F = oracle.general_tables(t, t, f)
+    Vg = oracle.w_test_vector(p.N, r, QW, 2 * t, 2 * t, g)
+    VF = oracle.w_test_vector(p.N, r, QW, 2 * t, t, F)
+    m = np.arange(t, dtype=np.uint32)
+    ed = enc_draws(p.n, q, t, 44, sigma=3.2)
+    ct = oracle.encrypt(p.n, q, 2 * t, keys.s, m, ed["a"], ed["e"])
+    out = oracle.w_bootstrap_general(p, r, keys.bsk, keys.ksk, Vg, VF, q, t, q, ct)
+    np.testing.assert_array_equal(oracle.decrypt(p.n, q, t, keys.s, out), m)
