@@ -52,11 +52,16 @@ def ops_per_bootstrap(n, N, l, r):
     return n * r * per_comp
 
 
-def ops_per_bootstrap_wide(n, N, l, r):
+def ops_per_bootstrap_wide(n, N, l, r, keys=1):
     """The same op model at a ring modulus of two primes: every NTT, product and
-    accumulation runs once per prime.  Joining the residues, the decomposition,
-    the rotation and data movement are not counted."""
-    return 2 * ops_per_bootstrap(n, N, l, r)
+    accumulation runs once per prime; with a ternary secret (keys = 2) each
+    step has two sets of forward NTTs and products and one inverse NTT pair.
+    Joining the residues, the decomposition, the rotation and data movement are
+    not counted."""
+    logN = int(np.log2(N))
+    bfly = (N // 2) * logN
+    per_prime = keys * (2 * l * bfly * 11 + 2 * N * l * 10) + 2 * bfly * 10
+    return n * r * 2 * per_prime
 
 
 def source_hash():
@@ -419,7 +424,7 @@ def margin_leg(args, binding, torch):
         row["bootstraps_per_s"] = round(Bm / dt, 1)
         row["blind_rotation_ms"] = round(float(np.mean(br_ms)), 3)
         row["keyswitch_ms"] = round(float(np.mean(ks_ms)), 3)
-        ops = ops_per_bootstrap_wide(pw.n, pw.N, pw.l, r) * Bm
+        ops = ops_per_bootstrap_wide(pw.n, pw.N, pw.l, r, pw.keys_per_coord) * Bm
         row["blind_rotation_tops"] = round(ops / (row["blind_rotation_ms"] * 1e-3) / 1e12, 3)
         # the identity on Z_t: plaintext modulus 2t, two bootstraps
         ident = mctx.table_create_general(t, t, r, np.arange(t, dtype=np.uint32))
@@ -451,9 +456,9 @@ def margin_leg(args, binding, torch):
         print(json.dumps({"paper_margin_row": row}), file=sys.stderr, flush=True)
     mctx.close()
     return {"params": {"n": pw.n, "N": pw.N, "log2_Q": int(pw.Q_ring).bit_length(), "Q": [pw.Q, pw.Q2],
-                       "log2_B": pw.log2_B, "l": pw.l, "log2_Bks": pw.log2_Bks, "l_ks": pw.l_ks, "secret": "binary",
-                       "sigma": pw.sigma},
-            "bsk_bytes": 2 * pw.n * 2 * pw.l * 2 * pw.N * 4, "ksk_bytes": ksk_bytes(pw.n, pw.N, pw),
+                       "log2_B": pw.log2_B, "l": pw.l, "log2_Bks": pw.log2_Bks, "l_ks": pw.l_ks,
+                       "secret": "ternary" if pw.ternary else "binary", "sigma": pw.sigma},
+            "bsk_bytes": pw.keys_per_coord * pw.n * 2 * pw.l * 2 * pw.N * 8, "ksk_bytes": ksk_bytes(pw.n, pw.N, pw),
             "rows": rows}
 
 

@@ -2,8 +2,8 @@
 // (Q odd, Q < 2^31), the negacyclic NTT held in registers, and the external
 // product of one RLWE pair by one bootstrapping-key row block.
 //
-// Data layout of one degree-N polynomial: it is spread over WPP waves
-// (WPP = 1 up to N = 1024, N / 1024 above) that act as one set of LANES =
+// Data layout of one degree-N polynomial: it is spread over WPP waves (by
+// default 1 up to N = 1024 and N / 1024 above) that act as one set of LANES =
 // 64 WPP virtual lanes, each holding E = N / LANES coefficients.  The NTT runs
 // in NPH phases; in phase p virtual lane L and register k hold coefficient
 //     idx_p(L, k) = ((L >> R_p) << (R_p + LE)) | (k << R_p) | (L & (2^R_p - 1)),
@@ -24,9 +24,13 @@ namespace dev {
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
-template <int N>
+// Waves per polynomial by default: one up to N = 1024, N / 1024 above (16
+// coefficients per lane); a kernel may spread a polynomial over more waves.
+constexpr int default_wpp(int N) { return N > 1024 ? N / 1024 : 1; }
+
+template <int N, int W = default_wpp(N)>
 struct Geo {
-    static constexpr int WPP = N > 1024 ? N / 1024 : 1;  // waves per polynomial
+    static constexpr int WPP = W;  // waves per polynomial
     static constexpr int LANES = 64 * WPP;
     static constexpr int LL = ilog2(LANES);
     static constexpr int E = N / LANES;
@@ -45,14 +49,41 @@ struct Geo {
 
 // LDS word address of coefficient idx: one pad word per 16 keeps all phase
 // layouts (strides 1, 2^R_p and E between neighbouring lanes) free of bank conflicts.
-__device__ __forceinline__ int swz(int idx) { return idx + (idx >> 4); }
+__host__ __device__ constexpr int swz(int idx) { return idx + (idx >> 4); }
 
-template <int N>
-__device__ __forceinline__ int idx_of(int p, int L, int k)
+template <int N, int W = default_wpp(N)>
+__host__ __device__ constexpr int idx_of(int p, int L, int k)
 {
-    using G = Geo<N>;
+    using G = Geo<N, W>;
     const int R = G::R(p);
     return ((L >> R) << (R + G::LE)) | (k << R) | (L & ((1 << R) - 1));
+}
+
+// swz(idx_of(p, L, k)) = swz_base(p, L) + swz_off(R_p, k): the register index k
+// only adds a constant (its bits sit between the lane's high and low bits and,
+// below bit 4, never carry past it), so a relayout needs one address register
+// per side and immediate offsets for the E registers.
+template <int N, int W = default_wpp(N)>
+__host__ __device__ constexpr int swz_base(int p, int L)
+{
+    using G = Geo<N, W>;
+    const int R = G::R(p);
+    const int H = (L >> R) << (R + G::LE), Lo = L & ((1 << R) - 1);
+    return H + (H >> 4) + Lo + (R >= 4 ? (Lo >> 4) : 0);
+}
+
+__host__ __device__ constexpr int swz_off(int R, int k) { return (k << R) + (R >= 4 ? k << (R - 4) : k >> (4 - R)); }
+
+// Every phase, lane and register of a geometry obeys the split above.
+template <int N, int W = default_wpp(N)>
+constexpr bool swz_split_holds()
+{
+    using G = Geo<N, W>;
+    for (int p = 0; p < G::NPH; p++)
+        for (int L = 0; L < G::LANES; L++)
+            for (int k = 0; k < G::E; k++)
+                if (swz(idx_of<N, W>(p, L, k)) != swz_base<N, W>(p, L) + swz_off(G::R(p), k)) return false;
+    return true;
 }
 
 struct ModQ {
@@ -95,46 +126,48 @@ __device__ __forceinline__ void wave_sync()
 
 // Barrier between the lanes that share a polynomial: the wave itself, or the
 // whole workgroup when a polynomial spans several waves.
-template <int N>
+template <int N, int W = default_wpp(N)>
 __device__ __forceinline__ void poly_sync()
 {
-    if constexpr (Geo<N>::WPP == 1) wave_sync();
+    if constexpr (W == 1) wave_sync();
     else __syncthreads();
 }
 
 // Move NP polys from the layout of phase `from` to that of phase `to`
 // through the LDS slot (NP <= 2).  L is the virtual lane.
-template <int N, int NP>
-__device__ __forceinline__ void relayout(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, int L, int from,
+template <int N, int NP, int W = default_wpp(N)>
+__device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, int L, int from,
                                          int to)
 {
-    using G = Geo<N>;
-    poly_sync<N>();
+    using G = Geo<N, W>;
+    static_assert(swz_split_holds<N, W>(), "LDS address split");
+    uint32_t *sf = slot + swz_base<N, W>(from, L), *st = slot + swz_base<N, W>(to, L);
+    poly_sync<N, W>();
 #pragma unroll
     for (int q = 0; q < NP; q++)
 #pragma unroll
-        for (int k = 0; k < G::E; k++) slot[q * G::POLYW + swz(idx_of<N>(from, L, k))] = x[q][k];
-    poly_sync<N>();
+        for (int k = 0; k < G::E; k++) sf[q * G::POLYW + swz_off(G::R(from), k)] = x[q][k];
+    poly_sync<N, W>();
 #pragma unroll
     for (int q = 0; q < NP; q++)
 #pragma unroll
-        for (int k = 0; k < G::E; k++) x[q][k] = slot[q * G::POLYW + swz(idx_of<N>(to, L, k))];
+        for (int k = 0; k < G::E; k++) x[q][k] = st[q * G::POLYW + swz_off(G::R(to), k)];
 }
 
 // Forward negacyclic NTT (Cooley-Tukey, merged psi powers, natural order in,
 // bit-reversed order out) of NP polys held in phase-0 layout; returns them in
 // the last phase's layout, reduced to [0, Q) (inputs in [0, Q)).
 // twf[k] = psi^bitrev(k) 2^32 mod Q.
-template <int N, int NP>
-__device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, const uint32_t *twf,
+template <int N, int NP, int W = default_wpp(N)>
+__device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twf,
                                         int L, const ModQ &m)
 {
-    using G = Geo<N>;
+    using G = Geo<N, W>;
 #pragma unroll
     for (int p = 0; p < G::NPH; p++) {
         const int R = G::R(p);
         if (p > 0) {
-            relayout<N, NP>(x, slot, L, p - 1, p);
+            relayout<N, NP, W>(x, slot, L, p - 1, p);
             // the previous phase left its last stage unreduced; reduce the values
             // that are not multiplicands of this phase's first stage
             const int kt = G::HI(p) - R;
@@ -180,11 +213,11 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][Geo<N>::E], uint32_t *
 // Inverse negacyclic NTT (Gentleman-Sande, bit-reversed in, natural out),
 // without the 1/N factor: polys arrive in the last phase's layout and leave in
 // phase-0 layout.  twi[k] = psi^-bitrev(k) 2^32 mod Q.
-template <int N, int NP>
-__device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][Geo<N>::E], uint32_t *slot, const uint32_t *twi,
+template <int N, int NP, int W = default_wpp(N)>
+__device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twi,
                                         int L, const ModQ &m)
 {
-    using G = Geo<N>;
+    using G = Geo<N, W>;
 #pragma unroll
     for (int p = G::NPH - 1; p >= 0; p--) {
         const int R = G::R(p);
@@ -205,7 +238,7 @@ __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][Geo<N>::E], uint32_t *
                 }
             }
         }
-        if (p > 0) relayout<N, NP>(x, slot, L, p, p - 1);
+        if (p > 0) relayout<N, NP, W>(x, slot, L, p, p - 1);
     }
 }
 

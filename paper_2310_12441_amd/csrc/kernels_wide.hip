@@ -5,7 +5,7 @@
 // 1024 components), so it lives in device memory as [component][part][prime][N]
 // residues, double-buffered, and every CMux step is one launch over all
 // (ciphertext, component) pairs: the launch boundary is the barrier between
-// steps.  Workgroup k_wide_step owns one pair for one step:
+// steps.  Workgroup k_wide_step (N / 512 waves) owns one pair for one step:
 //   1. reads its own component and the one that Phi(-a'_i) brings to it (index
 //      and sign remap of the source, eq. ex1:BPc), both primes, and forms
 //      D = Phi(-a'_i) ACC_j - ACC_j;
@@ -80,10 +80,17 @@ __global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
     }
 }
 
-template <int N, int KEYS>
-__global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
+// W waves per polynomial: N / 512 (8 coefficients per lane) and at least three
+// waves per SIMD (a few spilled loop-invariant LDS addresses) hide the
+// accumulator loads and the workgroup barriers of the relayouts: measured at
+// N = 2048, 16384 components, 982 ms per 512 steps with 16 coefficients per lane
+// and 2 waves, 904 ms with 8 and 2 waves, 794 ms with 8 and 3, 810 ms with 8 and 4.
+constexpr int wide_wpp(int N) { return N > 512 ? N / 512 : 1; }
+
+template <int N, int KEYS, int W = wide_wpp(N)>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_wide_step(WideArgs A)
 {
-    using G = Geo<N>;
+    using G = Geo<N, W>;
     constexpr int E = G::E;
     __shared__ uint32_t slot[G::SLOTW];
     const WideTask T = A.tasks[blockIdx.x];
@@ -118,47 +125,46 @@ __global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
                 y[part][k] = (uint64_t)xc + A.goff;
             }
     };
-    if constexpr (KEYS == 1) digit_fields(0);
     uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
-    // one prime at a time: NTT-domain output from the digit-offset correction,
-    // the products with BSK_i, inverse NTT, accumulate and store
-#pragma unroll
-    for (int pr = 0; pr < 2; pr++) {
-        uint32_t out[2][E];
+    // NTT-domain output of one prime from the digit-offset correction
+    auto start = [&](int pr, uint32_t (&out)[2][E]) {
         const uint32_t *corr = A.bsk_corr + ((size_t)A.step * 2 + pr) * 2 * N + L * E;
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
             for (int k = 0; k < E; k++) out[part][k] = corr[part * N + k];
-        for (int key = 0; key < KEYS; key++) {
-            if constexpr (KEYS == 2) digit_fields(key);
-            const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * 2 + pr) * (2 * A.l * 2 * N);
-            for (uint32_t u = 0; u < A.l; u++) {
-                __asm__ volatile("" ::: "memory");
-                const uint32_t sh = u * A.log2B;
-                const uint64_t mask = u + 1 == A.l ? ~0ull : (1ull << A.log2B) - 1;
-                uint32_t pd[2][E];
+    };
+    // out += the digits of y times BSK_{i,key} for one prime (eq. def:gsw)
+    auto mac = [&](int pr, int key, uint32_t (&out)[2][E]) {
+        const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * 2 + pr) * (2 * A.l * 2 * N);
+        for (uint32_t u = 0; u < A.l; u++) {
+            __asm__ volatile("" ::: "memory");
+            const uint32_t sh = u * A.log2B;
+            const uint64_t mask = u + 1 == A.l ? ~0ull : (1ull << A.log2B) - 1;
+            uint32_t pd[2][E];
 #pragma unroll
-                for (int k = 0; k < E; k++) {
-                    pd[0][k] = (uint32_t)((y[1][k] >> sh) & mask);  // digit of b meets rows u
-                    pd[1][k] = (uint32_t)((y[0][k] >> sh) & mask);  // digit of a meets rows l + u
-                }
-                ntt_fwd<N, 2>(pd, slot, twf[pr], L, m[pr]);
-                const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N + L * E;
-                const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N + L * E;
-                const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N + L * E;
-                const uint32_t *ka_b = Kp + ((size_t)(A.l + u) * 2 + 1) * N + L * E;
+            for (int k = 0; k < E; k++) {
+                pd[0][k] = (uint32_t)((y[1][k] >> sh) & mask);  // digit of b meets rows u
+                pd[1][k] = (uint32_t)((y[0][k] >> sh) & mask);  // digit of a meets rows l + u
+            }
+            ntt_fwd<N, 2, W>(pd, slot, twf[pr], L, m[pr]);
+            const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N + L * E;
+            const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N + L * E;
+            const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N + L * E;
+            const uint32_t *ka_b = Kp + ((size_t)(A.l + u) * 2 + 1) * N + L * E;
 #pragma unroll
-                for (int k = 0; k < E; k++) {
-                    const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
-                    const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
-                    out[0][k] = add_q(out[0][k], redc(xa, m[pr]), m[pr].Q);
-                    out[1][k] = add_q(out[1][k], redc(xb, m[pr]), m[pr].Q);
-                }
+            for (int k = 0; k < E; k++) {
+                const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
+                const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
+                out[0][k] = add_q(out[0][k], redc(xa, m[pr]), m[pr].Q);
+                out[1][k] = add_q(out[1][k], redc(xb, m[pr]), m[pr].Q);
             }
         }
+    };
+    // inverse NTT, ACC_j + product, store to the other buffer
+    auto finish = [&](int pr, uint32_t (&out)[2][E]) {
         __asm__ volatile("" ::: "memory");
-        ntt_inv<N, 2>(out, slot, twi[pr], L, m[pr]);
+        ntt_inv<N, 2, W>(out, slot, twi[pr], L, m[pr]);
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
@@ -167,6 +173,30 @@ __global__ __launch_bounds__(64 * Geo<N>::WPP) void k_wide_step(WideArgs A)
                 const size_t at = (size_t)part * 2 * N + pr * N + idx;
                 wr[at] = add_q(out[part][k], own[at], m[pr].Q);
             }
+    };
+    if constexpr (KEYS == 1) {
+        // one prime at a time: only one prime's outputs are live
+        digit_fields(0);
+#pragma unroll
+        for (int pr = 0; pr < 2; pr++) {
+            uint32_t out[2][E];
+            start(pr, out);
+            mac(pr, 0, out);
+            finish(pr, out);
+        }
+    } else {
+        // one prime at a time as well; each key's digit fields are formed again
+        // for the second prime (cheaper than keeping both primes' outputs live)
+#pragma unroll
+        for (int pr = 0; pr < 2; pr++) {
+            uint32_t out[2][E];
+            start(pr, out);
+            for (int key = 0; key < 2; key++) {
+                digit_fields(key);
+                mac(pr, key, out);
+            }
+            finish(pr, out);
+        }
     }
 }
 
@@ -236,8 +266,8 @@ void launch_wide_init(uint32_t N, const WideArgs &A, uint32_t num_tasks, hipStre
 void launch_wide_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
 {
 #define C_(n)                                                                                              \
-    if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2>), dim3(num_tasks), dim3(64 * Geo<n>::WPP), 0, st, A); \
-    else hipLaunchKernelGGL((k_wide_step<n, 1>), dim3(num_tasks), dim3(64 * Geo<n>::WPP), 0, st, A)
+    if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A); \
+    else hipLaunchKernelGGL((k_wide_step<n, 1>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A)
     WIDE_DISPATCH(N, C_)
 #undef C_
 }

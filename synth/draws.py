@@ -83,10 +83,11 @@ PRESETS = {
     "paper_shaped": dict(params=Params(n=630, N=1024, log2_B=7, l=4), t=4096, t_out=4096, r=4),
     "tfhe_shaped": dict(params=Params(n=630, N=4096, log2_B=7, l=4), t=4096, t_out=4096, r=1),
     # The parameters of the experiments in Sec. 5: log n = 9, log N = 11, a ring
-    # modulus of 54 bits (2147352577 x 8380417), gadget 2^15 x 4, q = 2Nr with
-    # 2Nr / t = 128 (so r = t / 32, log r = log t - 5 as in Tables 1-2); t = 2^12
-    # needs r = 128.
-    "paper_margin": dict(params=Params(n=512, N=2048, log2_B=15, l=4, Q2=Q2_DEFAULT), t=4096, t_out=4096, r=128),
+    # modulus of 54 bits (2147352577 x 8380417), gadget 2^15 x 4, a ternary secret
+    # (two RGSW keys per coordinate), q = 2Nr with 2Nr / t = 128 (so r = t / 32,
+    # log r = log t - 5 as in Tables 1-2); t = 2^12 needs r = 128.
+    "paper_margin": dict(params=Params(n=512, N=2048, log2_B=15, l=4, Q2=Q2_DEFAULT, ternary=True), t=4096,
+                         t_out=4096, r=128),
 }
 
 # (t, r) classes of the uneven batch and of the serving trace: q = 2Nr each.
