@@ -207,7 +207,7 @@ def main():
         "unit": "TOP/s",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
         "traffic": measured_traffic(),
-        "kernel": f"k_blind_rotate<1024,{sched[0]},1>",
+        "kernel": f"k_blind_rotate<1024,{sched[0]},1{',2' if sched[3] == 2 else ''}>",
         "kernel_ms": round(br_avg * 1e3, 3),
         "ops_per_launch": ops,
         "hbm_algorithmic_bytes": hbm_alg,
@@ -252,7 +252,7 @@ def main():
         mixed = {"batch": M, "classes": [list(c) for c in CLASS_MIX], "bootstraps_per_s": round(M / x_s, 1),
                  "ms_per_batch": round(x_s * 1e3, 3), "components": int(rs.sum()),
                  "schedule": {"index": x_sched, "group_waves": x_desc[0], "ks_cts_per_wave": x_desc[1],
-                              "ks_splits": x_desc[2]}}
+                              "ks_splits": x_desc[2], "waves_per_component": x_desc[3]}}
 
     # ---- Sec. 5 comparison: each class (t, k) by MMPM (N = 1024, r = k) and by one
     # ring of degree N k (r = 1, TFHE-shaped), same n, gadget and key switch
@@ -371,7 +371,8 @@ def main():
         "batched_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
         "plain_equals_batched": plain_same,
         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
-        "schedule": {"index": schedule, "group_waves": sched[0], "ks_cts_per_wave": sched[1], "ks_splits": sched[2]},
+        "schedule": {"index": schedule, "group_waves": sched[0], "ks_cts_per_wave": sched[1], "ks_splits": sched[2],
+                     "waves_per_component": sched[3]},
         "mixed_classes": mixed,
         "mmpm_vs_tfhe_shaped": comparison,
         "roofline": roofline,

@@ -244,9 +244,12 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
 
 /* What schedule `choice` of this batch shape is (choice < 0: the one in use):
  * waves per blind-rotation workgroup (8 or 4), ciphertexts per wave of the
- * LDS-tiled key switch (0 = the i-split key switch) and the number of i splits. */
+ * LDS-tiled key switch (0 = the i-split key switch), the number of i splits,
+ * and waves per ring component (1 up to N = 1024 and N / 1024 above by default;
+ * 2 at N = 512 and 1024 for batches that do not fill the device, r <= 4).  Any
+ * output pointer may be NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
-                         int *ks_cts_per_wave, int *ks_splits);
+                         int *ks_cts_per_wave, int *ks_splits, int *waves_per_component);
 
 /* ---- serving: continuous batching ---- */
 

@@ -294,7 +294,7 @@ uint32_t spread_cap(const Device &d, uint64_t comps, uint32_t gw, uint32_t wpp)
 
 static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const Device &d, const int *ids, size_t count,
                                               uint32_t flags, uint32_t i0, const std::vector<uint64_t> &acc_off,
-                                              uint32_t gw = 8)
+                                              uint32_t gw = 8, uint32_t wpp = 0)
 {
     std::vector<dev::WaveTask> cts(count);
     for (size_t k = 0; k < count; k++) {
@@ -311,7 +311,7 @@ static std::vector<dev::WaveTask> pack_groups(const mm_ctx &c, const Device &d, 
     }
     uint64_t comps = 0;
     for (auto &t : cts) comps += t.r;
-    const uint32_t wpp = (uint32_t)dev::waves_per_poly(c.p.N);
+    if (!wpp) wpp = (uint32_t)dev::waves_per_poly(c.p.N);
     return pack_tasks(cts, gw, wpp, spread_cap(d, comps, gw, wpp));
 }
 
@@ -425,7 +425,22 @@ static std::string shape_key(const mm_ctx &c, const int *ids, size_t count)
            std::to_string(max_r(c, ids, count));
 }
 
-// Candidate schedules for a batch: group width x key-switch tiling.
+// Two waves per component (N = 512, 1024, r <= 4): for batches that do not
+// fill every compute unit, both waves of a slot share one component's work.
+static bool wide_slots_ok(const mm_ctx &c, const int *ids, size_t count)
+{
+    return dev::br_supports_wpp(c.p.N, 2) && dev::waves_per_poly(c.p.N) == 1 && max_r(c, ids, count) <= 4;
+}
+
+static uint64_t sum_r(const mm_ctx &c, const int *ids, size_t count)
+{
+    uint64_t s = 0;
+    for (size_t i = 0; i < count; i++) s += c.tables[ids[i]].r;
+    return s;
+}
+
+// Candidate schedules for a batch: blind-rotation shape (8-wave groups, 4-wave
+// groups, 8-wave groups of 2-wave slots) x key-switch tiling.
 static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int *ids, size_t count)
 {
     std::vector<Sched> out;
@@ -443,6 +458,8 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
         if (gw == 4 && !narrow_ok) continue;
         for (auto &k : ks) out.push_back(Sched{gw, k});
     }
+    if (wide_slots_ok(c, ids, count))
+        for (auto &k : ks) out.push_back(Sched{8, k, 2});
     return out;
 }
 
@@ -453,7 +470,10 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         auto cand = candidates(c, d, ids, count);
         if (it->second >= 0 && (size_t)it->second < cand.size()) return cand[it->second];
     }
-    return Sched{8, ks_default(c, d, count)};
+    // untuned: 2-wave slots while the components fit half-full groups on every
+    // compute unit (the chip is not full), else the full-width default
+    const bool light = sum_r(c, ids, count) <= 4ull * (uint64_t)d.num_cu;
+    return Sched{8, ks_default(c, d, count), light && wide_slots_ok(c, ids, count) ? 2 : 0};
 }
 
 static int br_grid(const Device &d, int groups, int gw) { return std::min(groups, d.num_cu * (gw == 4 ? 2 : 1)); }
@@ -543,7 +563,8 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
     }
     const uint32_t N = c.p.N;
     const Sched S = force ? *force : schedule_for(c, d, ids, count);
-    auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw);
+    auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw,
+                             (uint32_t)S.wpp);
     const int groups = (int)(tasks.size() / S.gw);
     uint32_t q_scalar = q_out;
     const uint32_t *qv = resolve_q_out(c, d, ids, count, q_scalar, st);
@@ -562,11 +583,12 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
     const int grid = br_grid(d, groups, S.gw);
 
     const std::string key = std::to_string(count) + "/" + std::to_string(groups) + "/" + std::to_string(S.gw) + "/" +
-                            std::to_string(S.ks.cpw) + "/" + std::to_string(S.ks.P) + "/" + std::to_string(q_scalar) +
+                            std::to_string(S.wpp) + "/" + std::to_string(S.ks.cpw) + "/" + std::to_string(S.ks.P) +
+                            "/" + std::to_string(q_scalar) +
                             "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
                             std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
     run_sequence(
-        d, key, use_graph, st, [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s); },
+        d, key, use_graph, st, [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s, S.wpp); },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, S.ks, part, s); });
 }
 
@@ -903,7 +925,7 @@ void set_schedule(mm_ctx &c, const int *ids, size_t count, int choice)
     c.dev->tuned[shape_key(c, ids, count)] = choice;
 }
 
-void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P)
+void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P, int *wpp)
 {
     const int n = schedule_count(c, ids, count);
     MM_REQUIRE(choice < n, "schedule index out of range");
@@ -912,11 +934,13 @@ void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int 
     if (gw) *gw = S.gw;
     if (cpw) *cpw = S.ks.cpw;
     if (P) *P = (int)S.ks.P;
+    if (wpp) *wpp = S.wpp ? S.wpp : dev::waves_per_poly(c.p.N);
 }
 
-// Time the group widths (with the default key switch) and the key-switch
-// tilings (with 8-wave groups) on this batch, one untimed run each first, and
-// remember the fastest combination for the batch shape.
+// Time each blind-rotation shape (group width, waves per component; with the
+// default key switch) and each key-switch tiling (with the first shape) on this
+// batch, one untimed run each first, and remember the fastest combination for
+// the batch shape.
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
 {
     MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no autotuning)");
@@ -933,13 +957,16 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
     if (!d.tev[0])
         for (auto &e : d.tev) HIPC(hipEventCreate(&e));
     d.timing = true;
-    float best_br[2] = {1e30f, 1e30f}, best_ks = 1e30f;
-    KsSched ks_best = cand[0].ks;
     const KsSched ks0 = cand[0].ks;
+    const Sched first = cand[0];
+    float best_br = 1e30f, best_ks = 1e30f;
+    Sched br_best = first;
+    KsSched ks_best = ks0;
     for (size_t k = 0; k < cand.size(); k++) {
         const Sched &S = cand[k];
         const bool default_ks = S.ks.cpw == ks0.cpw && S.ks.P == ks0.P;
-        if (!default_ks && S.gw != 8) continue;  // each key-switch tiling is timed once
+        const bool first_shape = S.gw == first.gw && S.wpp == first.wpp;
+        if (!default_ks && !first_shape) continue;  // each key-switch tiling is timed once
         bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
         HIPC(hipStreamSynchronize(st));
         bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
@@ -947,17 +974,21 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
         float br = 0, ks = 0;
         HIPC(hipEventElapsedTime(&br, d.tev[0], d.tev[1]));
         HIPC(hipEventElapsedTime(&ks, d.tev[1], d.tev[2]));
-        if (default_ks) best_br[S.gw == 4 ? 1 : 0] = std::min(best_br[S.gw == 4 ? 1 : 0], br);
-        if (S.gw == 8 && ks < best_ks) {
+        if (default_ks && br < best_br) {
+            best_br = br;
+            br_best = S;
+        }
+        if (first_shape && ks < best_ks) {
             best_ks = ks;
             ks_best = S.ks;
         }
     }
     d.timing = was_timed;
-    const int gw = best_br[1] < best_br[0] ? 4 : 8;
     int choice = 0;
     for (size_t k = 0; k < cand.size(); k++)
-        if (cand[k].gw == gw && cand[k].ks.cpw == ks_best.cpw && cand[k].ks.P == ks_best.P) choice = (int)k;
+        if (cand[k].gw == br_best.gw && cand[k].wpp == br_best.wpp && cand[k].ks.cpw == ks_best.cpw &&
+            cand[k].ks.P == ks_best.P)
+            choice = (int)k;
     d.tuned[shape_key(c, ids, count)] = choice;
     return choice;
 }

@@ -284,12 +284,12 @@ __device__ __forceinline__ uint32_t gadget_field_start(uint32_t x, uint32_t off_
 // (eq. def:gsw).  out stays in the last phase's layout.  With OFF the digits
 // enter shifted by +B/2 (g.off then holds (B/2)(1 + ... + B^(l-1))) and the
 // caller starts out from minus (B/2) sum_rows K.
-template <int N, bool OFF = false>
-__device__ __forceinline__ void ext_mac(const uint32_t (&Da)[Geo<N>::E], const uint32_t (&Db)[Geo<N>::E],
+template <int N, bool OFF = false, int W = default_wpp(N)>
+__device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], const uint32_t (&Db)[(Geo<N, W>::E)],
                                         const uint32_t *__restrict__ K, uint32_t *slot, const uint32_t *twf, int L,
-                                        const ModQ &m, const GadgetC &g, uint32_t (&out)[2][Geo<N>::E])
+                                        const ModQ &m, const GadgetC &g, uint32_t (&out)[2][(Geo<N, W>::E)])
 {
-    using G = Geo<N>;
+    using G = Geo<N, W>;
     constexpr int E = G::E;
     uint32_t ya[E], yb[E];
 #pragma unroll
@@ -317,7 +317,7 @@ __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[Geo<N>::E], const u
                 pd[1][k] = gadget_digit((int32_t)ya[k], u, g, m.Q);
             }
         }
-        ntt_fwd<N, 2>(pd, slot, twf, L, m);
+        ntt_fwd<N, 2, W>(pd, slot, twf, L, m);
         // virtual lane L now holds NTT positions E L .. E L + E - 1
         const uint32_t *kb_a = K + ((size_t)(u)*2 + 0) * N + L * E;
         const uint32_t *kb_b = K + ((size_t)(u)*2 + 1) * N + L * E;

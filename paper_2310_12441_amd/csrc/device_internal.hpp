@@ -87,10 +87,12 @@ struct KsSched {
     uint32_t P = 1;
 };
 
-// A batch schedule: blind-rotation group width (8 or 4 waves) and key switch.
+// A batch schedule: blind-rotation group width (8 or 4 waves), waves per
+// component polynomial (0: the ring's default) and key switch.
 struct Sched {
     int gw = 8;
     KsSched ks;
+    int wpp = 0;
 };
 
 std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp,

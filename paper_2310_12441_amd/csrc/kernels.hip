@@ -79,10 +79,10 @@ struct BrLds {
     static_assert(BUF_WORDS == Geo<N>::SLOTW, "an accumulator buffer doubles as the exchange slot");
 };
 
-template <int N, int GW, int KEYS>
+template <int N, int GW, int KEYS, int W = default_wpp(N)>
 __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
-    using G = Geo<N>;
+    using G = Geo<N, W>;
     using LD = BrLds<N>;
     constexpr int E = G::E, P = G::POLYW, WPP = G::WPP, LN = G::LANES;
     static_assert(GW % WPP == 0, "a group holds whole component slots");
@@ -181,15 +181,15 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
                     o[0][k] = C0[k];
                     o[1][k] = C0[N + k];
                 }
-                ext_mac<N, true>(D[0], D[1], K, nxt, A.twf, L, m, g, o);
+                ext_mac<N, true, W>(D[0], D[1], K, nxt, A.twf, L, m, g, o);
             }
             if (KEYS == 2) {
                 if (active) rotated_diff(ai, accl, D);  // +a'_i from the same accumulator
-                if (run) ext_mac<N, true>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o);
+                if (run) ext_mac<N, true, W>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o);
             }
             if (run) {
                 __asm__ volatile("" ::: "memory");
-                ntt_inv<N, 2>(o, nxt, A.twi, L, m);
+                ntt_inv<N, 2, W>(o, nxt, A.twi, L, m);
             }
             if (WPP > 1) __syncthreads();  // every lane of the slot has left the exchange slot
             if (active) {
@@ -532,11 +532,15 @@ void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, 
 
 // ------------------------------------------------------------------ launchers
 
-template <int N, int GW, int KEYS>
+// Two waves per polynomial at N = 512 and 1024 (half the registers' work per
+// wave: lower latency for batches too small to fill the chip).
+constexpr bool br_wide_slots(int N) { return N == 512 || N == 1024; }
+
+template <int N, int GW, int KEYS, int W = default_wpp(N)>
 static hipError_t br_attr_n()
 {
-    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)br_lds_bytes(N, GW));
+    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS, W>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(N, GW, W));
 }
 
 template <int N>
@@ -547,6 +551,10 @@ static hipError_t br_attr_all()
     if constexpr (Geo<N>::WPP <= 4) {
         if (e == hipSuccess) e = br_attr_n<N, 4, 1>();
         if (e == hipSuccess) e = br_attr_n<N, 4, 2>();
+    }
+    if constexpr (br_wide_slots(N)) {
+        if (e == hipSuccess) e = br_attr_n<N, 8, 1, 2>();
+        if (e == hipSuccess) e = br_attr_n<N, 8, 2, 2>();
     }
     return e;
 }
@@ -589,8 +597,14 @@ bool device_supports_n(uint32_t N)
 int waves_per_poly(uint32_t N) { return N > 1024 ? (int)(N / 1024) : 1; }
 
 template <int N, int KEYS>
-static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st)
+static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp)
 {
+    if constexpr (br_wide_slots(N)) {
+        if (wpp == 2) {
+            hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS, 2>), dim3(grid), dim3(512), br_lds_bytes(N, 8, 2), st, A);
+            return;
+        }
+    }
     if constexpr (Geo<N>::WPP <= 4) {
         if (gw == 4) {
             hipLaunchKernelGGL((k_blind_rotate<N, 4, KEYS>), dim3(grid), dim3(256), br_lds_bytes(N, 4), st, A);
@@ -601,40 +615,42 @@ static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st)
 }
 
 template <int N>
-static void launch_br_n(const BrArgs &A, int gw, int grid, hipStream_t st)
+static void launch_br_n(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp)
 {
-    if (A.keys == 2) launch_br_nk<N, 2>(A, gw, grid, st);
-    else launch_br_nk<N, 1>(A, gw, grid, st);
+    if (A.keys == 2) launch_br_nk<N, 2>(A, gw, grid, st, wpp);
+    else launch_br_nk<N, 1>(A, gw, grid, st, wpp);
 }
 
-void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st)
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp)
 {
     switch (N) {
-    case 256: launch_br_n<256>(A, gw, grid, st); break;
-    case 512: launch_br_n<512>(A, gw, grid, st); break;
-    case 1024: launch_br_n<1024>(A, gw, grid, st); break;
-    case 2048: launch_br_n<2048>(A, gw, grid, st); break;
-    case 4096: launch_br_n<4096>(A, gw, grid, st); break;
-    case 8192: launch_br_n<8192>(A, gw, grid, st); break;
+    case 256: launch_br_n<256>(A, gw, grid, st, wpp); break;
+    case 512: launch_br_n<512>(A, gw, grid, st, wpp); break;
+    case 1024: launch_br_n<1024>(A, gw, grid, st, wpp); break;
+    case 2048: launch_br_n<2048>(A, gw, grid, st, wpp); break;
+    case 4096: launch_br_n<4096>(A, gw, grid, st, wpp); break;
+    case 8192: launch_br_n<8192>(A, gw, grid, st, wpp); break;
     default: break;
     }
 }
 
+bool br_supports_wpp(uint32_t N, int wpp) { return wpp == waves_per_poly(N) || (wpp == 2 && br_wide_slots((int)N)); }
+
 template <int N>
-static size_t br_lds_n(int gw)
+static size_t br_lds_n(int gw, int wpp)
 {
-    return (size_t)(gw / Geo<N>::WPP) * BrLds<N>::COMP_WORDS * sizeof(uint32_t);
+    return (size_t)(gw / (wpp ? wpp : Geo<N>::WPP)) * BrLds<N>::COMP_WORDS * sizeof(uint32_t);
 }
 
-size_t br_lds_bytes(uint32_t N, int gw)
+size_t br_lds_bytes(uint32_t N, int gw, int wpp)
 {
     switch (N) {
-    case 256: return br_lds_n<256>(gw);
-    case 512: return br_lds_n<512>(gw);
-    case 1024: return br_lds_n<1024>(gw);
-    case 2048: return br_lds_n<2048>(gw);
-    case 4096: return br_lds_n<4096>(gw);
-    default: return br_lds_n<8192>(gw);
+    case 256: return br_lds_n<256>(gw, wpp);
+    case 512: return br_lds_n<512>(gw, wpp);
+    case 1024: return br_lds_n<1024>(gw, wpp);
+    case 2048: return br_lds_n<2048>(gw, wpp);
+    case 4096: return br_lds_n<4096>(gw, wpp);
+    default: return br_lds_n<8192>(gw, wpp);
     }
 }
 

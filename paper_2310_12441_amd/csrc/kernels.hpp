@@ -98,7 +98,10 @@ void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, 
                         const uint32_t *qs, hipStream_t st);
 void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows, size_t count, uint32_t W,
                          hipStream_t st);
-void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st);
+// wpp: waves per polynomial (0: one up to N = 1024, N / 1024 above; 2 is also
+// available at N = 512 and 1024, see br_supports_wpp).
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp = 0);
+bool br_supports_wpp(uint32_t N, int wpp);
 // wide modulus: ACC = Phi(b')(0, V) into A.acc_wr; one CMux step (A.step) from
 // A.acc_rd into A.acc_wr; extraction of component 0 switched to Q[0]
 // (ext[c] from the component at acc_off[c]); the accumulator as uint64 values
@@ -108,7 +111,7 @@ void launch_wide_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num
 void launch_wide_extract(uint32_t N, const WideArgs &A, const uint64_t *acc_off, size_t count, uint32_t *ext,
                          hipStream_t st);
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st);
-size_t br_lds_bytes(uint32_t N, int gw);
+size_t br_lds_bytes(uint32_t N, int gw, int wpp = 0);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
                              const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,
                              uint32_t l, uint32_t sg, hipStream_t st);

@@ -304,6 +304,8 @@ def test_every_schedule_gives_the_same_bits(paper):
     n = paper.ctx.schedule_count(ids)
     say("schedules", n)
     assert n >= 4
+    # 2-wave component slots are among the candidates (N = 1024, r <= 4)
+    assert {paper.ctx.schedule_describe(ids, k)[3] for k in range(n)} == {1, 2}
     ref = None
     for choice in range(n):
         paper.ctx.set_schedule(ids, choice)
@@ -452,3 +454,37 @@ def test_empty_and_ragged_batches(paper):
         np.testing.assert_array_equal(paper.ctx.bootstrap([tid] * cnt, ct[:cnt]), full[:cnt], err_msg=f"count {cnt}")
     np.testing.assert_array_equal(full[130], oracle.bootstrap(paper.p, 4, paper.keys.bsk, paper.keys.ksk, V, 8192,
                                                               8192, ct[130]))
+
+
+@pytest.mark.parametrize("N,ternary", [(1024, False), (1024, True), (512, False), (512, True)])
+def test_two_wave_slots_small_batches(N, ternary):
+    """Batches too small to fill the device run each component on two waves
+    (N = 512, 1024, r <= 4): blind rotation and bootstrap against the oracle, and
+    the same bits as the one-wave schedule."""
+    from dataclasses import replace
+    say("two-wave slots N", N, "ternary", ternary)
+    p = replace(Params(n=12, N=N, log2_B=7, l=4), ternary=ternary)
+    c = Case(p, 1500 + N + ternary)
+    tid, f, V = c.table(2 * N, 2 * N, 4, 31)  # r = 4, t = 2N
+    tid8, f8, V8 = c.table(64, 64, 8, 32)     # r = 8 does not fit 2-wave slots
+    q = 2 * N * 4
+    ct = c.encrypt(q, 2 * N, messages(2 * N, 3, 33), 34)
+    ids = np.full(3, tid, np.int32)
+    assert c.ctx.schedule_describe(ids)[3] == 2
+    assert c.ctx.schedule_describe(np.full(3, tid8, np.int32))[3] == 1
+    acc = c.ctx.blind_rotate(ids, ct, 5)
+    for j in range(3):
+        np.testing.assert_array_equal(acc[j * 4 * 2 * N:(j + 1) * 4 * 2 * N].reshape(4, 2, N),
+                                      oracle.blind_rotate(p, 4, c.keys.bsk, V, ct[j], 5))
+    out = c.ctx.bootstrap(ids, ct)
+    np.testing.assert_array_equal(out, oracle.bootstrap_many(p, 4, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct, plain=True), out)
+    n = c.ctx.schedule_count(ids)
+    for k in range(n):
+        c.ctx.set_schedule(ids, k)
+        np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), out, err_msg=f"schedule {k}")
+    q8 = 2 * N * 8
+    ct8 = c.encrypt(q8, 64, messages(64, 2, 35), 36)
+    np.testing.assert_array_equal(c.ctx.bootstrap([tid8] * 2, ct8),
+                                  oracle.bootstrap_many(p, 8, c.keys.bsk, c.keys.ksk, V8, q8, q8, ct8))
+    c.ctx.close()
