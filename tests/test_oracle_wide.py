@@ -309,3 +309,28 @@ def test_w_identity_function_by_two_bootstraps_decrypts_at_delta_128():
     ct = oracle.encrypt(p.n, q, 2 * t, keys.s, m, ed["a"], ed["e"])
     out = oracle.w_bootstrap_general(p, r, keys.bsk, keys.ksk, Vg, VF, q, t, q, ct)
     np.testing.assert_array_equal(oracle.decrypt(p.n, q, t, keys.s, out), m)
+
+
+def test_w_switch_after_extraction_scales_the_phase():
+    """After extraction each coefficient is switched Q_w -> Q by rounding, so the
+    sample's phase at Q is the accumulator's constant phase at Q_w times Q / Q_w,
+    up to the rounding of N + 1 terms: |err| <= (||z||_1 + 1) / 2 (Sec. 2 item (9))."""
+    p = wide(6, 32)
+    r, t = 2, 4
+    q = 2 * p.N * r
+    dr = key_draws(p, 50)
+    keys = oracle.KeySetWide(p, dr)
+    f = negacyclic_table(t, t, 51)
+    V = oracle.w_test_vector(p.N, r, QW, t, t, f)
+    z = [int(v) for v in dr["z"]]
+    ed = enc_draws(p.n, q, 4, 52)
+    cts = oracle.encrypt(p.n, q, t, keys.s, messages(t, 4, 53), ed["a"], ed["e"])
+    for ct in cts:
+        acc = oracle.w_blind_rotate(p, r, keys.bsk, V, ct)
+        ph_w = big_phase(acc[0, 0], acc[0, 1], z, QW)[0]
+        _, ext = oracle.w_bootstrap(p, r, keys.bsk, keys.ksk, V, q, q, ct, ext_out=True)
+        ph_q = (int(ext[p.N]) - sum(int(a) * zk for a, zk in zip(ext[:p.N], z))) % Q
+        want = Fraction(ph_w * Q, QW)
+        diff = (ph_q - want) % Q
+        diff = diff - Q if diff > Q // 2 else diff
+        assert abs(diff) <= Fraction(sum(z) + 1, 2), (ph_w, ph_q, float(diff))
