@@ -92,14 +92,21 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
 {
     using G = Geo<N, W>;
     constexpr int E = G::E;
-    __shared__ uint32_t slot[G::SLOTW];
+    // a ternary secret keeps the first key's digit fields in LDS (each lane reads
+    // back only its own), so each key's fields are formed once per step
+    // (one array for both, so no alignment gap: three workgroups per CU at N = 2048)
+    constexpr bool Y_LDS = KEYS == 2 && (G::SLOTW * 4 + 2 * N * 8) <= 65536;
+    static_assert(G::SLOTW % 2 == 0, "the slot ends on an 8-byte boundary");
+    __shared__ uint64_t lds64[G::SLOTW / 2 + (Y_LDS ? 2 * N : 0)];
+    uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64);
+    uint64_t *const ylds = lds64 + G::SLOTW / 2;
     const WideTask T = A.tasks[blockIdx.x];
     const int L = threadIdx.x;
     const uint32_t M = 2u * N * T.r;
     const uint32_t am = wide_modswitch(A.ct_in[(size_t)T.ct * A.ct_stride + A.step], T.q_in, M);
-    const ModQ m[2] = {{A.Q[0], A.qn[0]}, {A.Q[1], A.qn[1]}};
+    // per-prime constants by selection (no private arrays: those would be placed in LDS)
+    auto mod = [&](int pr) { return ModQ{pr ? A.Q[1] : A.Q[0], pr ? A.qn[1] : A.qn[0]}; };
     const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * 4 * N;
-    const uint32_t *twf[2] = {A.twf0, A.twf1}, *twi[2] = {A.twi0, A.twi1};
 
     // y'' = round(centred(D) / 2^sg) + goff per coefficient of parts a (0) and b
     // (1), D = Phi(c) ACC_j - ACC_j joined from its two residues
@@ -118,7 +125,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
                 const uint32_t d0 = sub_q(wide_rot_load(s, idx, w, N, A.Q[0]), o[idx], A.Q[0]);
                 const uint32_t d1 = sub_q(wide_rot_load(s + N, idx, w, N, A.Q[1]), o[N + idx], A.Q[1]);
                 // x = d0 + Q0 ((d1 - d0) Q0^-1 mod Q1), in [0, Q0 Q1)
-                const uint32_t kk = mont_mul(d1 + A.crt_cq - d0, A.crt_inv, m[1]);
+                const uint32_t kk = mont_mul(d1 + A.crt_cq - d0, A.crt_inv, mod(1));
                 const uint64_t x = d0 + (uint64_t)A.Q[0] * kk;
                 int64_t xc = x > half ? (int64_t)(x - A.Qw) : (int64_t)x;
                 if (A.sg) xc = (xc + (1ll << (A.sg - 1))) >> A.sg;
@@ -135,7 +142,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             for (int k = 0; k < E; k++) out[part][k] = corr[part * N + k];
     };
     // out += the digits of y times BSK_{i,key} for one prime (eq. def:gsw)
-    auto mac = [&](int pr, int key, uint32_t (&out)[2][E]) {
+    auto mac = [&](int pr, int key, uint32_t (&out)[2][E], bool from_lds = false) {
         const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * 2 + pr) * (2 * A.l * 2 * N);
         for (uint32_t u = 0; u < A.l; u++) {
             __asm__ volatile("" ::: "memory");
@@ -144,10 +151,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             uint32_t pd[2][E];
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                pd[0][k] = (uint32_t)((y[1][k] >> sh) & mask);  // digit of b meets rows u
-                pd[1][k] = (uint32_t)((y[0][k] >> sh) & mask);  // digit of a meets rows l + u
+                const uint64_t ya = from_lds ? ylds[k * G::LANES + L] : y[0][k];
+                const uint64_t yb = from_lds ? ylds[(E + k) * G::LANES + L] : y[1][k];
+                pd[0][k] = (uint32_t)((yb >> sh) & mask);  // digit of b meets rows u
+                pd[1][k] = (uint32_t)((ya >> sh) & mask);  // digit of a meets rows l + u
             }
-            ntt_fwd<N, 2, W>(pd, slot, twf[pr], L, m[pr]);
+            ntt_fwd<N, 2, W>(pd, slot, pr ? A.twf1 : A.twf0, L, mod(pr));
             const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N + L * E;
             const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N + L * E;
             const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N + L * E;
@@ -156,22 +165,22 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             for (int k = 0; k < E; k++) {
                 const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
                 const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
-                out[0][k] = add_q(out[0][k], redc(xa, m[pr]), m[pr].Q);
-                out[1][k] = add_q(out[1][k], redc(xb, m[pr]), m[pr].Q);
+                out[0][k] = add_q(out[0][k], redc(xa, mod(pr)), mod(pr).Q);
+                out[1][k] = add_q(out[1][k], redc(xb, mod(pr)), mod(pr).Q);
             }
         }
     };
     // inverse NTT, ACC_j + product, store to the other buffer
     auto finish = [&](int pr, uint32_t (&out)[2][E]) {
         __asm__ volatile("" ::: "memory");
-        ntt_inv<N, 2, W>(out, slot, twi[pr], L, m[pr]);
+        ntt_inv<N, 2, W>(out, slot, pr ? A.twi1 : A.twi0, L, mod(pr));
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
             for (int k = 0; k < E; k++) {
                 const uint32_t idx = G::LANES * k + L;
                 const size_t at = (size_t)part * 2 * N + pr * N + idx;
-                wr[at] = add_q(out[part][k], own[at], m[pr].Q);
+                wr[at] = add_q(out[part][k], own[at], mod(pr).Q);
             }
     };
     if constexpr (KEYS == 1) {
@@ -182,6 +191,22 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             uint32_t out[2][E];
             start(pr, out);
             mac(pr, 0, out);
+            finish(pr, out);
+        }
+    } else if constexpr (Y_LDS) {
+        // key 0's fields to LDS, key 1's stay in registers across both primes
+        digit_fields(0);
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int k = 0; k < E; k++) ylds[(part * E + k) * G::LANES + L] = y[part][k];
+        digit_fields(1);
+#pragma unroll
+        for (int pr = 0; pr < 2; pr++) {
+            uint32_t out[2][E];
+            start(pr, out);
+            mac(pr, 1, out);
+            mac(pr, 0, out, true);
             finish(pr, out);
         }
     } else {
