@@ -52,6 +52,15 @@ def ops_per_bootstrap(n, N, l, r):
     return n * r * per_comp
 
 
+# The paper's own times for the same workload (identity f by two bootstraps, n = 2^9,
+# N = 2^11, log Q = 54, B = 2^15, q = 128 t), seconds per evaluation on one CPU
+# thread: Table 1 (Intel i7-10700, log t = 5..11) and, for log t = 12, Table 2
+# (Xeon Gold 6258R, n = 2^10).  Context for the paper-margin sweep, not a target.
+PAPER_IDENTITY_SECONDS = {5: (0.7375, "Table 1"), 6: (1.3625, "Table 1"), 7: (2.6376, "Table 1"),
+                          8: (5.2578, "Table 1"), 9: (10.203, "Table 1"), 10: (20.261, "Table 1"),
+                          11: (41.795, "Table 1"), 12: (202.56, "Table 2, n = 2^10")}
+
+
 def ops_per_bootstrap_wide(n, N, l, r, keys=1):
     """The same op model at a ring modulus of two primes: every NTT, product and
     accumulation runs once per prime; with a ternary secret (keys = 2) each
@@ -453,6 +462,9 @@ def margin_leg(args, binding, torch):
             mctx.bootstrap([ident], cti[k:k + 1], plain=True)
             lat.append(time.perf_counter() - t0)
         row["identity_plain_ms"] = round(float(np.median(lat)) * 1e3, 3)
+        if logt in PAPER_IDENTITY_SECONDS:
+            sec, where = PAPER_IDENTITY_SECONDS[logt]
+            row["paper_identity_s"] = {"value": sec, "source": where, "hardware": "one CPU thread (PALISADE)"}
         rows.append(row)
         print(json.dumps({"paper_margin_row": row}), file=sys.stderr, flush=True)
     mctx.close()
