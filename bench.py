@@ -251,15 +251,22 @@ def main():
         x_desc = ctx.schedule_describe(x_ids)
         ctx.bootstrap(x_ids, x_in, out=x_out)
         torch.cuda.synchronize()
-        reps = max(1, args.steps)
-        t3 = time.perf_counter()
-        for _ in range(reps):
+        reps = max(3, args.steps)
+        x_times, x_br, x_ks = [], [], []
+        for _ in range(reps):  # each call synchronised; the median resists a stray slow call
+            t3 = time.perf_counter()
             ctx.bootstrap(x_ids, x_in, out=x_out)
-        torch.cuda.synchronize()
-        x_s = (time.perf_counter() - t3) / reps
+            torch.cuda.synchronize()
+            x_times.append(time.perf_counter() - t3)
+            a_, b_ = ctx.last_timing()
+            x_br.append(a_)
+            x_ks.append(b_)
+        x_s = float(np.median(x_times))
         rs = np.array([tabs[i][2] for i in class_mix(M, 8)])
         mixed = {"batch": M, "classes": [list(c) for c in CLASS_MIX], "bootstraps_per_s": round(M / x_s, 1),
-                 "ms_per_batch": round(x_s * 1e3, 3), "components": int(rs.sum()),
+                 "ms_per_batch": round(x_s * 1e3, 3), "ms_per_batch_all": [round(v * 1e3, 3) for v in x_times],
+                 "blind_rotation_ms": round(float(np.median(x_br)), 3), "keyswitch_ms": round(float(np.median(x_ks)), 3),
+                 "components": int(rs.sum()),
                  "schedule": {"index": x_sched, "group_waves": x_desc[0], "ks_cts_per_wave": x_desc[1],
                               "ks_splits": x_desc[2], "waves_per_component": x_desc[3]}}
 
