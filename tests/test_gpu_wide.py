@@ -217,3 +217,61 @@ def test_paper_margin_noisy_batch_decrypts_at_t_4096(margin):
     err = (ph - f[m].astype(np.int64) * (q // t)) % q
     err = np.where(err > q // 2, err - q, err)
     assert np.max(np.abs(err)) < 32
+
+
+def test_wide_maximum_r_1024():
+    """r = 1024 (the largest table) at N = 256: two CMux steps against the oracle."""
+    c = case(256, 8)
+    r = 1024
+    t = 2 * 256 * r // 128
+    tid, f, V = c.table(t, r, 120)
+    ct = c.encrypt(2 * 256 * r, t, messages(t, 1, 121), 122)
+    say("wide r = 1024, 2 steps")
+    got = c.ctx.blind_rotate([tid], ct, 2).reshape(r, 2, 256)
+    np.testing.assert_array_equal(got, oracle.w_blind_rotate(c.p, r, c.keys.bsk, V, ct[0], 2))
+
+
+def test_wide_ragged_batches_and_device_pointers():
+    """Batch sizes 1, 3, 17, 64 give the bits of one batch of 65; device tensors in and out
+    give the bits of host buffers (bootstrap and blind rotation)."""
+    import torch
+    c = case(256, 16)
+    r = 2
+    t = 2 * 256 * r // 128
+    q = 2 * 256 * r
+    tid, f, V = c.table(t, r, 123)
+    ct = c.encrypt(q, t, messages(t, 65, 124), 125)
+    full = c.ctx.bootstrap([tid] * 65, ct)
+    for cnt in (1, 3, 17, 64):
+        np.testing.assert_array_equal(c.ctx.bootstrap([tid] * cnt, ct[:cnt]), full[:cnt], err_msg=f"count {cnt}")
+    np.testing.assert_array_equal(full[64], oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct[64:]).reshape(-1))
+    din = torch.from_numpy(ct.view(np.int32)).cuda()
+    dout = c.ctx.bootstrap([tid] * 65, din)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dout.cpu().numpy().view(np.uint32), full)
+    host_acc = c.ctx.blind_rotate([tid] * 3, ct[:3], 4)
+    dev_acc = c.ctx.blind_rotate([tid] * 3, din[:3].contiguous(), 4)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(dev_acc.cpu().numpy().view(np.uint64).reshape(-1), host_acc.reshape(-1))
+
+
+def test_wide_general_function_plain_at_r_256():
+    """A general f with r = 256 (t = 512 at N = 256) by the plain path, against the batched
+    path and the oracle for one ciphertext."""
+    c = case(256, 16)
+    r = 256
+    t = 2 * 256 * r // 128 // 2
+    q = 2 * 256 * r
+    rng = np.random.default_rng(126)
+    f = rng.integers(0, t, t).astype(np.uint32)
+    tid = c.ctx.table_create_general(t, t, r, f)
+    m = messages(t, 2, 127)
+    ct = c.encrypt(q, 2 * t, m, 128)
+    batched = c.ctx.bootstrap([tid] * 2, ct)
+    np.testing.assert_array_equal(c.ctx.bootstrap([tid] * 2, ct, plain=True), batched)
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, t, c.keys.s, batched), f[m])
+    g, F = oracle.general_tables(t, t, f)
+    Vg = oracle.w_test_vector(256, r, c.p.Q_ring, 2 * t, 2 * t, g)
+    VF = oracle.w_test_vector(256, r, c.p.Q_ring, 2 * t, t, F)
+    np.testing.assert_array_equal(batched[:1], oracle.w_bootstrap_general(c.p, r, c.keys.bsk, c.keys.ksk, Vg, VF, q,
+                                                                           t, q, ct[:1]))
