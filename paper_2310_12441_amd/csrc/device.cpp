@@ -255,7 +255,7 @@ std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uin
     cap = std::max<uint32_t>(1, std::min(cap ? cap : slots, slots));
     for (auto &t : cts)
         MM_REQUIRE(t.r >= 1 && t.r <= slots,
-                   "a ciphertext's r components times N/1024 waves each must fit one workgroup of 8 waves");
+                   "a ciphertext's r components times their waves per component must fit one workgroup");
     std::vector<size_t> order(cts.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cts[a].r > cts[b].r; });

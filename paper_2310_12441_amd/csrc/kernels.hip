@@ -3,8 +3,9 @@
 // k_blind_rotate: the fused, persistent blind rotation (Alg. 1, first modulus
 //   switch, accumulator initialisation and the n CMux steps, then the sample
 //   extraction of entry 0).  One workgroup of GW waves owns a "group" of
-//   component slots: a slot is one wave up to N = 1024 and N / 1024 waves
-//   above, and holds one component j of one ciphertext, whose RLWE pair (a, b)
+//   component slots: a slot is W waves (by default one up to N = 1024 and
+//   N / 1024 above; two at N = 512 and 1024 for batches that do not fill the
+//   device) and holds one component j of one ciphertext, whose RLWE pair (a, b)
 //   stays in LDS for all n steps.  Each step the slots read the pair that
 //   Phi(-a'_i) brings to them (an index-and-sign remap, eq. ex1:BPc), form
 //   D = Phi(-a'_i) ACC - ACC, and add D x BSK_i (the binary CMux of

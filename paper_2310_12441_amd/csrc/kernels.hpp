@@ -15,9 +15,10 @@ enum : uint32_t {
 };
 
 // What one wave of a blind-rotation workgroup does.  A group is GW (8 or 4)
-// consecutive WaveTasks.  A component slot is WPP consecutive waves (1 up to
-// N = 1024, N / 1024 above) holding the same task; the components 0..r-1 of a
-// ciphertext sit on consecutive slots of one group.
+// consecutive WaveTasks.  A component slot is WPP consecutive waves (by default
+// 1 up to N = 1024, N / 1024 above; 2 in the small-batch schedule) holding the
+// same task; the components 0..r-1 of a ciphertext sit on consecutive slots of
+// one group.
 struct WaveTask {
     int32_t ct;        // ciphertext index, -1 for an idle wave
     uint32_t comp;     // component j
