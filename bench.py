@@ -27,6 +27,9 @@ BATCH = 4096
 # 128 FMA lanes/clock x 2 flops x 2.4 GHz, i.e. 78.6 T lane-instructions/s; a
 # 32-bit integer VALU instruction takes the same issue slot.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# One wave64 VALU instruction per 4 clocks per SIMD, without dual issue: the
+# rate a stream of 64-bit multiply-adds can reach.
+SINGLE_ISSUE_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
 KERNEL_SOURCES = ("paper_2310_12441_amd/csrc/kernels.hip", "paper_2310_12441_amd/csrc/device_common.hpp")
 COUNTERS = os.path.join(ROOT, "profiles", "k_blind_rotate_paper_shaped_4096_counters.txt")
@@ -215,6 +218,8 @@ def main():
         "peak": round(PEAK_LANE_OPS / 1e12, 3),
         "unit": "TOP/s",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
+        "peak_single_issue": round(SINGLE_ISSUE_LANE_OPS / 1e12, 3),
+        "frac_single_issue": round(achieved / SINGLE_ISSUE_LANE_OPS, 4),
         "traffic": measured_traffic(),
         "kernel": f"k_blind_rotate<1024,{sched[0]},1{',2' if sched[3] == 2 else ''}>",
         "kernel_ms": round(br_avg * 1e3, 3),
