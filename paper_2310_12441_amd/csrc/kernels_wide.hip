@@ -81,10 +81,11 @@ __global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
 }
 
 // W waves per polynomial: N / 512 (8 coefficients per lane) and at least three
-// waves per SIMD (a few spilled loop-invariant LDS addresses) hide the
-// accumulator loads and the workgroup barriers of the relayouts: measured at
-// N = 2048, 16384 components, 982 ms per 512 steps with 16 coefficients per lane
-// and 2 waves, 904 ms with 8 and 2 waves, 794 ms with 8 and 3, 810 ms with 8 and 4.
+// waves per SIMD hide the accumulator loads and the workgroup barriers of the
+// relayouts.  Measured at N = 2048, binary secret, 16384 components, per 512
+// steps: 982 ms with 16 coefficients per lane and 2 waves per SIMD, 904 ms with
+// 8 and 2, 794 ms with 8 and 3 (735 ms once relayouts addressed LDS from one base
+// per side), 810 ms with 8 and 4 (spills).
 constexpr int wide_wpp(int N) { return N > 512 ? N / 512 : 1; }
 
 template <int N, int KEYS, int W = wide_wpp(N)>
