@@ -488,3 +488,30 @@ def test_two_wave_slots_small_batches(N, ternary):
     np.testing.assert_array_equal(c.ctx.bootstrap([tid8] * 2, ct8),
                                   oracle.bootstrap_many(p, 8, c.keys.bsk, c.keys.ksk, V8, q8, q8, ct8))
     c.ctx.close()
+
+
+@pytest.mark.parametrize("q_in", [2 ** 31, 12289, 196611])
+@pytest.mark.parametrize("plain", [False, True])
+def test_bootstrap_first_switch_not_identity(tiny, q_in, plain):
+    """Ciphertexts at a modulus q_in other than 2Nr: the first modulus switch of
+    Alg. 1 (round(a 2Nr / q_in), ties upward) runs inside the blind rotation."""
+    say("q_in", q_in, "plain", plain)
+    t, r = 16, 2
+    tid, f, V = tiny.table(t, t, r, 140, q_in=q_in)
+    m = np.arange(t, dtype=np.uint32)
+    ct = tiny.encrypt(q_in, t, m, 141)
+    got = tiny.ctx.bootstrap([tid] * t, ct, plain=plain)
+    want = oracle.bootstrap_many(tiny.p, r, tiny.keys.bsk, tiny.keys.ksk, V, q_in, q_in, ct)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(oracle.decrypt(tiny.p.n, q_in, t, tiny.keys.s, got), f[m])
+
+
+def test_two_entry_table(tiny):
+    """t = 2, the smallest nega-cyclic table (f(1) = -f(0) mod t')."""
+    t, t_out, r = 2, 16, 2
+    tid, f, V = tiny.table(t, t_out, r, 142)
+    q = 2 * tiny.p.N * r
+    m = np.array([0, 1, 1, 0], dtype=np.uint32)
+    ct = tiny.encrypt(q, t, m, 143)
+    got = tiny.ctx.bootstrap([tid] * 4, ct)
+    np.testing.assert_array_equal(got, oracle.bootstrap_many(tiny.p, r, tiny.keys.bsk, tiny.keys.ksk, V, q, q, ct))

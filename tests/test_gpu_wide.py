@@ -275,3 +275,19 @@ def test_wide_general_function_plain_at_r_256():
     VF = oracle.w_test_vector(256, r, c.p.Q_ring, 2 * t, t, F)
     np.testing.assert_array_equal(batched[:1], oracle.w_bootstrap_general(c.p, r, c.keys.bsk, c.keys.ksk, Vg, VF, q,
                                                                            t, q, ct[:1]))
+
+
+@pytest.mark.parametrize("q_in", [2 ** 31, 12289])
+def test_wide_first_switch_not_identity(q_in):
+    """Ciphertexts at q_in other than 2Nr on the wide path (the switch runs in the
+    accumulator initialisation and in every step)."""
+    c = case(256, 16)
+    r, t = 4, 16
+    f = negacyclic_table(t, t, 130)
+    tid = c.ctx.table_create(t, t, r, f, q_in)
+    V = oracle.w_test_vector(256, r, c.p.Q_ring, t, t, f)
+    m = np.arange(t, dtype=np.uint32)
+    ct = c.encrypt(q_in, t, m, 131)
+    got = c.ctx.bootstrap([tid] * t, ct)
+    np.testing.assert_array_equal(got, oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q_in, q_in, ct))
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q_in, t, c.keys.s, got), f[m])
