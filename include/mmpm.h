@@ -272,11 +272,12 @@ int mm_submit(mm_server *s, int table_id, const uint32_t *ct, uint64_t *ticket);
 
 /* Copy the result of `ticket` into ct_out (n+1 words) once ready; MM_EAGAIN
  * before that, MM_ESTATE if the serving loop stopped before finishing it,
- * MM_EINVAL for a ticket never issued.  A ticket can be collected once. */
+ * MM_EINVAL for a ticket never issued or already collected (a ticket can be
+ * collected once). */
 int mm_poll(mm_server *s, uint64_t ticket, uint32_t *ct_out);
 
-/* Latency percentiles (submit to result ready, ms) and completed bootstraps per
- * second since start. */
+/* Latency percentiles (submit to result ready, ms) over the last 2^20 completed
+ * requests, and completed bootstraps per second since start. */
 int mm_server_stats(mm_server *s, double *p50_ms, double *p99_ms, double *boots_per_s,
                     uint64_t *completed);
 

@@ -18,6 +18,7 @@
 #include <set>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "device_internal.hpp"
 
@@ -141,7 +142,10 @@ struct Server {
     std::deque<Req> pending;
     size_t pending_cap = 1u << 20;
     std::unordered_map<uint64_t, Result> done;
-    std::vector<double> lat;
+    std::unordered_set<uint64_t> live;  // issued tickets whose result is not ready yet
+    std::vector<double> lat;            // latencies of the last LAT_CAP completed requests (a ring)
+    size_t lat_next = 0;
+    static constexpr size_t LAT_CAP = size_t(1) << 20;
     uint64_t next_ticket = 1, completed = 0;
     bool have_first = false;
     clk::time_point t_first, t_last;
@@ -251,6 +255,7 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
         return 0;
     }
     Req r{next_ticket++, table, std::vector<uint32_t>(ct, ct + W), t0};
+    live.insert(r.ticket);
     if (!have_first) {
         have_first = true;
         t_first = t0;
@@ -273,7 +278,10 @@ bool Server::harvest(Part &p)
         const Active &a = p.finishing[k];
         Result res{std::vector<uint32_t>(p.out.h + k * W, p.out.h + (k + 1) * W),
                    std::chrono::duration<double, std::milli>(now - a.t0).count()};
-        lat.push_back(res.ms);
+        if (lat.size() < LAT_CAP) lat.push_back(res.ms);
+        else lat[lat_next] = res.ms;
+        lat_next = (lat_next + 1) % LAT_CAP;
+        live.erase(a.ticket);
         done.emplace(a.ticket, std::move(res));
         free_slots.push_back(a.slot);
         buddy.release(a.unit, a.order);
@@ -490,8 +498,8 @@ int mm_poll(mm_server *h, uint64_t ticket, uint32_t *ct_out)
     std::lock_guard<std::mutex> g(s.mu);
     auto it = s.done.find(ticket);
     if (it == s.done.end()) {
-        if (ticket == 0 || ticket >= s.next_ticket) return MM_EINVAL;
-        return s.stop ? MM_ESTATE : MM_EAGAIN;  // a stopped loop will not finish it
+        if (!s.live.count(ticket)) return MM_EINVAL;  // never issued, or already collected
+        return s.stop ? MM_ESTATE : MM_EAGAIN;        // a stopped loop will not finish it
     }
     std::memcpy(ct_out, it->second.ct.data(), it->second.ct.size() * 4);
     s.done.erase(it);

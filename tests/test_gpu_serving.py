@@ -60,6 +60,9 @@ def test_submit_poll_matches_alone(setup):
             if got[k] is None:
                 got[k] = srv.poll(tk)
         time.sleep(0.002)
+    if got[0] is not None:
+        with pytest.raises(b.MMError):
+            srv.poll(tickets[0])  # collected already: an error, not "not ready" forever
     st = srv.stats()
     srv.stop()
     assert all(g is not None for g in got)
