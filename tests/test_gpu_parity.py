@@ -443,6 +443,23 @@ def test_full_batch_bench_configuration_sampled():
     ctx.close()
 
 
+def test_batch_three_times_the_bench_sampled(paper):
+    """12,288 paper-shaped ciphertexts in one launch (49,152 components: 24 groups per
+    persistent workgroup, workspaces three times the timed batch's); the first 4096
+    equal the same ciphertexts bootstrapped as a batch of their own, and sampled
+    outputs across the whole batch equal the oracle's."""
+    B = 3 * 4096
+    tid, f, V = paper.table(4096, 4096, 4, 41)
+    ct = paper.encrypt(8192, 4096, messages(4096, B, 42), 43)
+    say("batch of", B)
+    out = paper.ctx.bootstrap([tid] * B, ct)
+    np.testing.assert_array_equal(paper.ctx.bootstrap([tid] * 4096, ct[:4096]), out[:4096])
+    pick = np.array([0, 4095, 4096, 8191, 8192, B - 1])
+    say("oracle on", pick.size, "samples")
+    want = oracle.bootstrap_many(paper.p, 4, paper.keys.bsk, paper.keys.ksk, V, 8192, 8192, ct[pick])
+    np.testing.assert_array_equal(out[pick], want)
+
+
 def test_empty_and_ragged_batches(paper):
     """count = 0 is a no-op; ragged batch sizes give the same bits as one larger batch."""
     tid, f, V = paper.table(4096, 4096, 4, 15)
