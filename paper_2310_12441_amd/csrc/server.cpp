@@ -139,7 +139,7 @@ struct Server {
     Part part[2];
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Req> pending;
+    std::deque<Req> pending[2];  // by class: at most 4 components, and wider
     size_t pending_cap = 1u << 20;
     std::unordered_map<uint64_t, Result> done;
     std::unordered_set<uint64_t> live;  // issued tickets whose result is not ready yet
@@ -236,10 +236,12 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
 {
     const size_t W = c->p.n + 1;
     bool ok;
+    int cls = 0;
     {
         std::lock_guard<std::mutex> gc(c->lock);  // the table list may grow under this lock
         ok = table >= 0 && (size_t)table < c->tables.size() && c->tables[table].g_id < 0 &&
              c->tables[table].r * (uint32_t)dev::waves_per_poly(c->p.N) <= 8;
+        if (ok) cls = c->tables[table].r > 4 ? 1 : 0;
     }
     std::lock_guard<std::mutex> g(mu);
     if (!ok) {
@@ -250,7 +252,7 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
         *rc = MM_ESTATE;  // the serving loop has stopped (a device error ends it; see mm_last_error)
         return 0;
     }
-    if (pending.size() >= pending_cap) {
+    if (pending[0].size() + pending[1].size() >= pending_cap) {
         *rc = MM_EBUSY;
         return 0;
     }
@@ -260,10 +262,11 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
         have_first = true;
         t_first = t0;
     }
-    pending.push_back(std::move(r));
+    const uint64_t ticket = r.ticket;
+    pending[cls].push_back(std::move(r));
     cv.notify_all();
     *rc = MM_OK;
-    return pending.back().ticket;
+    return ticket;
 }
 
 // Collect the results of a finished tick.  Returns true if it harvested.
@@ -302,16 +305,24 @@ void Server::launch(Part &p)
     std::lock_guard<std::mutex> dev_lock(c->lock);  // tables and device state; taken before mu
     {
         std::lock_guard<std::mutex> g(mu);
-        while (!pending.empty() && !free_slots.empty()) {
-            const Req &q = pending.front();
-            const uint32_t order = order_of(c->tables[q.table].r);
-            const int64_t unit = buddy.alloc(order);
-            if (unit < 0) break;  // no accumulator memory: wait for completions
-            Active a{q.ticket, q.table, free_slots.back(), (uint32_t)unit, order, 0, q.t0};
-            free_slots.pop_back();
-            fresh.push_back(a);
-            fresh_req.push_back(std::move(pending.front()));
-            pending.pop_front();
+        // each partition admits one class (at most 4 components, or wider), so that
+        // the groups of a tick are alike and every ciphertext advances the full chunk;
+        // a partition with nothing in flight and an empty queue of its own takes the other class
+        const int own = (int)(&p - part);
+        for (int k : {own, own ^ 1}) {
+            if (k != own && !(p.active.empty() && fresh.empty())) break;
+            std::deque<Req> &queue = pending[k];
+            while (!queue.empty() && !free_slots.empty()) {
+                const Req &q = queue.front();
+                const uint32_t order = order_of(c->tables[q.table].r);
+                const int64_t unit = buddy.alloc(order);
+                if (unit < 0) break;  // no accumulator memory: wait for completions
+                Active a{q.ticket, q.table, free_slots.back(), (uint32_t)unit, order, 0, q.t0};
+                free_slots.pop_back();
+                fresh.push_back(a);
+                fresh_req.push_back(std::move(queue.front()));
+                queue.pop_front();
+            }
         }
     }
     if (fresh.empty() && p.active.empty()) return;
@@ -331,13 +342,15 @@ void Server::launch(Part &p)
     // one task per resident ciphertext, packed into 8-wave groups; under light
     // load the groups hold at most 4 components (one wave per SIMD), and a
     // ciphertext that still needs all 8 slots (two waves per SIMD, about 1.5x
-    // slower per step) advances 2/3 of the steps, so its group does not set the
-    // length of the tick for the others
+    // slower per step) advances 2/3 of the steps when the tick also holds narrower
+    // ones, so its group does not set the length of the tick for the others
     const uint32_t wpp = (uint32_t)dev::waves_per_poly(c->p.N);
     uint64_t comps = 0;
     for (auto &a : p.active) comps += c->tables[a.table].r;
     const uint32_t cap = spread_cap(d, comps, 8, wpp);
-    const uint32_t wide_chunk = std::max<uint32_t>(1, chunk * 2 / 3);
+    bool narrow = false, wide = false;
+    for (auto &a : p.active) (c->tables[a.table].r > cap ? wide : narrow) = true;
+    const uint32_t wide_chunk = narrow && wide ? std::max<uint32_t>(1, chunk * 2 / 3) : chunk;
     auto steps_of = [&](const Active &a) { return c->tables[a.table].r > cap ? wide_chunk : chunk; };
     std::vector<dev::WaveTask> cts(p.active.size());
     for (size_t k = 0; k < p.active.size(); k++) {
@@ -424,7 +437,7 @@ void Server::loop()
             next_admit ^= 1;
             const bool idle = !part[0].busy && !part[1].busy;
             std::unique_lock<std::mutex> g(mu);
-            if (idle && pending.empty()) {
+            if (idle && pending[0].empty() && pending[1].empty()) {
                 if (stop) break;
                 cv.wait_for(g, std::chrono::milliseconds(5));
             } else if (!progress) {
