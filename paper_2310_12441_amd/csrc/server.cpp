@@ -366,7 +366,11 @@ void Server::launch(Part &p)
         w.flags = (a.step == 0 ? dev::TASK_INIT : 0u) | dev::TASK_STORE | dev::TASK_EXTRACT;
         w.acc_off = (uint64_t)a.unit * 2 * N;
     }
-    auto tasks = pack_tasks(cts, 8, wpp, cap);
+    // a light tick of ciphertexts of at most 4 components (the partition of that
+    // class) runs two waves per component, 4 components per group, where the ring
+    // has that kernel: each step about 13 % shorter than with one wave per component
+    const bool slots2 = wpp == 1 && cap < 8 && !wide && dev::br_supports_wpp(N, 2);
+    auto tasks = slots2 ? pack_tasks(cts, 8, 2, 0) : pack_tasks(cts, 8, wpp, cap);
     p.tasks.reserve(tasks.size());
     std::memcpy(p.tasks.h, tasks.data(), tasks.size() * sizeof(dev::WaveTask));
     SRV_HIP(hipMemcpyAsync(p.tasks.d, p.tasks.h, tasks.size() * sizeof(dev::WaveTask), hipMemcpyHostToDevice, p.st));
@@ -377,7 +381,7 @@ void Server::launch(Part &p)
     A.ct_in = d_ct;
     A.acc_state = d_acc;
     A.ext_out = d_ext;
-    dev::launch_blind_rotate(N, A, 8, std::min(A.num_groups, d.num_cu), p.st);
+    dev::launch_blind_rotate(N, A, 8, std::min(A.num_groups, d.num_cu), p.st, slots2 ? 2 : 0);
 
     // ciphertexts that reach step n in this tick: key switch and copy back
     std::vector<Active> keep;
