@@ -256,9 +256,12 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
 /* Start a server on ctx (one per context; MM_ESTATE if one runs).  It keeps as
  * many in-flight ciphertexts as their device state (accumulators, inputs,
  * outputs) fits in hbm_budget_bytes (MM_EINVAL below one 8-component group);
- * chunk_steps in [1, n].  Each launch advances every resident ciphertext by
- * chunk_steps CMux steps, so a request admitted while others run joins them at
- * the next launch.  Tables of general f, or with r N/1024 > 8, are not served.
+ * chunk_steps in [1, n].  Two partitions, one for requests of at most 4
+ * components and one for wider ones, alternate launches; each launch advances
+ * every resident ciphertext of its partition by chunk_steps CMux steps (2/3 of
+ * that for the wider ones when a partition holds both kinds), so a request
+ * admitted while others run joins them at the next launch.  Tables of general
+ * f, or with r N/1024 > 8, are not served.
  * The handle stays valid until mm_server_stop; mm_free of the context stops a
  * running server too, after which the handle must not be used. */
 int mm_server_start(mm_ctx *ctx, size_t hbm_budget_bytes, uint32_t chunk_steps, mm_server **out);
