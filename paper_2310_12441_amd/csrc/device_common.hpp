@@ -143,7 +143,13 @@ __device__ __forceinline__ void poly_sync()
 // 4096-ciphertext batch at N = 1024); where relayouts end at workgroup
 // barriers it loses (4-5 % at N = 4096), since the barrier then waits for the
 // waves held back, hence the default.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1)>
+//
+// SYNC_BEFORE = false drops the barrier that keeps the writes from overtaking the
+// previous relayout's reads; valid only when consecutive relayouts alternate
+// between two slots (then the previous user of this slot is two relayouts back,
+// and every wave finished reading it before it wrote for the relayout in between,
+// whose barrier this wave has passed).
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool SYNC_BEFORE = true>
 __device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, int L, int from,
                                          int to)
 {
@@ -151,7 +157,7 @@ __device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint
     static_assert(swz_split_holds<N, W>(), "LDS address split");
     uint32_t *sf = slot + swz_base<N, W>(from, L), *st = slot + swz_base<N, W>(to, L);
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
-    poly_sync<N, W>();
+    if constexpr (SYNC_BEFORE) poly_sync<N, W>();
 #pragma unroll
     for (int q = 0; q < NP; q++)
 #pragma unroll
@@ -164,20 +170,36 @@ __device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
 }
 
+// One relayout through `slot`, or, with DS, through slot and slot2 in turn (par
+// counts the relayouts since the last workgroup barrier), dropping the barrier
+// before the writes.
+template <int N, int NP, int W, bool PRIO, bool DS>
+__device__ __forceinline__ void relayout_ds(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, uint32_t *slot2,
+                                            int *par, int L, int from, int to)
+{
+    if constexpr (DS) {
+        uint32_t *s = (*par & 1) ? slot2 : slot;
+        *par ^= 1;
+        relayout<N, NP, W, PRIO, false>(x, s, L, from, to);
+    } else {
+        relayout<N, NP, W, PRIO>(x, slot, L, from, to);
+    }
+}
+
 // Forward negacyclic NTT (Cooley-Tukey, merged psi powers, natural order in,
 // bit-reversed order out) of NP polys held in phase-0 layout; returns them in
 // the last phase's layout, reduced to [0, Q) (inputs in [0, Q)).
 // twf[k] = psi^bitrev(k) 2^32 mod Q.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1)>
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false>
 __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twf,
-                                        int L, const ModQ &m)
+                                        int L, const ModQ &m, uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
 #pragma unroll
     for (int p = 0; p < G::NPH; p++) {
         const int R = G::R(p);
         if (p > 0) {
-            relayout<N, NP, W, PRIO>(x, slot, L, p - 1, p);
+            relayout_ds<N, NP, W, PRIO, DS>(x, slot, slot2, par, L, p - 1, p);
             // the previous phase left its last stage unreduced; reduce the values
             // that are not multiplicands of this phase's first stage
             const int kt = G::HI(p) - R;
@@ -223,9 +245,9 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
 // Inverse negacyclic NTT (Gentleman-Sande, bit-reversed in, natural out),
 // without the 1/N factor: polys arrive in the last phase's layout and leave in
 // phase-0 layout.  twi[k] = psi^-bitrev(k) 2^32 mod Q.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1)>
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false>
 __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twi,
-                                        int L, const ModQ &m)
+                                        int L, const ModQ &m, uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
 #pragma unroll
@@ -248,7 +270,7 @@ __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
                 }
             }
         }
-        if (p > 0) relayout<N, NP, W, PRIO>(x, slot, L, p, p - 1);
+        if (p > 0) relayout_ds<N, NP, W, PRIO, DS>(x, slot, slot2, par, L, p, p - 1);
     }
 }
 
@@ -294,10 +316,11 @@ __device__ __forceinline__ uint32_t gadget_field_start(uint32_t x, uint32_t off_
 // (eq. def:gsw).  out stays in the last phase's layout.  With OFF the digits
 // enter shifted by +B/2 (g.off then holds (B/2)(1 + ... + B^(l-1))) and the
 // caller starts out from minus (B/2) sum_rows K.
-template <int N, bool OFF = false, int W = default_wpp(N), bool PRIO = (W == 1)>
+template <int N, bool OFF = false, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false>
 __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], const uint32_t (&Db)[(Geo<N, W>::E)],
                                         const uint32_t *__restrict__ K, uint32_t *slot, const uint32_t *twf, int L,
-                                        const ModQ &m, const GadgetC &g, uint32_t (&out)[2][(Geo<N, W>::E)])
+                                        const ModQ &m, const GadgetC &g, uint32_t (&out)[2][(Geo<N, W>::E)],
+                                        uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
     constexpr int E = G::E;
@@ -327,7 +350,7 @@ __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], co
                 pd[1][k] = gadget_digit((int32_t)ya[k], u, g, m.Q);
             }
         }
-        ntt_fwd<N, 2, W, PRIO>(pd, slot, twf, L, m);
+        ntt_fwd<N, 2, W, PRIO, DS>(pd, slot, twf, L, m, slot2, par);
         // virtual lane L now holds NTT positions E L .. E L + E - 1
         const uint32_t *kb_a = K + ((size_t)(u)*2 + 0) * N + L * E;
         const uint32_t *kb_b = K + ((size_t)(u)*2 + 1) * N + L * E;

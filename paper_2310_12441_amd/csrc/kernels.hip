@@ -92,6 +92,11 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
     const int cs = wave / WPP;                             // component slot
     const int L = (wave % WPP) * 64 + (threadIdx.x & 63);  // virtual lane of the slot
     uint32_t *const base = lds + cs * LD::COMP_WORDS;
+    // two waves per polynomial at N <= 1024: a second exchange slot per component
+    // after the accumulator buffers, so that consecutive relayouts alternate between
+    // the two and each needs one workgroup barrier instead of two
+    constexpr bool DS = WPP == 2 && N <= 1024;
+    uint32_t *const slot2 = lds + (GW / WPP) * LD::COMP_WORDS + cs * G::SLOTW;
     const ModQ m{A.Q, A.qn};
     const GadgetC g{A.log2B, A.l, A.sg, A.goff};
 
@@ -174,6 +179,7 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             uint32_t o[2][E];
             const uint32_t ik = active ? i : 0u;
             const uint32_t *K = A.bsk + (size_t)ik * KEYS * (4u * A.l * N);
+            int par = 0;  // relayouts since the step's barrier (which slot the next one uses)
             if (run) {
                 // start from the digit-offset correction of coordinate i
                 const uint32_t *C0 = A.bsk_corr + (size_t)ik * 2 * N + L * E;
@@ -182,15 +188,15 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
                     o[0][k] = C0[k];
                     o[1][k] = C0[N + k];
                 }
-                ext_mac<N, true, W>(D[0], D[1], K, nxt, A.twf, L, m, g, o);
+                ext_mac<N, true, W, (W == 1), DS>(D[0], D[1], K, nxt, A.twf, L, m, g, o, slot2, &par);
             }
             if (KEYS == 2) {
                 if (active) rotated_diff(ai, accl, D);  // +a'_i from the same accumulator
-                if (run) ext_mac<N, true, W>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o);
+                if (run) ext_mac<N, true, W, (W == 1), DS>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o, slot2, &par);
             }
             if (run) {
                 __asm__ volatile("" ::: "memory");
-                ntt_inv<N, 2, W>(o, nxt, A.twi, L, m);
+                ntt_inv<N, 2, W, (W == 1), DS>(o, nxt, A.twi, L, m, slot2, &par);
             }
             if (WPP > 1) __syncthreads();  // every lane of the slot has left the exchange slot
             if (active) {
@@ -640,7 +646,9 @@ bool br_supports_wpp(uint32_t N, int wpp) { return wpp == waves_per_poly(N) || (
 template <int N>
 static size_t br_lds_n(int gw, int wpp)
 {
-    return (size_t)(gw / (wpp ? wpp : Geo<N>::WPP)) * BrLds<N>::COMP_WORDS * sizeof(uint32_t);
+    const int w = wpp ? wpp : Geo<N>::WPP;
+    const size_t extra = (w == 2 && N <= 1024) ? (size_t)Geo<N>::SLOTW : 0;  // the second exchange slot
+    return (size_t)(gw / w) * (BrLds<N>::COMP_WORDS + extra) * sizeof(uint32_t);
 }
 
 size_t br_lds_bytes(uint32_t N, int gw, int wpp)
