@@ -101,9 +101,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     // issue priority around the relayouts (see relayout): on where they are wave-private,
     // and with a ternary secret, which measured 5 % faster at N = 2048 (binary: 1 % slower)
     constexpr bool PRIO = W == 1 || KEYS == 2;
-    __shared__ uint64_t lds64[G::SLOTW / 2 + (Y_LDS ? 2 * N : 0)];
+    // a binary secret leaves LDS to spare: a second exchange slot, so that
+    // consecutive relayouts alternate and each needs one workgroup barrier, not two
+    // (a third of the LDS a ternary workgroup needs, so occupancy is unchanged)
+    constexpr bool DS = KEYS == 1 && W > 1;
+    __shared__ uint64_t lds64[G::SLOTW / 2 + (Y_LDS ? 2 * N : 0) + (DS ? G::SLOTW / 2 : 0)];
     uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64);
     uint64_t *const ylds = lds64 + G::SLOTW / 2;
+    uint32_t *const slot2 = slot + G::SLOTW;  // DS only (ylds is ternary only)
+    int par = 0;                              // relayouts so far: which slot the next one uses
     const WideTask T = A.tasks[blockIdx.x];
     const int L = threadIdx.x;
     const uint32_t M = 2u * N * T.r;
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
                 pd[0][k] = (uint32_t)((yb >> sh) & mask);  // digit of b meets rows u
                 pd[1][k] = (uint32_t)((ya >> sh) & mask);  // digit of a meets rows l + u
             }
-            ntt_fwd<N, 2, W, PRIO>(pd, slot, pr ? A.twf1 : A.twf0, L, mod(pr));
+            ntt_fwd<N, 2, W, PRIO, DS>(pd, slot, pr ? A.twf1 : A.twf0, L, mod(pr), slot2, &par);
             const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N + L * E;
             const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N + L * E;
             const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N + L * E;
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     // inverse NTT, ACC_j + product, store to the other buffer
     auto finish = [&](int pr, uint32_t (&out)[2][E]) {
         __asm__ volatile("" ::: "memory");
-        ntt_inv<N, 2, W, PRIO>(out, slot, pr ? A.twi1 : A.twi0, L, mod(pr));
+        ntt_inv<N, 2, W, PRIO, DS>(out, slot, pr ? A.twi1 : A.twi0, L, mod(pr), slot2, &par);
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
