@@ -558,6 +558,11 @@ void orc_bootstrap_many(uint32_t n, uint32_t N, uint32_t Q, uint32_t log2B, uint
  * m in [0, t), b an unknown top bit.  The two nega-cyclic tables on Z_2t:
  *   g(x) = t/2 for x in [0, t), -t/2 for x in [t, 2t)   (the sign of x, times t/2)
  *   F(y) = f(y) for y in [0, t), -f(y - t) for y in [t, 2t)   (mod t').
+ * g is not the sign table of eq. (rel:mp) as printed: that table is -t/2 on
+ * [-t/2, t/2) and t/2 on the rest of [-t, t), so it plus t/2 (eq. rel:sign) is
+ * 0 or t according to |x| < t/2, not to the top bit.  g is that table moved by
+ * t/2, g(x) = -mp(x - t/2), which is t/2 exactly when b = 0; then
+ * x + g(x) - t/2 = m + b t + (t/2 - b t) - t/2 = m for both values of b.
  * Outputs g[2t] in Z_2t and F[2t] in Z_t'. */
 void orc_general_tables(uint32_t t, uint32_t t_out, const uint32_t *f, uint32_t *g, uint32_t *F)
 {
