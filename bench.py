@@ -30,6 +30,10 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # One wave64 VALU instruction per 4 clocks per SIMD, without dual issue: the
 # rate a stream of 64-bit multiply-adds can reach.
 SINGLE_ISSUE_LANE_OPS = 256 * 64 * 2.4e9
+# Issue rate of a register-only loop with the butterfly's instruction mix (64-bit
+# multiply-adds, low-word multiplies, adds, subtracts, mins) at 2 waves per SIMD,
+# measured on the MI355X: the ceiling this kernel's instruction mix can reach.
+MIX_CEILING_LANE_OPS = 35.0e12
 PEAK_HBM = 8.0e12
 KERNEL_SOURCES = ("paper_2310_12441_amd/csrc/kernels.hip", "paper_2310_12441_amd/csrc/device_common.hpp")
 COUNTERS = os.path.join(ROOT, "profiles", "k_blind_rotate_paper_shaped_4096_counters.txt")
@@ -61,7 +65,9 @@ def ops_per_bootstrap(n, N, l, r):
 # (Xeon Gold 6258R, n = 2^10).  Context for the paper-margin sweep, not a target.
 PAPER_IDENTITY_SECONDS = {5: (0.7375, "Table 1"), 6: (1.3625, "Table 1"), 7: (2.6376, "Table 1"),
                           8: (5.2578, "Table 1"), 9: (10.203, "Table 1"), 10: (20.261, "Table 1"),
-                          11: (41.795, "Table 1"), 12: (202.56, "Table 2, n = 2^10")}
+                          11: (41.795, "Table 1"), 12: (202.56, "Table 2, n = 2^10"),
+                          13: (413.22, "Table 2, n = 2^10"), 14: (834.60, "Table 2, n = 2^10"),
+                          15: (1676.3, "Table 2, n = 2^10")}
 
 
 def ops_per_bootstrap_wide(n, N, l, r, keys=1):
@@ -129,7 +135,7 @@ def main():
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
     ap.add_argument("--margin", type=int, default=16384,
                     help="ring components per batch of the paper-margin sweep (0: no such leg)")
-    ap.add_argument("--margin-logt", default="5,6,7,8,9,10,11,12", help="log2 t of the paper-margin sweep")
+    ap.add_argument("--margin-logt", default="5,6,7,8,9,10,11,12,13,14,15", help="log2 t of the paper-margin sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -164,24 +170,36 @@ def main():
     schedule = ctx.autotune(ids, ct)
     sched = ctx.schedule_describe(ids)
 
-    # ---- batched path (timed)
-    ctx.set_timing(True)
+    # ---- batched path (timed): the product's path, one captured graph per batch,
+    # no events inside; wall clock over the steps
+    ctx.set_timing(False)
     for _ in range(args.warmup):
         ctx.bootstrap(ids, dev_in, out=dev_out)
-        ctx.last_timing()
     torch.cuda.synchronize()
-    br_ms, ks_ms = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.bootstrap(ids, dev_in, out=dev_out)
-        a, b = ctx.last_timing()
-        br_ms.append(a)
-        ks_ms.append(b)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     value = B * args.steps / wall
     batched_out = dev_out.cpu().numpy().view(np.uint32).copy()
+    # kernel split, separately: the blind-rotation and key-switch halves as two
+    # graphs with HIP events between them on the stream they run on
+    ctx.set_timing(True)
+    ctx.bootstrap(ids, dev_in, out=dev_out)
+    ctx.last_timing()
+    br_ms, ks_ms = [], []
+    t_ev = time.perf_counter()
+    for _ in range(max(2, min(args.steps, 5))):
+        ctx.bootstrap(ids, dev_in, out=dev_out)
+        a, b = ctx.last_timing()
+        br_ms.append(a)
+        ks_ms.append(b)
+    torch.cuda.synchronize()
+    timed_wall_ms = (time.perf_counter() - t_ev) * 1e3 / len(br_ms)
+    ctx.set_timing(False)
+    split_same = bool(np.array_equal(dev_out.cpu().numpy().view(np.uint32), batched_out))
 
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(7)
@@ -220,8 +238,10 @@ def main():
         "frac": round(achieved / PEAK_LANE_OPS, 4),
         "peak_single_issue": round(SINGLE_ISSUE_LANE_OPS / 1e12, 3),
         "frac_single_issue": round(achieved / SINGLE_ISSUE_LANE_OPS, 4),
+        "mix_ceiling": round(MIX_CEILING_LANE_OPS / 1e12, 3),
+        "frac_mix_ceiling": round(achieved / MIX_CEILING_LANE_OPS, 4),
         "traffic": measured_traffic(),
-        "kernel": f"k_blind_rotate<1024,{sched[0]},1{',2' if sched[3] == 2 else ''}>",
+        "kernel": (f"k_blind_rotate<1024,{sched[0]},1,{sched[3]}" + (",true" if sched[5] == 1 else "") + ">"),
         "kernel_ms": round(br_avg * 1e3, 3),
         "ops_per_launch": ops,
         "hbm_algorithmic_bytes": hbm_alg,
@@ -267,11 +287,27 @@ def main():
             x_br.append(a_)
             x_ks.append(b_)
         x_s = float(np.median(x_times))
-        rs = np.array([tabs[i][2] for i in class_mix(M, 8)])
+        cls_x = class_mix(M, 8)
+        rs = np.array([tabs[i][2] for i in cls_x])
+        x_check = None
+        if not args.no_cpu:
+            # oracle on 4 ciphertexts of every class of this batch
+            import oracle
+            okeys = oracle.KeySet(p, draws)
+            x_got = x_out.cpu().numpy().view(np.uint32)
+            x_ok = True
+            for k, (tid_k, tt, rr) in enumerate(tabs):
+                sel = np.where(cls_x == k)[0]
+                pick = sel[np.linspace(0, sel.size - 1, 4).astype(int)]
+                Vk = oracle.test_vector(p.N, rr, p.Q, tt, tt, negacyclic_table(tt, tt, 100 + k))
+                qq = 2 * p.N * rr
+                want_k = oracle.bootstrap_many(p, rr, okeys.bsk, okeys.ksk, Vk, qq, qq, x_ct[pick])
+                x_ok = x_ok and bool(np.array_equal(x_got[pick], want_k))
+            x_check = {"oracle_samples": 4 * len(tabs), "equal": x_ok}
         mixed = {"batch": M, "classes": [list(c) for c in CLASS_MIX], "bootstraps_per_s": round(M / x_s, 1),
                  "ms_per_batch": round(x_s * 1e3, 3), "ms_per_batch_all": [round(v * 1e3, 3) for v in x_times],
                  "blind_rotation_ms": round(float(np.median(x_br)), 3), "keyswitch_ms": round(float(np.median(x_ks)), 3),
-                 "components": int(rs.sum()),
+                 "components": int(rs.sum()), "parity": x_check,
                  "schedule": {"index": x_sched, "group_waves": x_desc[0], "ks_cts_per_wave": x_desc[1],
                               "ks_splits": x_desc[2], "waves_per_component": x_desc[3]}}
 
@@ -357,7 +393,7 @@ def main():
     if not args.no_cpu:
         import oracle
         nthr = oracle.num_threads()
-        S = args.cpu_sample or max(8, 3 * nthr)
+        S = args.cpu_sample or max(64, 4 * nthr)
         keys = oracle.KeySet(p, draws)
         V = oracle.test_vector(p.N, r, p.Q, t, t, f)
         idx = np.linspace(0, B - 1, S).astype(int)
@@ -396,6 +432,12 @@ def main():
         "plain_runs": len(plain_lat),
         "batched_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
         "plain_equals_batched": plain_same,
+        "kernel_split": {"blind_rotation_ms": round(float(np.mean(br_ms)), 3),
+                         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
+                         "wall_ms_per_batch_with_events": round(timed_wall_ms, 3),
+                         "same_bits_as_timed_steps": split_same,
+                         "how": "two graphs (blind rotation; key switch + final switch) with HIP events "
+                                "between them on their stream, run after the timed steps"},
         "keyswitch_ms": round(float(np.mean(ks_ms)), 3),
         "schedule": {"index": schedule, "group_waves": sched[0], "ks_cts_per_wave": sched[1], "ks_splits": sched[2],
                      "waves_per_component": sched[3]},
@@ -473,6 +515,7 @@ def margin_leg(args, binding, torch):
         outi = iout.cpu().numpy().view(np.uint32)
         row["correct"] = bool(np.array_equal(mctx.decrypt(q, t, outi), mi) and
                               np.array_equal(mctx.decrypt(q, t, outn), negacyclic_table(t, t, 500 + logt)[mn]))
+        row["check"] = "every output decrypted (noisy keys and inputs); not compared with the oracle here"
         lat = []
         for k in range(3):
             t0 = time.perf_counter()
@@ -489,6 +532,9 @@ def margin_leg(args, binding, torch):
                        "log2_B": pw.log2_B, "l": pw.l, "log2_Bks": pw.log2_Bks, "l_ks": pw.l_ks,
                        "secret": "ternary" if pw.ternary else "binary", "sigma": pw.sigma},
             "bsk_bytes": pw.keys_per_coord * pw.n * 2 * pw.l * 2 * pw.N * 8, "ksk_bytes": ksk_bytes(pw.n, pw.N, pw),
+            "parity": ("rows are checked by decryption only; the kernels they time are compared bit for bit with "
+                       "the oracle in tests/test_gpu_wide.py: this preset's r = 128 (3 CMux steps) and r = 1024 "
+                       "(2 steps), and whole ternary bootstraps at N = 2048 with small n"),
             "rows": rows}
 
 

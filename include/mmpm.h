@@ -244,12 +244,18 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
 
 /* What schedule `choice` of this batch shape is (choice < 0: the one in use):
  * waves per blind-rotation workgroup (8 or 4), ciphertexts per wave of the
- * LDS-tiled key switch (0 = the i-split key switch), the number of i splits,
- * and waves per ring component (1 up to N = 1024 and N / 1024 above by default;
- * 2 at N = 512 and 1024 for batches that do not fill the device, r <= 4).  Any
- * output pointer may be NULL. */
+ * key switch (0 = the i-split key switch), the number of i splits, waves per
+ * ring component (1 up to N = 1024 and N / 1024 above by default; 2 at N = 512
+ * and 1024 for batches that do not fill the device, r <= 4), the key-switch
+ * kernel (0: i split over workgroups, per-thread sums; 1: KSK rows staged in
+ * LDS, one output column per lane; 2: KSK rows staged in LDS, one ciphertext
+ * per lane) and the NTT stage schedule of the blind rotation (0: every
+ * cross-lane exchange through LDS; 1: the exchange across the two highest
+ * lane bits by wavefront lane swaps, the others through LDS).  Any output
+ * pointer may be NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
-                         int *ks_cts_per_wave, int *ks_splits, int *waves_per_component);
+                         int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
+                         int *ntt_schedule);
 
 /* ---- serving: continuous batching ---- */
 

@@ -76,7 +76,7 @@ def _load():
         "mm_schedule_count": (i32, [vp, vp, sz, C.POINTER(i32)]),
         "mm_set_schedule": (i32, [vp, vp, sz, i32]),
         "mm_schedule_describe": (i32, [vp, vp, sz, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                       C.POINTER(i32)]),
+                                       C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "mm_server_start": (i32, [vp, sz, u32, C.POINTER(vp)]),
         "mm_submit": (i32, [vp, i32, vp, C.POINTER(u64)]),
         "mm_poll": (i32, [vp, u64, vp]),
@@ -328,9 +328,10 @@ class Context:
 
     def schedule_describe(self, table_ids, choice: int = -1):
         """(waves per blind-rotation workgroup, key-switch ciphertexts per wave, key-switch splits,
-        waves per ring component)."""
+        waves per ring component, key-switch kernel (0 i-split, 1 columns in lanes, 2 one ciphertext
+        per lane), NTT schedule)."""
         ids = _i32(np.atleast_1d(table_ids))
-        v = [C.c_int() for _ in range(4)]
+        v = [C.c_int() for _ in range(6)]
         self._check(lib.mm_schedule_describe(self.h, ids.ctypes.data_as(C.c_void_p), ids.size, choice,
                                              *(C.byref(x) for x in v)))
         return tuple(x.value for x in v)

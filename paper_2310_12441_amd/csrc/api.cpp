@@ -248,13 +248,14 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
 }
 
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
-                         int *ks_cts_per_wave, int *ks_splits, int *waves_per_component)
+                         int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
+                         int *ntt_schedule)
 {
     if (!ctx || !table_ids) return MM_EINVAL;
     std::lock_guard<std::mutex> g(ctx->lock);
     return guard(ctx, [&] {
         mm::describe_schedule(*ctx, table_ids, count, choice, group_waves, ks_cts_per_wave, ks_splits,
-                              waves_per_component);
+                              waves_per_component, ks_kernel, ntt_schedule);
     });
 }
 

@@ -181,7 +181,33 @@ void device_init(mm_ctx &c, int id)
     }
     upload(&d->bsk, kb.data(), kb.size());
     upload(&d->bsk_corr, corr.data(), corr.size());
-    upload(&d->ksk, c.ksk.data(), c.ksk.size());
+    {
+        // the key-switching key in column tiles, [i][tile][l_ks B_ks][64], a few
+        // coordinates at a time through a host buffer
+        const size_t W = p.n + 1, rows = (size_t)p.l_ks << p.log2_Bks, T = (W + 63) / 64;
+        const size_t per_i = T * rows * 64;
+        if (hipMalloc((void **)&d->ksk, (size_t)N * per_i * 4) != hipSuccess) {
+            d->ksk = nullptr;
+            throw Error(MM_ENOMEM, "device key allocation failed");
+        }
+        const size_t chunk = std::max<size_t>(1, ((size_t)64 << 20) / (per_i * 4));
+        std::vector<uint32_t> buf(std::min<size_t>(chunk, N) * per_i);
+        for (size_t i0 = 0; i0 < N; i0 += chunk) {
+            const size_t ni = std::min<size_t>(chunk, N - i0);
+            parallel_for((int64_t)(ni * T), [&](int64_t it) {
+                const size_t i = i0 + (size_t)it / T, x = (size_t)it % T;
+                uint32_t *dst = &buf[(size_t)it * rows * 64];
+                for (size_t row = 0; row < rows; row++) {
+                    const uint32_t *srow = &c.ksk[(i * rows + row) * W];
+                    for (size_t cc = 0; cc < 64; cc++) {
+                        const size_t col = x * 64 + cc;
+                        dst[row * 64 + cc] = col < W ? srow[col] : 0u;
+                    }
+                }
+            });
+            HIPC(hipMemcpy(d->ksk + i0 * per_i, buf.data(), ni * per_i * 4, hipMemcpyHostToDevice));
+        }
+    }
     HIPC(dev::init_kernel_attributes());
     HIPC(hipStreamCreateWithFlags(&d->own, hipStreamNonBlocking));
     c.dev = std::move(d);
@@ -369,13 +395,25 @@ uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count)
     return (uint32_t)P;
 }
 
-// Key-switch schedule for `count` samples: the LDS-tiled kernel (cpw > 0)
-// for large batches, the i-split kernel for small ones.
+// Splits of the i range for the one-ciphertext-per-lane key switch: as many as
+// keep the launch within one round of two workgroups per compute unit.
+static uint32_t ks_lanes_splits(const mm_ctx &c, const Device &d, size_t count)
+{
+    const size_t blocks = ((c.p.n + 1 + 63) / 64) * ((count + 255) / 256);
+    return (uint32_t)std::max<size_t>(1, std::min<size_t>(8, 2 * (size_t)d.num_cu / blocks));
+}
+
+// Key-switch schedule for `count` samples: one ciphertext per lane for large
+// batches, the LDS-tiled kernel with columns in lanes (cpw > 0) for medium
+// ones, the i-split kernel for small ones.
 KsSched ks_default(const mm_ctx &c, const Device &d, size_t count)
 {
     KsSched k;
     const uint32_t rows = c.p.l_ks << c.p.log2_Bks;
-    if (count >= 256 && rows <= (uint32_t)dev::KS_TILED_MAX_ROWS) {
+    if (count >= 512 && rows <= (uint32_t)dev::KS_TILED_MAX_ROWS) {
+        k.cpw = KS_LANES;
+        k.P = ks_lanes_splits(c, d, count);
+    } else if (count >= 256 && rows <= (uint32_t)dev::KS_TILED_MAX_ROWS) {
         k.cpw = 32;
         const size_t blocks = ((c.p.n + 1 + 63) / 64) * ((count + 4 * k.cpw - 1) / (4 * k.cpw));
         k.P = (uint32_t)std::max<size_t>(1, std::min<size_t>(4, (2 * (size_t)d.num_cu + blocks - 1) / blocks));
@@ -398,6 +436,7 @@ void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const in
     K.lwe_N = ext;
     K.rows = rows;
     K.ksk = d.ksk;
+    K.col_tiles = (c.p.n + 1 + 63) / 64;
     K.part = part;
     K.count = count;
     K.n = c.p.n;
@@ -405,7 +444,8 @@ void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const in
     K.Q = c.p.Q;
     K.log2Bks = c.p.log2_Bks;
     K.l_ks = c.p.l_ks;
-    if (ks.cpw > 0) dev::launch_keyswitch_tiled(K, ks.cpw, ks.P, st);
+    if (ks.cpw == KS_LANES) dev::launch_keyswitch_lanes(K, ks.P, st);
+    else if (ks.cpw > 0) dev::launch_keyswitch_tiled(K, ks.cpw, ks.P, st);
     else dev::launch_keyswitch(K, ks.P, st);
     dev::launch_ks_finalize(part, ext, rows, out, count, c.p.n, c.p.N, ks.P, c.p.Q, q_out_per_ct, q_out, st);
 }
@@ -447,12 +487,16 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
     const bool narrow_ok = max_r(c, ids, count) * (uint32_t)dev::waves_per_poly(c.p.N) <= 4;
     std::vector<KsSched> ks{ks_default(c, d, count)};
     const uint32_t rows = c.p.l_ks << c.p.log2_Bks;
+    auto add = [&](KsSched k) {
+        for (auto &o : ks)
+            if (o.cpw == k.cpw && o.P == k.P) return;
+        ks.push_back(k);
+    };
     if (rows <= (uint32_t)dev::KS_TILED_MAX_ROWS && count >= 64)
         for (int cpw : {16, 32, 64})
-            for (uint32_t P : {1u, 2u, 4u}) {
-                KsSched k{cpw, P};
-                if (k.cpw != ks[0].cpw || k.P != ks[0].P) ks.push_back(k);
-            }
+            for (uint32_t P : {1u, 2u, 4u}) add(KsSched{cpw, P});
+    if (rows <= (uint32_t)dev::KS_TILED_MAX_ROWS && count >= 256)
+        for (uint32_t P : {2u, 3u, 4u, 6u}) add(KsSched{KS_LANES, P});
     if (count < 256) ks.push_back(KsSched{0, ks_splits(c, d, count)});
     for (int gw : {8, 4}) {
         if (gw == 4 && !narrow_ok) continue;
@@ -460,6 +504,11 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
     }
     if (wide_slots_ok(c, ids, count))
         for (auto &k : ks) out.push_back(Sched{8, k, 2});
+    if (dev::br_supports_lane_swap(c.p.N))
+        for (int gw : {8, 4}) {
+            if (gw == 4 && !narrow_ok) continue;
+            for (auto &k : ks) out.push_back(Sched{gw, k, 0, 1});
+        }
     return out;
 }
 
@@ -583,12 +632,13 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
     const int grid = br_grid(d, groups, S.gw);
 
     const std::string key = std::to_string(count) + "/" + std::to_string(groups) + "/" + std::to_string(S.gw) + "/" +
-                            std::to_string(S.wpp) + "/" + std::to_string(S.ks.cpw) + "/" + std::to_string(S.ks.P) +
+                            std::to_string(S.wpp) + "/" + std::to_string(S.ntt) + "/" + std::to_string(S.ks.cpw) +
+                            "/" + std::to_string(S.ks.P) +
                             "/" + std::to_string(q_scalar) +
                             "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
                             std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
     run_sequence(
-        d, key, use_graph, st, [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s, S.wpp); },
+        d, key, use_graph, st, [&](hipStream_t s) { dev::launch_blind_rotate(N, A, S.gw, grid, s, S.wpp, S.ntt); },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, S.ks, part, s); });
 }
 
@@ -925,14 +975,17 @@ void set_schedule(mm_ctx &c, const int *ids, size_t count, int choice)
     c.dev->tuned[shape_key(c, ids, count)] = choice;
 }
 
-void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P, int *wpp)
+void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P, int *wpp,
+                       int *ks_kernel, int *ntt)
 {
     const int n = schedule_count(c, ids, count);
     MM_REQUIRE(choice < n, "schedule index out of range");
     Device &d = *c.dev;
     const Sched S = choice >= 0 ? candidates(c, d, ids, count)[choice] : schedule_for(c, d, ids, count);
     if (gw) *gw = S.gw;
-    if (cpw) *cpw = S.ks.cpw;
+    if (cpw) *cpw = S.ks.cpw == KS_LANES ? 64 : S.ks.cpw;
+    if (ks_kernel) *ks_kernel = S.ks.cpw == KS_LANES ? 2 : (S.ks.cpw > 0 ? 1 : 0);
+    if (ntt) *ntt = S.ntt;
     if (P) *P = (int)S.ks.P;
     if (wpp) *wpp = S.wpp ? S.wpp : dev::waves_per_poly(c.p.N);
 }
@@ -965,7 +1018,7 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
     for (size_t k = 0; k < cand.size(); k++) {
         const Sched &S = cand[k];
         const bool default_ks = S.ks.cpw == ks0.cpw && S.ks.P == ks0.P;
-        const bool first_shape = S.gw == first.gw && S.wpp == first.wpp;
+        const bool first_shape = S.gw == first.gw && S.wpp == first.wpp && S.ntt == first.ntt;
         if (!default_ks && !first_shape) continue;  // each key-switch tiling is timed once
         bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &S);
         HIPC(hipStreamSynchronize(st));
@@ -986,8 +1039,8 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
     d.timing = was_timed;
     int choice = 0;
     for (size_t k = 0; k < cand.size(); k++)
-        if (cand[k].gw == br_best.gw && cand[k].wpp == br_best.wpp && cand[k].ks.cpw == ks_best.cpw &&
-            cand[k].ks.P == ks_best.P)
+        if (cand[k].gw == br_best.gw && cand[k].wpp == br_best.wpp && cand[k].ntt == br_best.ntt &&
+            cand[k].ks.cpw == ks_best.cpw && cand[k].ks.P == ks_best.P)
             choice = (int)k;
     d.tuned[shape_key(c, ids, count)] = choice;
     return choice;

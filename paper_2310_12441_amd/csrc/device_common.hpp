@@ -134,7 +134,8 @@ __device__ __forceinline__ void poly_sync()
 }
 
 // Move NP polys from the layout of phase `from` to that of phase `to`
-// through the LDS slot (NP <= 2).  L is the virtual lane.
+// through the LDS slot (NP <= 2).  Lf and Lt are the (virtual) lanes by which
+// the two phases address their layouts.
 //
 // PRIO: the wave drops its issue priority for the LDS round trip and raises it
 // again for the butterflies that follow, so that of the waves sharing a SIMD
@@ -150,12 +151,12 @@ __device__ __forceinline__ void poly_sync()
 // and every wave finished reading it before it wrote for the relayout in between,
 // whose barrier this wave has passed).
 template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool SYNC_BEFORE = true>
-__device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, int L, int from,
-                                         int to)
+__device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, int Lf, int Lt,
+                                         int from, int to)
 {
     using G = Geo<N, W>;
     static_assert(swz_split_holds<N, W>(), "LDS address split");
-    uint32_t *sf = slot + swz_base<N, W>(from, L), *st = slot + swz_base<N, W>(to, L);
+    uint32_t *sf = slot + swz_base<N, W>(from, Lf), *st = slot + swz_base<N, W>(to, Lt);
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     if constexpr (SYNC_BEFORE) poly_sync<N, W>();
 #pragma unroll
@@ -175,31 +176,98 @@ __device__ __forceinline__ void relayout(uint32_t (&x)[NP][(Geo<N, W>::E)], uint
 // before the writes.
 template <int N, int NP, int W, bool PRIO, bool DS>
 __device__ __forceinline__ void relayout_ds(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, uint32_t *slot2,
-                                            int *par, int L, int from, int to)
+                                            int *par, int Lf, int Lt, int from, int to)
 {
     if constexpr (DS) {
         uint32_t *s = (*par & 1) ? slot2 : slot;
         *par ^= 1;
-        relayout<N, NP, W, PRIO, false>(x, s, L, from, to);
+        relayout<N, NP, W, PRIO, false>(x, s, Lf, Lt, from, to);
     } else {
-        relayout<N, NP, W, PRIO>(x, slot, L, from, to);
+        relayout<N, NP, W, PRIO>(x, slot, Lf, Lt, from, to);
     }
+}
+
+// Lane-swap exchange (PL) between the last two NTT phases.  Where one wave
+// holds a polynomial and the next-to-last phase has R = 2 (N = 256 and 1024),
+// the two layouts differ only in which holds idx bits 0, 1 (lanes) and which
+// the two idx bits above the registers' (registers).  With PL the next-to-last
+// phase runs on the virtual lane pl_lane(L), which puts idx bits 0, 1 on lane
+// bits 4, 5, so the exchange is two wavefront lane swaps: v_permlane16_swap
+// across lane bit 4 and v_permlane32_swap across lane bit 5, each exchanging
+// one register bit for the lane bit in one instruction per register pair,
+// instead of an LDS round trip.  Afterwards physical register k holds virtual
+// register pl_reg(k) of the last phase, whose lane is pl_lane(L) as well.
+template <int N, int W>
+constexpr bool pl_ok()
+{
+    using G = Geo<N, W>;
+    return W == 1 && G::NPH >= 3 && G::R(G::NPH - 2) == 2;
+}
+
+__host__ __device__ constexpr int pl_lane(int L) { return ((L >> 4) & 3) | ((L & 15) << 2); }
+
+// an involution: swaps the register bits {LE-2, LE-1} with {0, 1}, keeping the order
+template <int LE>
+__host__ __device__ constexpr int pl_reg(int k)
+{
+    return (k >> (LE - 2)) | ((k & ((1 << (LE - 2)) - 1)) << 2);
+}
+
+template <int N, int W, bool PL>
+__device__ __forceinline__ int phase_lane(int p, int L)
+{
+    if constexpr (PL) return p >= Geo<N, W>::NPH - 2 ? pl_lane(L) : L;
+    else return L;
+}
+
+// physical register of virtual register k in phase p
+template <int N, int W, bool PL>
+__host__ __device__ constexpr int phase_reg(int p, int k)
+{
+    return (PL && p == Geo<N, W>::NPH - 1) ? pl_reg<Geo<N, W>::LE>(k) : k;
+}
+
+template <int E, int NP>
+__device__ __forceinline__ void lane_swap_45(uint32_t (&x)[NP][E])
+{
+    constexpr int LE = ilog2(E), b4 = 1 << (LE - 2), b5 = 1 << (LE - 1);
+#pragma unroll
+    for (int q = 0; q < NP; q++)
+#pragma unroll
+        for (int k0 = 0; k0 < E; k0++) {
+            if (k0 & b4) continue;
+            const auto r = __builtin_amdgcn_permlane16_swap(x[q][k0], x[q][k0 | b4], false, false);
+            x[q][k0] = r[0];
+            x[q][k0 | b4] = r[1];
+        }
+#pragma unroll
+    for (int q = 0; q < NP; q++)
+#pragma unroll
+        for (int k0 = 0; k0 < E; k0++) {
+            if (k0 & b5) continue;
+            const auto r = __builtin_amdgcn_permlane32_swap(x[q][k0], x[q][k0 | b5], false, false);
+            x[q][k0] = r[0];
+            x[q][k0 | b5] = r[1];
+        }
 }
 
 // Forward negacyclic NTT (Cooley-Tukey, merged psi powers, natural order in,
 // bit-reversed order out) of NP polys held in phase-0 layout; returns them in
 // the last phase's layout, reduced to [0, Q) (inputs in [0, Q)).
 // twf[k] = psi^bitrev(k) 2^32 mod Q.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false>
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false>
 __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twf,
                                         int L, const ModQ &m, uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
+    static_assert(!PL || pl_ok<N, W>(), "lane-swap exchange needs one wave per polynomial and R = 2 before the last phase");
 #pragma unroll
     for (int p = 0; p < G::NPH; p++) {
         const int R = G::R(p);
+        const int Lp = phase_lane<N, W, PL>(p, L);
         if (p > 0) {
-            relayout_ds<N, NP, W, PRIO, DS>(x, slot, slot2, par, L, p - 1, p);
+            if (PL && p == G::NPH - 1) lane_swap_45<G::E, NP>(x);
+            else relayout_ds<N, NP, W, PRIO, DS>(x, slot, slot2, par, phase_lane<N, W, PL>(p - 1, L), Lp, p - 1, p);
             // the previous phase left its last stage unreduced; reduce the values
             // that are not multiplicands of this phase's first stage
             const int kt = G::HI(p) - R;
@@ -207,9 +275,12 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
             for (int k = 0; k < G::E; k++)
                 if (!((k >> kt) & 1))
 #pragma unroll
-                    for (int q = 0; q < NP; q++) x[q][k] = min(x[q][k], x[q][k] - m.Q);
+                    for (int q = 0; q < NP; q++) {
+                        uint32_t &v = x[q][phase_reg<N, W, PL>(p, k)];
+                        v = min(v, v - m.Q);
+                    }
         }
-        const int Lhi = (p == 0) ? 0 : (L >> R);
+        const int Lhi = (p == 0) ? 0 : (Lp >> R);
 #pragma unroll
         for (int b = G::HI(p); b >= R; b--) {
             const int kb = b - R, s = G::LOGN - 1 - b;
@@ -225,16 +296,17 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
                 // lane bit, so all outputs stay unreduced and the next phase reduces its
                 // non-multiplicands after the relayout; the last phase ends reduced.
                 const bool lazy = kb > 0 ? ((k0 >> (kb - 1)) & 1) != 0 : p + 1 < G::NPH;
+                const int r0 = phase_reg<N, W, PL>(p, k0), r1 = phase_reg<N, W, PL>(p, k1);
 #pragma unroll
                 for (int q = 0; q < NP; q++) {
-                    const uint32_t u = x[q][k0];
-                    const uint32_t v = mont_mul(x[q][k1], w, m);
+                    const uint32_t u = x[q][r0];
+                    const uint32_t v = mont_mul(x[q][r1], w, m);
                     if (lazy) {
-                        x[q][k0] = u + v;
-                        x[q][k1] = u - v + m.Q;
+                        x[q][r0] = u + v;
+                        x[q][r1] = u - v + m.Q;
                     } else {
-                        x[q][k0] = add_q(u, v, m.Q);
-                        x[q][k1] = sub_q(u, v, m.Q);
+                        x[q][r0] = add_q(u, v, m.Q);
+                        x[q][r1] = sub_q(u, v, m.Q);
                     }
                 }
             }
@@ -245,15 +317,17 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
 // Inverse negacyclic NTT (Gentleman-Sande, bit-reversed in, natural out),
 // without the 1/N factor: polys arrive in the last phase's layout and leave in
 // phase-0 layout.  twi[k] = psi^-bitrev(k) 2^32 mod Q.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false>
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false>
 __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twi,
                                         int L, const ModQ &m, uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
+    static_assert(!PL || pl_ok<N, W>(), "lane-swap exchange needs one wave per polynomial and R = 2 before the last phase");
 #pragma unroll
     for (int p = G::NPH - 1; p >= 0; p--) {
         const int R = G::R(p);
-        const int Lhi = (p == 0) ? 0 : (L >> R);
+        const int Lp = phase_lane<N, W, PL>(p, L);
+        const int Lhi = (p == 0) ? 0 : (Lp >> R);
 #pragma unroll
         for (int b = R; b <= G::HI(p); b++) {
             const int kb = b - R, s = G::LOGN - 1 - b;
@@ -262,15 +336,19 @@ __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
                 if (k0 & (1 << kb)) continue;
                 const int k1 = k0 | (1 << kb);
                 const uint32_t w = twi[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
+                const int r0 = phase_reg<N, W, PL>(p, k0), r1 = phase_reg<N, W, PL>(p, k1);
 #pragma unroll
                 for (int q = 0; q < NP; q++) {
-                    const uint32_t u = x[q][k0], v = x[q][k1];
-                    x[q][k0] = add_q(u, v, m.Q);
-                    x[q][k1] = mont_mul(u - v + m.Q, w, m);
+                    const uint32_t u = x[q][r0], v = x[q][r1];
+                    x[q][r0] = add_q(u, v, m.Q);
+                    x[q][r1] = mont_mul(u - v + m.Q, w, m);
                 }
             }
         }
-        if (p > 0) relayout_ds<N, NP, W, PRIO, DS>(x, slot, slot2, par, L, p, p - 1);
+        if (p > 0) {
+            if (PL && p == G::NPH - 1) lane_swap_45<G::E, NP>(x);
+            else relayout_ds<N, NP, W, PRIO, DS>(x, slot, slot2, par, Lp, phase_lane<N, W, PL>(p - 1, L), p, p - 1);
+        }
     }
 }
 
@@ -316,7 +394,7 @@ __device__ __forceinline__ uint32_t gadget_field_start(uint32_t x, uint32_t off_
 // (eq. def:gsw).  out stays in the last phase's layout.  With OFF the digits
 // enter shifted by +B/2 (g.off then holds (B/2)(1 + ... + B^(l-1))) and the
 // caller starts out from minus (B/2) sum_rows K.
-template <int N, bool OFF = false, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false>
+template <int N, bool OFF = false, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false>
 __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], const uint32_t (&Db)[(Geo<N, W>::E)],
                                         const uint32_t *__restrict__ K, uint32_t *slot, const uint32_t *twf, int L,
                                         const ModQ &m, const GadgetC &g, uint32_t (&out)[2][(Geo<N, W>::E)],
@@ -350,16 +428,19 @@ __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], co
                 pd[1][k] = gadget_digit((int32_t)ya[k], u, g, m.Q);
             }
         }
-        ntt_fwd<N, 2, W, PRIO, DS>(pd, slot, twf, L, m, slot2, par);
-        // virtual lane L now holds NTT positions E L .. E L + E - 1
-        const uint32_t *kb_a = K + ((size_t)(u)*2 + 0) * N + L * E;
-        const uint32_t *kb_b = K + ((size_t)(u)*2 + 1) * N + L * E;
-        const uint32_t *ka_a = K + ((size_t)(g.l + u) * 2 + 0) * N + L * E;
-        const uint32_t *ka_b = K + ((size_t)(g.l + u) * 2 + 1) * N + L * E;
+        ntt_fwd<N, 2, W, PRIO, DS, PL>(pd, slot, twf, L, m, slot2, par);
+        // the lane now holds NTT positions E Lk .. E Lk + E - 1 (Lk its lane in the
+        // last phase), position E Lk + v in register phase_reg(last, v)
+        const int Lk = phase_lane<N, W, PL>(G::NPH - 1, L);
+        const uint32_t *kb_a = K + ((size_t)(u)*2 + 0) * N + Lk * E;
+        const uint32_t *kb_b = K + ((size_t)(u)*2 + 1) * N + Lk * E;
+        const uint32_t *ka_a = K + ((size_t)(g.l + u) * 2 + 0) * N + Lk * E;
+        const uint32_t *ka_b = K + ((size_t)(g.l + u) * 2 + 1) * N + Lk * E;
 #pragma unroll
         for (int k = 0; k < E; k++) {
-            const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
-            const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
+            const int v = phase_reg<N, W, PL>(G::NPH - 1, k);  // an involution: also the word of register k
+            const uint64_t xa = (uint64_t)pd[0][k] * kb_a[v] + (uint64_t)pd[1][k] * ka_a[v];
+            const uint64_t xb = (uint64_t)pd[0][k] * kb_b[v] + (uint64_t)pd[1][k] * ka_b[v];
             out[0][k] = add_q(out[0][k], redc(xa, m), m.Q);
             out[1][k] = add_q(out[1][k], redc(xb, m), m.Q);
         }

@@ -81,18 +81,23 @@ Device &ensure_device(mm_ctx &c);
 void *ws(Device &d, int slot, size_t bytes);
 void *pinned(Device &d, int slot, size_t bytes);
 // A key-switch schedule: cpw > 0 selects the LDS-tiled kernel with cpw
-// ciphertexts per wave, cpw = 0 the i-split kernel; P splits the i range.
+// ciphertexts per wave (columns in lanes), cpw = 0 the i-split kernel,
+// cpw = KS_LANES the kernel with one ciphertext per lane; P splits the i range.
+constexpr int KS_LANES = -1;
 struct KsSched {
     int cpw = 0;
     uint32_t P = 1;
 };
 
 // A batch schedule: blind-rotation group width (8 or 4 waves), waves per
-// component polynomial (0: the ring's default) and key switch.
+// component polynomial (0: the ring's default), key switch, and the NTT stage
+// schedule (0: every cross-lane exchange through LDS; 1: the last exchange by
+// wavefront lane swaps).
 struct Sched {
     int gw = 8;
     KsSched ks;
     int wpp = 0;
+    int ntt = 0;
 };
 
 std::vector<dev::WaveTask> pack_tasks(const std::vector<dev::WaveTask> &cts, uint32_t gw, uint32_t wpp,

@@ -80,7 +80,7 @@ struct BrLds {
     static_assert(BUF_WORDS == Geo<N>::SLOTW, "an accumulator buffer doubles as the exchange slot");
 };
 
-template <int N, int GW, int KEYS, int W = default_wpp(N)>
+template <int N, int GW, int KEYS, int W = default_wpp(N), bool PL = false>
 __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N, W>;
@@ -181,22 +181,26 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
             const uint32_t *K = A.bsk + (size_t)ik * KEYS * (4u * A.l * N);
             int par = 0;  // relayouts since the step's barrier (which slot the next one uses)
             if (run) {
-                // start from the digit-offset correction of coordinate i
-                const uint32_t *C0 = A.bsk_corr + (size_t)ik * 2 * N + L * E;
+                // start from the digit-offset correction of coordinate i, in the
+                // layout of the forward NTT's output
+                const uint32_t *C0 = A.bsk_corr + (size_t)ik * 2 * N + phase_lane<N, W, PL>(G::NPH - 1, L) * E;
 #pragma unroll
                 for (int k = 0; k < E; k++) {
-                    o[0][k] = C0[k];
-                    o[1][k] = C0[N + k];
+                    const int v = phase_reg<N, W, PL>(G::NPH - 1, k);
+                    o[0][k] = C0[v];
+                    o[1][k] = C0[N + v];
                 }
-                ext_mac<N, true, W, (W == 1), DS>(D[0], D[1], K, nxt, A.twf, L, m, g, o, slot2, &par);
+                ext_mac<N, true, W, (W == 1), DS, PL>(D[0], D[1], K, nxt, A.twf, L, m, g, o, slot2, &par);
             }
             if (KEYS == 2) {
                 if (active) rotated_diff(ai, accl, D);  // +a'_i from the same accumulator
-                if (run) ext_mac<N, true, W, (W == 1), DS>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o, slot2, &par);
+                if (run)
+                    ext_mac<N, true, W, (W == 1), DS, PL>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o, slot2,
+                                                          &par);
             }
             if (run) {
                 __asm__ volatile("" ::: "memory");
-                ntt_inv<N, 2, W, (W == 1), DS>(o, nxt, A.twi, L, m, slot2, &par);
+                ntt_inv<N, 2, W, (W == 1), DS, PL>(o, nxt, A.twi, L, m, slot2, &par);
             }
             if (WPP > 1) __syncthreads();  // every lane of the slot has left the exchange slot
             if (active) {
@@ -353,14 +357,14 @@ __global__ void __launch_bounds__(256) k_keyswitch(KsArgs A)
     }
     if (col < W) {
         for (uint32_t i = i_begin; i < i_end; i++) {
-            const uint32_t *rowbase = A.ksk + (size_t)i * A.l_ks * (Bm + 1) * W + col;
+            const uint32_t *rowbase = A.ksk + ((size_t)i * A.col_tiles + blockIdx.x) * A.l_ks * (Bm + 1) * 64 + lane;
 #pragma unroll
             for (int q = 0; q < CPW; q++) {
                 const uint32_t a = __builtin_amdgcn_readfirstlane(src[q][i]);
                 for (uint32_t j = 0; j < A.l_ks; j++) {
                     const uint32_t sh = j * A.log2Bks;
                     const uint32_t d = sh < 32 ? (a >> sh) & Bm : 0u;
-                    acc[q] += rowbase[((size_t)j * (Bm + 1) + d) * W];
+                    acc[q] += rowbase[(j * (Bm + 1) + d) * 64];
                 }
             }
         }
@@ -397,23 +401,25 @@ __global__ void __launch_bounds__(256) k_keyswitch_tiled(KsArgs A)
 #pragma unroll
     for (int q = 0; q < CPW; q++) acc[q] = 0;
 
-    // each thread moves rows*64/256 words of a tile
-    const int per_thread = (int)(rows * 64 / 256);
+    // each thread moves ceil(rows*64/256) words of a tile (rows need not be a
+    // multiple of 4: l_ks * B_ks = 62 with B_ks = 2 and l_ks = 31)
+    const uint32_t tile_words = rows * 64;
+    const int per_thread = (int)((tile_words + 255) / 256);
     uint32_t stage[ROWS / 4];
     auto fetch = [&](uint32_t i) {
-        const uint32_t *base = A.ksk + (size_t)i * rows * W;
+        const uint32_t *base = A.ksk + ((size_t)i * A.col_tiles + blockIdx.x) * tile_words;
 #pragma unroll
         for (int k = 0; k < ROWS / 4; k++) {
-            if (k < per_thread) {
-                const uint32_t e = threadIdx.x + 256u * k, rr = e >> 6, c = col0 + (e & 63);
-                stage[k] = c < W ? base[(size_t)rr * W + c] : 0u;
-            }
+            const uint32_t e = threadIdx.x + 256u * k;
+            if (k < per_thread) stage[k] = e < tile_words ? base[e] : 0u;
         }
     };
     auto put = [&](int b) {
 #pragma unroll
-        for (int k = 0; k < ROWS / 4; k++)
-            if (k < per_thread) tile[b][threadIdx.x + 256 * k] = stage[k];
+        for (int k = 0; k < ROWS / 4; k++) {
+            const uint32_t e = threadIdx.x + 256u * k;
+            if (k < per_thread && e < tile_words) tile[b][e] = stage[k];
+        }
     };
     if (i_begin < i_end) {
         fetch(i_begin);
@@ -465,6 +471,119 @@ __global__ void __launch_bounds__(256) k_keyswitch_tiled(KsArgs A)
             const size_t ct = ct_base + q;
             if (ct < A.count) A.part[((size_t)blockIdx.z * A.count + ct) * W + col] = acc[q];
         }
+    }
+}
+
+// Key switch for large batches with one ciphertext per lane.  A workgroup
+// (4 waves) owns 256 ciphertexts and 64 output columns; for each input
+// coordinate i it stages the l_ks x B_ks candidate rows KSK[i][*][*][cols] in
+// LDS (double-buffered through registers, rows padded to 66 words), and every
+// lane forms the LDS addresses of the l_ks rows its own digits select once per
+// i, then adds the 64 columns of those rows to 64-bit sums in registers, two
+// rows at a time summed in 32 bits first (both below Q < 2^31).  The digit
+// work is thus spread over the lanes and amortised over 64 columns; lanes
+// whose digits agree read the same LDS words (broadcasts), and the 66-word row
+// pitch puts the B_ks candidates of one digit on distinct banks.  KSK traffic:
+// one read of the column slice per 256 ciphertexts.  Partial sums over the
+// i-split blockIdx.z go to part (not reduced; every sum < 2^31 l_ks N).
+constexpr int KSL_COLS = KS_TILE_COLS, KSL_PITCH = 66, KSL_CTS = 256, KSL_CHUNK = 32;
+
+template <bool FULL>
+__global__ void __launch_bounds__(256, 2) k_keyswitch_lanes(KsArgs A)
+{
+    constexpr int ROWS = KS_TILED_MAX_ROWS, V4 = ROWS * KSL_COLS / 4 / 256;
+    __shared__ __align__(16) uint32_t tile[2][ROWS * KSL_PITCH];
+    const uint32_t W = A.n + 1, Bks = 1u << A.log2Bks, rows = FULL ? (uint32_t)ROWS : A.l_ks * Bks;
+    const uint32_t col0 = blockIdx.x * KSL_COLS;
+    const uint32_t iper = (A.N + gridDim.z - 1) / gridDim.z;
+    const uint32_t i_begin = blockIdx.z * iper, i_end = min(A.N, i_begin + iper);
+    const size_t ct = (size_t)blockIdx.y * KSL_CTS + threadIdx.x;
+    const bool ok = ct < A.count;
+    const uint32_t *src = A.lwe_N + (ok ? (A.rows ? (size_t)A.rows[ct] : ct) : 0) * (A.N + 1);
+    uint64_t acc[KSL_COLS];
+#pragma unroll
+    for (int c = 0; c < KSL_COLS; c++) acc[c] = 0;
+
+    // staging: the tile of coordinate i is rows x 64 contiguous words; thread t
+    // moves the 4-word pieces t + 256 k (row (t + 256 k) >> 4, column 4 (t & 15))
+    const uint32_t tile4 = rows * KSL_COLS / 4;
+    uint4 stage[V4];
+    auto fetch = [&](uint32_t i) {
+        const uint4 *base = reinterpret_cast<const uint4 *>(A.ksk + ((size_t)i * A.col_tiles + blockIdx.x) * rows * KSL_COLS);
+#pragma unroll
+        for (int k = 0; k < V4; k++) {
+            const uint32_t e4 = threadIdx.x + 256u * k;
+            if (FULL || e4 < tile4) stage[k] = base[e4];
+        }
+    };
+    auto put = [&](int b) {
+#pragma unroll
+        for (int k = 0; k < V4; k++) {
+            const uint32_t e4 = threadIdx.x + 256u * k;
+            if (FULL || e4 < tile4) {
+                uint32_t *d = &tile[b][(e4 >> 4) * KSL_PITCH + 4 * (e4 & 15)];
+                *reinterpret_cast<uint2 *>(d) = make_uint2(stage[k].x, stage[k].y);
+                *reinterpret_cast<uint2 *>(d + 2) = make_uint2(stage[k].z, stage[k].w);
+            }
+        }
+    };
+    // acc += row0 + row1 (64 columns each), or row0 alone, 16 columns at a time
+    // (the compiler is kept from hoisting every LDS read of the rows: registers)
+    auto add2 = [&](const uint32_t *r0, const uint32_t *r1) {
+#pragma unroll
+        for (int c0 = 0; c0 < KSL_COLS; c0 += KSL_CHUNK) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = c0; c < c0 + KSL_CHUNK; c += 2) {
+                const uint2 x = *reinterpret_cast<const uint2 *>(r0 + c);
+                const uint2 y = *reinterpret_cast<const uint2 *>(r1 + c);
+                acc[c] += (uint64_t)(x.x + y.x);
+                acc[c + 1] += (uint64_t)(x.y + y.y);
+            }
+        }
+    };
+    auto add1 = [&](const uint32_t *r0) {
+#pragma unroll
+        for (int c0 = 0; c0 < KSL_COLS; c0 += KSL_CHUNK) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = c0; c < c0 + KSL_CHUNK; c += 2) {
+                const uint2 x = *reinterpret_cast<const uint2 *>(r0 + c);
+                acc[c] += (uint64_t)x.x;
+                acc[c + 1] += (uint64_t)x.y;
+            }
+        }
+    };
+    if (i_begin < i_end) {
+        fetch(i_begin);
+        put(0);
+    }
+    __syncthreads();
+    int b = 0;
+    for (uint32_t i = i_begin; i < i_end; i++) {
+        if (i + 1 < i_end) fetch(i + 1);
+        const uint32_t a = src[i];
+        const uint32_t *tb = tile[b];
+        // the row of each digit, two rows at a time (the digit loop stays rolled:
+        // unrolled, the compiler keeps too many row reads in flight)
+        auto digit = [&](uint32_t j) {
+            const uint32_t sh = j * A.log2Bks;
+            return sh < 32 ? (a >> sh) & (Bks - 1) : 0u;
+        };
+        uint32_t j = 0;
+        for (; j + 1 < A.l_ks; j += 2)
+            add2(tb + (j * Bks + digit(j)) * KSL_PITCH, tb + ((j + 1) * Bks + digit(j + 1)) * KSL_PITCH);
+        if (j < A.l_ks) add1(tb + (j * Bks + digit(j)) * KSL_PITCH);
+        __syncthreads();
+        if (i + 1 < i_end) put(b ^ 1);
+        __syncthreads();
+        b ^= 1;
+    }
+    if (ok) {
+        uint64_t *o = A.part + ((size_t)blockIdx.z * A.count + ct) * W + col0;
+#pragma unroll
+        for (int c = 0; c < KSL_COLS; c++)
+            if (col0 + c < W) o[c] = acc[c];
     }
 }
 
@@ -543,11 +662,20 @@ void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, 
 // wave: lower latency for batches too small to fill the chip).
 constexpr bool br_wide_slots(int N) { return N == 512 || N == 1024; }
 
-template <int N, int GW, int KEYS, int W = default_wpp(N)>
+template <int N, int GW, int KEYS, int W = default_wpp(N), bool PL = false>
 static hipError_t br_attr_n()
 {
-    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS, W>,
+    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS, W, PL>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(N, GW, W));
+}
+
+// NTT schedule 1 (the lane-swap exchange) exists where one wave holds a
+// polynomial and the next-to-last phase has R = 2: N = 256 and 1024.
+template <int N>
+constexpr bool br_lane_swap()
+{
+    if constexpr (default_wpp(N) == 1) return pl_ok<N, 1>();
+    else return false;
 }
 
 template <int N>
@@ -562,6 +690,12 @@ static hipError_t br_attr_all()
     if constexpr (br_wide_slots(N)) {
         if (e == hipSuccess) e = br_attr_n<N, 8, 1, 2>();
         if (e == hipSuccess) e = br_attr_n<N, 8, 2, 2>();
+    }
+    if constexpr (br_lane_swap<N>()) {
+        if (e == hipSuccess) e = br_attr_n<N, 8, 1, 1, true>();
+        if (e == hipSuccess) e = br_attr_n<N, 8, 2, 1, true>();
+        if (e == hipSuccess) e = br_attr_n<N, 4, 1, 1, true>();
+        if (e == hipSuccess) e = br_attr_n<N, 4, 2, 1, true>();
     }
     return e;
 }
@@ -604,8 +738,19 @@ bool device_supports_n(uint32_t N)
 int waves_per_poly(uint32_t N) { return N > 1024 ? (int)(N / 1024) : 1; }
 
 template <int N, int KEYS>
-static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp)
+static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp, int ntt)
 {
+    if constexpr (br_lane_swap<N>()) {
+        if (ntt == 1 && (wpp == 0 || wpp == 1)) {
+            if (gw == 4)
+                hipLaunchKernelGGL((k_blind_rotate<N, 4, KEYS, 1, true>), dim3(grid), dim3(256), br_lds_bytes(N, 4),
+                                   st, A);
+            else
+                hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS, 1, true>), dim3(grid), dim3(512), br_lds_bytes(N, 8),
+                                   st, A);
+            return;
+        }
+    }
     if constexpr (br_wide_slots(N)) {
         if (wpp == 2) {
             hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS, 2>), dim3(grid), dim3(512), br_lds_bytes(N, 8, 2), st, A);
@@ -622,26 +767,32 @@ static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st, int 
 }
 
 template <int N>
-static void launch_br_n(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp)
+static void launch_br_n(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp, int ntt)
 {
-    if (A.keys == 2) launch_br_nk<N, 2>(A, gw, grid, st, wpp);
-    else launch_br_nk<N, 1>(A, gw, grid, st, wpp);
+    if (A.keys == 2) launch_br_nk<N, 2>(A, gw, grid, st, wpp, ntt);
+    else launch_br_nk<N, 1>(A, gw, grid, st, wpp, ntt);
 }
 
-void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp)
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp, int ntt)
 {
     switch (N) {
-    case 256: launch_br_n<256>(A, gw, grid, st, wpp); break;
-    case 512: launch_br_n<512>(A, gw, grid, st, wpp); break;
-    case 1024: launch_br_n<1024>(A, gw, grid, st, wpp); break;
-    case 2048: launch_br_n<2048>(A, gw, grid, st, wpp); break;
-    case 4096: launch_br_n<4096>(A, gw, grid, st, wpp); break;
-    case 8192: launch_br_n<8192>(A, gw, grid, st, wpp); break;
+    case 256: launch_br_n<256>(A, gw, grid, st, wpp, ntt); break;
+    case 512: launch_br_n<512>(A, gw, grid, st, wpp, ntt); break;
+    case 1024: launch_br_n<1024>(A, gw, grid, st, wpp, ntt); break;
+    case 2048: launch_br_n<2048>(A, gw, grid, st, wpp, ntt); break;
+    case 4096: launch_br_n<4096>(A, gw, grid, st, wpp, ntt); break;
+    case 8192: launch_br_n<8192>(A, gw, grid, st, wpp, ntt); break;
     default: break;
     }
 }
 
 bool br_supports_wpp(uint32_t N, int wpp) { return wpp == waves_per_poly(N) || (wpp == 2 && br_wide_slots((int)N)); }
+
+bool br_supports_lane_swap(uint32_t N)
+{
+    return (N == 256 && br_lane_swap<256>()) || (N == 512 && br_lane_swap<512>()) ||
+           (N == 1024 && br_lane_swap<1024>());
+}
 
 template <int N>
 static size_t br_lds_n(int gw, int wpp)
@@ -758,6 +909,14 @@ void launch_keyswitch_tiled(const KsArgs &A, int cpw, uint32_t splits, hipStream
         else hipLaunchKernelGGL((k_keyswitch_tiled<64, false>), grid, dim3(256), 0, st, A);
         break;
     }
+}
+
+void launch_keyswitch_lanes(const KsArgs &A, uint32_t splits, hipStream_t st)
+{
+    dim3 grid(A.col_tiles, (uint32_t)((A.count + KSL_CTS - 1) / KSL_CTS), splits);
+    const bool full = (A.l_ks << A.log2Bks) == (uint32_t)KS_TILED_MAX_ROWS;
+    if (full) hipLaunchKernelGGL(k_keyswitch_lanes<true>, grid, dim3(256), 0, st, A);
+    else hipLaunchKernelGGL(k_keyswitch_lanes<false>, grid, dim3(256), 0, st, A);
 }
 
 void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st)

@@ -83,11 +83,18 @@ struct WideArgs {
 constexpr int KS_CTS_PER_WAVE = 4;
 constexpr int KS_TILED_MAX_ROWS = 128;  // l_ks * B_ks handled by the LDS-tiled key switch
 
+// Device layout of the key-switching key: column tiles of 64 output words,
+// [i][tile][l_ks B_ks rows][64] (columns past n + 1 hold zeros), so that the
+// candidate rows of one coordinate for one tile are one contiguous block.
+constexpr int KS_TILE_COLS = 64;
+
 struct KsArgs {
     const uint32_t *lwe_N;  // extracted samples at Q, [*][N + 1]
     const int32_t *rows;    // output row k reads sample rows[k] (null: sample k)
-    const uint32_t *ksk;    // [N][l_ks][B_ks][n + 1]
-    uint64_t *part;         // [splits][count][n + 1] (the tiled kernel writes u32 residues into u64 slots)
+    const uint32_t *ksk;    // [N][col_tiles][l_ks B_ks][64] (tiles of the [N][l_ks][B_ks][n + 1] key)
+    uint32_t col_tiles;     // ceil((n + 1) / 64)
+    uint64_t *part;         // [splits][count][n + 1] (the tiled kernel writes u32 residues into u64 slots,
+                            // the lane kernel unreduced 64-bit sums)
     size_t count;
     uint32_t n, N, Q, log2Bks, l_ks;
 };
@@ -101,8 +108,12 @@ void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows
                          hipStream_t st);
 // wpp: waves per polynomial (0: one up to N = 1024, N / 1024 above; 2 is also
 // available at N = 512 and 1024, see br_supports_wpp).
-void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp = 0);
+// ntt: the NTT stage schedule, 0 (every exchange through LDS) or 1 (the last
+// exchange by wavefront lane swaps; where br_supports_lane_swap(N), one wave per
+// polynomial).
+void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp = 0, int ntt = 0);
 bool br_supports_wpp(uint32_t N, int wpp);
+bool br_supports_lane_swap(uint32_t N);
 // wide modulus: ACC = Phi(b')(0, V) into A.acc_wr; one CMux step (A.step) from
 // A.acc_rd into A.acc_wr; extraction of component 0 switched to Q[0]
 // (ext[c] from the component at acc_off[c]); the accumulator as uint64 values
@@ -125,6 +136,8 @@ void launch_sample_extract(const uint32_t *rlwe, uint32_t *lwe, size_t count, ui
                            hipStream_t st);
 void launch_keyswitch(const KsArgs &A, uint32_t splits, hipStream_t st);
 void launch_keyswitch_tiled(const KsArgs &A, int cpw, uint32_t splits, hipStream_t st);
+// one ciphertext per lane, 256 per workgroup, 64 columns (l_ks B_ks <= KS_TILED_MAX_ROWS)
+void launch_keyswitch_lanes(const KsArgs &A, uint32_t splits, hipStream_t st);
 void launch_ks_finalize(const uint64_t *part, const uint32_t *lwe_N, const int32_t *rows, uint32_t *out, size_t count,
                         uint32_t n,
                         uint32_t N, uint32_t splits, uint32_t Q, const uint32_t *q_out_per_ct, uint32_t q_out,

@@ -115,7 +115,8 @@ void run_negacyclic_mul(mm_ctx &c, const uint32_t *a, const uint32_t *b, size_t 
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count);
 int schedule_count(mm_ctx &c, const int *ids, size_t count);
 void set_schedule(mm_ctx &c, const int *ids, size_t count, int choice);
-void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P, int *wpp);
+void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int *gw, int *cpw, int *P, int *wpp,
+                       int *ks_kernel, int *ntt);
 void set_timing(mm_ctx &c, bool on);
 void last_timing(mm_ctx &c, float *br_ms, float *ks_ms);
 

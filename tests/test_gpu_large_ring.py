@@ -146,6 +146,59 @@ def test_bootstrap_tfhe_shaped_small(plain):
     np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, 16, c.keys.s, got), f[m])
 
 
+@pytest.mark.parametrize("plain", [False, True])
+def test_bootstrap_8192_end_to_end(plain):
+    """r = 1 at N = 8192 (one polynomial over 8 waves), t = 2^14: the whole
+    bootstrap -- n CMux steps, extraction of an 8193-word sample, its key switch
+    over 65,536 key rows and the final switch -- against the oracle."""
+    say("bootstrap N=8192 r=1 n=12 plain", plain)
+    c = case(8192, n=12)
+    t = 16384
+    tid, f, V = c.table(t, t, 1, 63)
+    q = 2 * 8192
+    ct = c.encrypt(q, t, messages(t, 3, 64), 65)
+    got = c.ctx.bootstrap([tid] * 3, ct, plain=plain)
+    want = oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, q, ct)
+    np.testing.assert_array_equal(got, want)
+    # the same at Q, before the last modulus switch
+    np.testing.assert_array_equal(c.ctx.bootstrap([tid] * 3, ct, q_out=Q, plain=plain),
+                                  oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, Q, ct))
+
+
+def test_bootstrap_tfhe_shaped_8192_bench_batch_sampled():
+    """The TFHE-shaped comparison point for t = 2^14 exactly as the benchmark times
+    it: n = 630, N = 8192, r = 1, its key, table and encryption seeds, a batch of
+    4096 in one autotuned launch; sampled outputs equal the oracle's, stored by
+    tests/golden/make_oracle_expected.py (the oracle takes minutes per ciphertext
+    at this size)."""
+    import importlib.util
+    import os
+    b = _gpu()
+    spec_path = os.path.join(os.path.dirname(__file__), "golden", "make_oracle_expected.py")
+    sp = importlib.util.spec_from_file_location("make_oracle_expected", spec_path)
+    gold = importlib.util.module_from_spec(sp)
+    sp.loader.exec_module(gold)
+    spec = gold.SETS["tfhe_shaped_8192"]
+    expected = gold.load("tfhe_shaped_8192")
+    p, t, r = spec["params"], spec["t"], spec["r"]
+    say("tfhe-shaped 8192 keygen (n = 630)")
+    dr = key_draws(p, spec["key_seed"])
+    ctx = b.Context(p, dr)
+    ctx.device_init(0)
+    tid = ctx.table_create(t, t, r, negacyclic_table(t, t, spec["table_seed"]))
+    q, m, ct = gold.inputs(spec, dr["s"])
+    ed = enc_draws(p.n, q, spec["batch"], spec["enc_seed"])
+    np.testing.assert_array_equal(ctx.encrypt(q, t, m, ed["a"], ed["e"]), ct)
+    ids = np.full(spec["batch"], tid, np.int32)
+    say("autotune + batch of", spec["batch"])
+    ctx.autotune(ids, ct)
+    out = ctx.bootstrap(ids, ct)
+    assert sorted(expected) == sorted(spec["pick"])
+    for i, want in expected.items():
+        np.testing.assert_array_equal(out[i], want, err_msg=f"ciphertext {i}")
+    ctx.close()
+
+
 def test_bootstrap_mmpm_r2_at_4096_and_schedules():
     """r = 2 at N = 4096 (one 8-wave group per ciphertext); every schedule gives the same bits."""
     c = case(4096, n=12)

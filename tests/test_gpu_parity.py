@@ -241,7 +241,9 @@ def test_bootstrap_mixed_batch_equals_alone(paper):
     got = paper.ctx.bootstrap(ids, cts)
     alone = paper.ctx.bootstrap(ids, cts, plain=True)
     np.testing.assert_array_equal(got, alone)
-    for c in range(0, len(ids), 6):
+    # the first ciphertext of every class, and every sixth
+    picks = sorted({int(np.where(cls == k)[0][0]) for k in range(len(CLASS_MIX))} | set(range(0, len(ids), 6)))
+    for c in picks:
         tid, t, r, V = tabs[cls[c]]
         q = 2 * paper.p.N * r
         want = oracle.bootstrap(paper.p, r, paper.keys.bsk, paper.keys.ksk, V, q, q, cts[c])
@@ -291,6 +293,35 @@ def test_keyswitch_tiled_batch(paper):
         np.testing.assert_array_equal(got[c], oracle.keyswitch(paper.p, paper.keys.ksk, lw[c]))
 
 
+def test_keyswitch_tiled_rows_not_multiple_of_4():
+    """Key-switch base 2 with 31 digits (l_ks B_ks = 62 candidate rows per
+    coordinate, not a multiple of 4, an odd digit count): both LDS-staged
+    kernels stage every row and take every digit, at their default tilings
+    (300 and 600 samples) and at every tiling a bootstrap batch of 300 may use
+    (eq. equ-key-swi)."""
+    p = Params(n=16, N=256, log2_B=8, l=3, log2_Bks=1, l_ks=31)
+    c = Case(p, 31)
+    rng = np.random.default_rng(31)
+    for cnt in (300, 600):
+        lw = rng.integers(0, Q, (cnt, p.N + 1), dtype=np.uint32)
+        say("keyswitch base 2, 31 digits,", cnt, "samples")
+        got = c.ctx.keyswitch(lw)
+        for k in (0, 1, 150, 298, cnt - 1):
+            np.testing.assert_array_equal(got[k], oracle.keyswitch(p, c.keys.ksk, lw[k]), err_msg=f"sample {k}")
+    tid, f, V = c.table(16, 16, 2, 32)
+    q = 2 * p.N * 2
+    cts = c.encrypt(q, 16, messages(16, 300, 33), 34)
+    ids = np.full(300, tid, np.int32)
+    want = oracle.bootstrap_many(p, 2, c.keys.bsk, c.keys.ksk, V, q, q, cts)
+    n = c.ctx.schedule_count(ids)
+    kinds = {c.ctx.schedule_describe(ids, k)[4] for k in range(n)}
+    assert kinds == {1, 2}, kinds  # both LDS-staged key switches among the candidates
+    for choice in range(n):
+        c.ctx.set_schedule(ids, choice)
+        np.testing.assert_array_equal(c.ctx.bootstrap(ids, cts), want, err_msg=f"schedule {choice}")
+    c.ctx.close()
+
+
 def test_every_schedule_gives_the_same_bits(paper):
     """All candidate schedules (4- and 8-wave groups, key-switch tilings) agree bit for bit."""
     tabs = []
@@ -304,8 +335,10 @@ def test_every_schedule_gives_the_same_bits(paper):
     n = paper.ctx.schedule_count(ids)
     say("schedules", n)
     assert n >= 4
-    # 2-wave component slots are among the candidates (N = 1024, r <= 4)
+    # 2-wave component slots are among the candidates (N = 1024, r <= 4), and
+    # both LDS-staged key switches
     assert {paper.ctx.schedule_describe(ids, k)[3] for k in range(n)} == {1, 2}
+    assert {paper.ctx.schedule_describe(ids, k)[4] for k in range(n)} == {1, 2}
     ref = None
     for choice in range(n):
         paper.ctx.set_schedule(ids, choice)
@@ -417,14 +450,23 @@ def test_ternary_paper_shaped_single():
     case.ctx.close()
 
 
-def test_full_batch_bench_configuration_sampled():
-    """The timed workload itself: 4096 paper-shaped ciphertexts (sigma = 3.2, the bench
-    seeds), autotuned schedule, one batched launch; sampled outputs equal the oracle's."""
+@pytest.fixture(scope="module")
+def bench_keys():
+    """The key set of the benchmark (paper-shaped parameters, key seed 1)."""
     b = _gpu()
     p = PRESETS["paper_shaped"]["params"]
     dr = key_draws(p, 1)
     ctx = b.Context(p, dr)
     ctx.device_init(0)
+    yield ctx, oracle.KeySet(p, dr), p
+    ctx.close()
+
+
+def test_full_batch_bench_configuration_sampled(bench_keys):
+    """The timed workload itself: 4096 paper-shaped ciphertexts (sigma = 3.2, the bench
+    seeds), autotuned schedule, one batched launch; 64 outputs spread over the batch
+    equal the oracle's."""
+    ctx, keys, p = bench_keys
     f = negacyclic_table(4096, 4096, 2)
     tid = ctx.table_create(4096, 4096, 4, f)
     m = messages(4096, 4096, 3)
@@ -432,15 +474,46 @@ def test_full_batch_bench_configuration_sampled():
     ct = ctx.encrypt(8192, 4096, m, ed["a"], ed["e"])
     ids = np.full(4096, tid, np.int32)
     say("bench configuration: autotune + batch of 4096")
+    np.testing.assert_array_equal(ct, oracle.encrypt(p.n, 8192, 4096, keys.s, m, ed["a"], ed["e"]))
     ctx.autotune(ids, ct)
     out = ctx.bootstrap(ids, ct)
-    keys = oracle.KeySet(p, dr)
     V = oracle.test_vector(p.N, 4, Q, 4096, 4096, f)
-    pick = np.array([0, 1, 2, 1023, 2048, 3071, 4094, 4095])
+    pick = np.unique(np.concatenate([[0, 1, 2, 1023, 2048, 3071, 4094, 4095], np.linspace(0, 4095, 60).astype(int)]))
     say("oracle on", pick.size, "samples")
     want = oracle.bootstrap_many(p, 4, keys.bsk, keys.ksk, V, 8192, 8192, ct[pick])
     np.testing.assert_array_equal(out[pick], want)
-    ctx.close()
+
+
+def test_mixed_bench_configuration_sampled_per_class(bench_keys):
+    """The uneven batch the benchmark times: 2048 paper-shaped ciphertexts, class
+    (t, r) drawn uniformly from {(2^8,1), (2^10,2), (2^12,4), (2^14,8)} with the
+    bench's seeds, autotuned schedule, one launch; 16 outputs of every class equal
+    the oracle's."""
+    ctx, keys, p = bench_keys
+    M = 2048
+    cls = class_mix(M, 8)
+    cts = np.empty((M, p.n + 1), np.uint32)
+    tabs = []
+    for k, (t, r) in enumerate(CLASS_MIX):
+        f = negacyclic_table(t, t, 100 + k)
+        tabs.append((ctx.table_create(t, t, r, f), t, r, oracle.test_vector(p.N, r, Q, t, t, f)))
+        sel = np.where(cls == k)[0]
+        q = 2 * p.N * r
+        ed = enc_draws(p.n, q, sel.size, 400 + k)
+        mk = messages(t, sel.size, 500 + k)
+        cts[sel] = oracle.encrypt(p.n, q, t, keys.s, mk, ed["a"], ed["e"])
+        np.testing.assert_array_equal(ctx.encrypt(q, t, mk, ed["a"], ed["e"]), cts[sel])
+    ids = np.array([tabs[k][0] for k in cls], np.int32)
+    say("uneven batch of", M, "autotuned")
+    ctx.autotune(ids, cts)
+    out = ctx.bootstrap(ids, cts)
+    for k, (tid, t, r, V) in enumerate(tabs):
+        sel = np.where(cls == k)[0]
+        pick = sel[np.linspace(0, sel.size - 1, 16).astype(int)]
+        q = 2 * p.N * r
+        say("oracle on 16 of class", (t, r))
+        want = oracle.bootstrap_many(p, r, keys.bsk, keys.ksk, V, q, q, cts[pick])
+        np.testing.assert_array_equal(out[pick], want, err_msg=f"class {(t, r)}")
 
 
 def test_batch_three_times_the_bench_sampled(paper):

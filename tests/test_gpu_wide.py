@@ -135,6 +135,53 @@ def test_wide_ternary():
     np.testing.assert_array_equal(out, oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
 
 
+@pytest.mark.parametrize("plain", [False, True])
+def test_wide_ternary_2048_end_to_end(plain):
+    """The ternary wide-modulus kernel the paper-margin rows time (N = 2048, two
+    waves per polynomial, both CMux terms per step), over a whole bootstrap at
+    small n, r = 2, 2Nr/t = 128: against the oracle, and the outputs decrypt."""
+    c = case(2048, 8, ternary=True)
+    r = 2
+    t = 2 * 2048 * r // 128
+    q = 2 * 2048 * r
+    tid, f, V = c.table(t, r, 93)
+    m = messages(t, 3, 94)
+    ct = c.encrypt(q, t, m, 95)
+    say("wide ternary N=2048 bootstrap plain", plain)
+    got = c.ctx.bootstrap([tid] * 3, ct, plain=plain)
+    np.testing.assert_array_equal(got, oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, t, c.keys.s, got), f[m])
+
+
+@pytest.mark.parametrize("ternary", [False, True])
+def test_wide_blind_rotate_4096(ternary):
+    """N = 4096 at the wide modulus (8 waves per polynomial; the largest ring the
+    second prime carries): three CMux steps for mixed r against the oracle, and
+    a whole bootstrap at small n."""
+    c = case(4096, 4, ternary=ternary)
+    ids, cts, Vs, rr = [], [], [], []
+    for k, r in enumerate((1, 2)):
+        t = 2 * 4096 * r // 128
+        tid, f, V = c.table(t, r, 130 + k)
+        ct = c.encrypt(2 * 4096 * r, t, messages(t, 1, 131 + k), 132 + k)
+        ids.append(tid)
+        cts.append(ct[0])
+        Vs.append(V)
+        rr.append(r)
+    say("wide N=4096 ternary", ternary, "3 steps")
+    got = c.ctx.blind_rotate(ids, np.array(cts), 3)
+    off = 0
+    for j, r in enumerate(rr):
+        size = r * 2 * 4096
+        want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, Vs[j], cts[j], 3)
+        np.testing.assert_array_equal(got[off:off + size].reshape(r, 2, 4096), want, err_msg=f"ct {j} r {r}")
+        off += size
+    q = 2 * 4096
+    out = c.ctx.bootstrap([ids[0]], np.array(cts[:1]))
+    np.testing.assert_array_equal(out, oracle.w_bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, Vs[0], q, q,
+                                                               np.array(cts[:1])))
+
+
 def test_wide_bootstrap_2048():
     c = case(2048, 8)
     r = 2
@@ -187,17 +234,33 @@ def margin():
     return WideCase(pre["params"], 21), pre
 
 
-def test_paper_margin_first_step_sampled(margin):
-    """n = 512, N = 2048, r = 128: the accumulator after the initialisation and one
-    CMux step, against the oracle, for one ciphertext."""
+@pytest.mark.parametrize("steps", [1, 3])
+def test_paper_margin_first_steps(margin, steps):
+    """n = 512, N = 2048, r = 128, ternary: the accumulator after the
+    initialisation and the first CMux steps, against the oracle, for one
+    ciphertext (every component)."""
     c, pre = margin
     t, r = pre["t"], pre["r"]
     q = 2 * c.p.N * r
     tid, f, V = c.table(t, r, 22)
     ct = c.encrypt(q, t, messages(t, 1, 23), 24)
-    got = c.ctx.blind_rotate([tid], ct, 1).reshape(r, 2, c.p.N)
-    say("oracle, one step at r = 128")
-    want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, V, ct[0], 1)
+    got = c.ctx.blind_rotate([tid], ct, steps).reshape(r, 2, c.p.N)
+    say("oracle,", steps, "steps at r = 128")
+    want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, V, ct[0], steps)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_paper_margin_r_1024_two_steps(margin):
+    """The largest table of the sweep (log t = 15: r = 1024 at N = 2048, Table 2),
+    ternary, 54-bit ring: two CMux steps against the oracle."""
+    c, pre = margin
+    r, t = 1024, 1 << 15
+    q = 2 * c.p.N * r
+    tid, f, V = c.table(t, r, 28)
+    ct = c.encrypt(q, t, messages(t, 1, 29), 30)
+    got = c.ctx.blind_rotate([tid], ct, 2).reshape(r, 2, c.p.N)
+    say("oracle, two steps at r = 1024")
+    want = oracle.w_blind_rotate(c.p, r, c.keys.bsk, V, ct[0], 2)
     np.testing.assert_array_equal(got, want)
 
 
