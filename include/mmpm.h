@@ -213,6 +213,21 @@ int mm_sample_extract(mm_ctx *ctx, const uint32_t *rlwe, size_t count, uint32_t 
 int mm_keyswitch(mm_ctx *ctx, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n,
                  uint32_t flags, void *stream);
 
+/* The key switch of mm_keyswitch (with the final residues at Q) for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  lwe_N and lwe_n are device
+ * pointers ([count][N+1] and [count][n+1], the caller's), the call is
+ * asynchronous on `stream` and calls no hipMalloc/hipFree nor any allocating
+ * routine: the partial sums live in a fixed 64 MiB device array per GPU (held
+ * until the process ends), so count * (n + 1) * 8 must not exceed 64 MiB
+ * (MM_EINVAL otherwise; 13,290 samples at n = 630).  mm_device_init must have
+ * run on the context (MM_ESTATE otherwise).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams, other contexts or
+ * threads) race and must be serialised by the caller.  Same bits as
+ * mm_keyswitch. */
+int mm_keyswitch_noalloc(mm_ctx *ctx, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n,
+                         void *stream);
+
 /* Negacyclic products a_c * b_c in Z_Q[x]/(x^N+1) through the device NTT:
  * a, b, out are [count][N]. */
 int mm_negacyclic_mul(mm_ctx *ctx, const uint32_t *a, const uint32_t *b, size_t count,

@@ -23,7 +23,7 @@ SYMBOLS = [
     "mm_keygen", "mm_free", "mm_last_error", "mm_get_params", "mm_export_bsk", "mm_export_ksk",
     "mm_device_init", "mm_table_create", "mm_table_create_general", "mm_table_info", "mm_table_export", "mm_encrypt", "mm_decrypt",
     "mm_bootstrap", "mm_modswitch", "mm_blind_rotate", "mm_external_product", "mm_sample_extract",
-    "mm_keyswitch", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune",
+    "mm_keyswitch", "mm_keyswitch_noalloc", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune",
     "mm_schedule_count", "mm_set_schedule", "mm_schedule_describe", "mm_server_start", "mm_submit", "mm_poll",
     "mm_server_stats", "mm_server_stop", "mm_server_replay",
 ]
@@ -70,6 +70,7 @@ def _load():
         "mm_sample_extract": (i32, [vp, vp, sz, vp, u32, vp]),
         "mm_keyswitch": (i32, [vp, vp, sz, vp, u32, vp]),
         "mm_negacyclic_mul": (i32, [vp, vp, vp, sz, vp, u32, vp]),
+        "mm_keyswitch_noalloc": (i32, [vp, vp, sz, vp, vp]),
         "mm_set_timing": (i32, [vp, i32]),
         "mm_last_timing": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "mm_autotune": (i32, [vp, vp, vp, sz, C.POINTER(i32)]),
@@ -290,6 +291,17 @@ class Context:
         i, o, flags, st = self._io(lwe_N, (cnt, self.params.n + 1), out)
         self._check(lib.mm_keyswitch(self.h, i.ptr, cnt, o.ptr, flags, st))
         return o.arr
+
+    def keyswitch_noalloc(self, lwe_N, out):
+        """mm_keyswitch_noalloc on device tensors (int32 views of the words):
+        lwe_N [count][N+1], out [count][n+1]; asynchronous on torch's current
+        stream."""
+        assert _is_dev(lwe_N) and _is_dev(out), "mm_keyswitch_noalloc takes device buffers"
+        N, W = self.params.N, self.params.n + 1
+        cnt = lwe_N.numel() // (N + 1)
+        i, o = Buf(lwe_N, cnt * (N + 1)), Buf(out, cnt * W)
+        self._check(lib.mm_keyswitch_noalloc(self.h, i.ptr, cnt, o.ptr, _stream()))
+        return out
 
     def negacyclic_mul(self, a, b, out=None):
         N = self.params.N

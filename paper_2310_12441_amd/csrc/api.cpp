@@ -204,6 +204,13 @@ int mm_keyswitch(mm_ctx *ctx, const uint32_t *lwe_N, size_t count, uint32_t *lwe
     return guard(ctx, [&] { mm::run_keyswitch(*ctx, lwe_N, count, lwe_n, flags, stream); });
 }
 
+int mm_keyswitch_noalloc(mm_ctx *ctx, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n, void *stream)
+{
+    if (!ctx || (count && (!lwe_N || !lwe_n))) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->lock);
+    return guard(ctx, [&] { mm::run_keyswitch_noalloc(*ctx, lwe_N, count, lwe_n, stream); });
+}
+
 int mm_negacyclic_mul(mm_ctx *ctx, const uint32_t *a, const uint32_t *b, size_t count, uint32_t *out, uint32_t flags,
                       void *stream)
 {

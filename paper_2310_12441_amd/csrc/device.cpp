@@ -209,6 +209,7 @@ void device_init(mm_ctx &c, int id)
         }
     }
     HIPC(dev::init_kernel_attributes());
+    HIPC(dev::noalloc_scratch_init(id, &d->scratch));
     HIPC(hipStreamCreateWithFlags(&d->own, hipStreamNonBlocking));
     c.dev = std::move(d);
 }
@@ -937,6 +938,25 @@ void run_keyswitch(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe
     enqueue_keyswitch(c, d, din, nullptr, count, dout, nullptr, c.p.Q, ks, part, st);
     HIPC(hipGetLastError());
     finish_out(lwe_n, dout, count * W, dptr, st);
+}
+
+// The key switch with its partial sums in the device's fixed scratch array: no
+// allocation, no staging, no schedule lookup that could upload anything.
+void run_keyswitch_noalloc(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n, void *stream)
+{
+    if (!c.dev) throw Error(MM_ESTATE, "mm_keyswitch_noalloc needs mm_device_init first (it allocates nothing)");
+    const size_t W = c.p.n + 1, per_split = count * W * sizeof(uint64_t);
+    MM_REQUIRE(per_split <= dev::NOALLOC_SCRATCH_BYTES,
+               "mm_keyswitch_noalloc: count * (n + 1) * 8 bytes exceeds its 64 MiB scratch");
+    if (count == 0) return;
+    Device &d = *c.dev;
+    HIPC(hipSetDevice(d.id));
+    MM_REQUIRE(d.scratch != nullptr, "no device scratch");
+    KsSched ks = ks_default(c, d, count);
+    ks.P = (uint32_t)std::max<size_t>(1, std::min<size_t>(ks.P, dev::NOALLOC_SCRATCH_BYTES / per_split));
+    enqueue_keyswitch(c, d, lwe_N, nullptr, count, lwe_n, nullptr, c.p.Q, ks, (uint64_t *)d.scratch,
+                      (hipStream_t)stream);
+    HIPC(hipGetLastError());
 }
 
 void set_timing(mm_ctx &c, bool on)

@@ -53,6 +53,7 @@ struct Device {
     std::vector<Graph> graphs;
     std::map<std::string, int> tuned;  // batch shape -> index into the schedule candidates
     int ws_generation = 0;
+    void *scratch = nullptr;  // this GPU's fixed scratch array (never freed; see noalloc.hip)
     bool timing = false;
     hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // before BR, after BR, after key switch
 

@@ -99,6 +99,12 @@ struct KsArgs {
     uint32_t n, N, Q, log2Bks, l_ks;
 };
 
+// Device scratch of the allocation-free key switch: one array per GPU, held
+// until the process ends; noalloc_scratch_init returns its device address for
+// `device`, which must be the current device (looked up once per device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+hipError_t noalloc_scratch_init(int device, void **out);
+
 hipError_t init_kernel_attributes();
 bool device_supports_n(uint32_t N);  // N in {256, ..., 8192}
 int waves_per_poly(uint32_t N);

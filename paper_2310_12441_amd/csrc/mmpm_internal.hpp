@@ -110,6 +110,7 @@ void run_sample_extract(mm_ctx &c, const uint32_t *rlwe, size_t count, uint32_t 
                         void *stream);
 void run_keyswitch(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n, uint32_t flags,
                    void *stream);
+void run_keyswitch_noalloc(mm_ctx &c, const uint32_t *lwe_N, size_t count, uint32_t *lwe_n, void *stream);
 void run_negacyclic_mul(mm_ctx &c, const uint32_t *a, const uint32_t *b, size_t count, uint32_t *out,
                         uint32_t flags, void *stream);
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count);
