@@ -52,10 +52,14 @@ typedef struct mm_ctx mm_ctx;
 typedef struct mm_server mm_server;
 
 /* Ring and gadget parameters of one key set (Alg. 1 inputs).
- * n: LWE dimension; N: ring degree, a power of two in [64, 8192] (the device
- * path takes 256 ... 8192; above 1024 one polynomial spans N / 1024 waves, and
- * a table's r components must then satisfy r * N / 1024 <= 8, so r = 1 at
- * N = 8192: the TFHE-shaped case of the comparison in Sec. 5); Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l:
+ * n: LWE dimension; N: ring degree, a power of two in [64, 16384] (the device
+ * path takes 256 ... 16384; above 1024 one polynomial spans N / 1024 waves; a
+ * batch whose tables all have r * N / 1024 <= 8 runs the fused persistent
+ * kernel, any other batch, and every batch at N = 16384, the global-
+ * accumulator path: accumulators in device memory, one launch per CMux step,
+ * r up to 1024 -- so the TFHE-shaped rings of the comparison in Sec. 5 reach
+ * N = 16384 and MMPM tables r = 16 and beyond); Q: ring modulus (odd prime,
+ * Q = 1 mod 2N, Q < 2^31); log2_B, l:
  * the blind-rotation gadget base 2^log2_B and length, l * log2_B <= 32 and
  * log2_B <= 15; log2_Bks, l_ks: the key-switch base and length,
  * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact; ternary: 0 for
@@ -84,7 +88,9 @@ typedef struct {
 } mm_params;
 
 /* The random material of a key set, drawn by the caller (host memory, read
- * only during mm_keygen):
+ * only during mm_keygen).  The library takes draws instead of a seed so that it
+ * holds no random generator of its own: a checker builds the same keys from the
+ * same arrays, and the caller picks the generator and its seed.
  *   s      n values in {0,1} (binary) or {-1,0,1} (ternary)   LWE secret
  *   z      N values in {0,1}           RLWE secret
  *   bsk_a  n * K * 2l * N in [0, Q)    RGSW masks, [i][key][row][coeff]
@@ -131,7 +137,7 @@ int mm_export_ksk(const mm_ctx *ctx, uint32_t *out, size_t words);
 int mm_device_init(mm_ctx *ctx, int device);
 
 /* Register a look-up table f: Z_t -> Z_t' held in r polynomials (Sec. 3,
- * Example 2; Alg. 1 input v_test).  Requires t, t' even, t | 2Nr, f nega-cyclic
+ * Example 2; Alg. 1 input v_test), 1 <= r <= 1024.  Requires t, t' even, t | 2Nr, f nega-cyclic
  * (f[m + t/2] = -f[m] mod t', Definition 1) with entries in [0, t').  q_in is
  * the modulus of the ciphertexts bootstrapped with this table (0 selects 2Nr, so
  * the first modulus switch is the identity); 2 <= q_in <= 2^31.  The test vector
@@ -166,7 +172,8 @@ int mm_table_export(const mm_ctx *ctx, int id, uint32_t *V, size_t words);
 int mm_encrypt(const mm_ctx *ctx, uint32_t q, uint32_t t, const uint32_t *m, size_t count,
                const uint32_t *mask, const int32_t *err, uint32_t *ct);
 
-/* m_c = round((b - <a, s> mod q) / floor(q/t)) mod t (ties upward). Host buffers. */
+/* LWE decryption under s (Sec. 2 item (8), the phase of eq. def:phase):
+ * m_c = round((b - <a, s> mod q) / floor(q/t)) mod t (ties upward). Host buffers. */
 int mm_decrypt(const mm_ctx *ctx, uint32_t q, uint32_t t, const uint32_t *ct, size_t count,
                uint32_t *m);
 
@@ -245,9 +252,12 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
 /* ---- autotuning ---- */
 
 /* Time the kernel schedules that fit this batch shape (ciphertexts per
- * workgroup slot packing, key-switch tiling) on the device and remember the
- * fastest for the shape (N, sum of r, count).  mm_bootstrap uses the
- * remembered schedule.  *choice receives the chosen schedule index. */
+ * workgroup slot packing, waves per component, NTT stage schedule, key-switch
+ * kernel and tiling) on the device and remember the fastest for the shape (N,
+ * sum of r, count).  mm_bootstrap uses the remembered schedule.  *choice
+ * receives the chosen schedule index.  A batch on the global-accumulator path
+ * (see mm_params) has one schedule: this call and the mm_schedule_* calls
+ * return MM_EINVAL for it. */
 int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
                 int *choice);
 
@@ -265,9 +275,11 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
  * kernel (0: i split over workgroups, per-thread sums; 1: KSK rows staged in
  * LDS, one output column per lane; 2: KSK rows staged in LDS, one ciphertext
  * per lane) and the NTT stage schedule of the blind rotation (0: every
- * cross-lane exchange through LDS; 1: the exchange across the two highest
- * lane bits by wavefront lane swaps, the others through LDS).  Any output
- * pointer may be NULL. */
+ * cross-lane exchange through LDS, the two polynomials of an NTT in lockstep;
+ * 1: the last exchange between NTT phases by wavefront lane swaps
+ * (v_permlane16/32_swap), the others through LDS; 2: LDS exchanges with the two
+ * polynomials staggered, one's relayout in flight while the other's
+ * butterflies run).  Any output pointer may be NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
                          int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
                          int *ntt_schedule);

@@ -25,6 +25,7 @@ COMMON = [
 ]
 # Packed FP32 instructions stay off in every device object.
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-fconstexpr-steps=20000000",  # the compile-time check of every LDS address of the 16-wave NTT
           "-munsafe-fp-atomics"]
 HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 

@@ -131,8 +131,9 @@ void device_init(mm_ctx &c, int id)
     d->num_cu = prop.multiProcessorCount;
     const mm_params &p = c.p;
     const uint32_t N = p.N, Q = p.Q;
-    MM_REQUIRE(dev::device_supports_n(N), "device path supports N in {256, 512, ..., 8192}");
-    MM_REQUIRE(!c.wide || N <= 4096, "the wide-modulus path supports N in {256, ..., 4096}");
+    MM_REQUIRE(dev::device_supports_n(N) || dev::wide_supports_n(N, 1),
+               "device path supports N in {256, 512, ..., 16384}");
+    MM_REQUIRE(!c.wide || dev::wide_supports_n(N, 2), "the wide-modulus path supports N in {256, ..., 4096}");
     d->qn = neg_inv_2_32(Q);
     // 2^64 / N mod Q, for the pointwise product of two forward NTTs
     d->c_fix = mulmod(to_mont(to_mont(1, Q), Q), c.ntt.n_inv, Q);
@@ -466,6 +467,16 @@ static std::string shape_key(const mm_ctx &c, const int *ids, size_t count)
            std::to_string(max_r(c, ids, count));
 }
 
+// The global-accumulator path (accumulators in device memory, one launch per
+// CMux step): the wide modulus, rings above 8192, and tables whose components
+// do not fit one workgroup (r N / 1024 > 8).
+static bool use_global(const mm_ctx &c, const int *ids, size_t count)
+{
+    return c.wide || !dev::device_supports_n(c.p.N) || max_r(c, ids, count) * (uint32_t)dev::waves_per_poly(c.p.N) > 8;
+}
+
+static int primes_of(const mm_ctx &c) { return c.wide ? 2 : 1; }
+
 // Two waves per component (N = 512, 1024, r <= 4): for batches that do not
 // fill every compute unit, both waves of a slot share one component's work.
 static bool wide_slots_ok(const mm_ctx &c, const int *ids, size_t count)
@@ -509,6 +520,11 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
         for (int gw : {8, 4}) {
             if (gw == 4 && !narrow_ok) continue;
             for (auto &k : ks) out.push_back(Sched{gw, k, 0, 1});
+        }
+    if (dev::waves_per_poly(c.p.N) == 1)
+        for (int gw : {8, 4}) {
+            if (gw == 4 && !narrow_ok) continue;
+            for (auto &k : ks) out.push_back(Sched{gw, k, 0, 2});
         }
     return out;
 }
@@ -607,7 +623,7 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
 static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
                             uint32_t q_out, bool use_graph, hipStream_t st, const Sched *force = nullptr)
 {
-    if (c.wide) {
+    if (use_global(c, ids, count)) {
         bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st);
         return;
     }
@@ -651,15 +667,19 @@ static dev::WideArgs wide_args(const mm_ctx &c, const Device &d)
     dev::WideArgs A{};
     A.ct_stride = p.n + 1;
     A.Q[0] = p.Q;
-    A.Q[1] = p.Q2;
     A.qn[0] = d.qn;
-    A.qn[1] = d.qn2;
     A.log2B = p.log2_B;
     A.l = p.l;
     A.sg = c.sg;
-    A.crt_cq = (p.Q + p.Q2 - 1) / p.Q2 * p.Q2;
-    A.crt_inv = to_mont(powmod(p.Q % p.Q2, p.Q2 - 2, p.Q2), p.Q2);
-    A.Qw = c.Qw;
+    if (c.wide) {
+        A.Q[1] = p.Q2;
+        A.qn[1] = d.qn2;
+        A.crt_cq = (p.Q + p.Q2 - 1) / p.Q2 * p.Q2;
+        A.crt_inv = to_mont(powmod(p.Q % p.Q2, p.Q2 - 2, p.Q2), p.Q2);
+        A.Qw = c.Qw;
+    } else {
+        A.Qw = p.Q;  // one prime: the 31-bit ring modulus itself
+    }
     A.goff = 0;
     for (uint32_t u = 0; u < p.l; u++) A.goff += (uint64_t)(1u << (p.log2_B - 1)) << (u * p.log2_B);
     A.bsk = d.bsk;
@@ -672,8 +692,8 @@ static dev::WideArgs wide_args(const mm_ctx &c, const Device &d)
     return A;
 }
 
-// One task per (ciphertext, component); accumulators of 4N words per component
-// laid out ciphertext after ciphertext.  Returns the total accumulator words.
+// One task per (ciphertext, component); accumulators of 2N words per component
+// and prime laid out ciphertext after ciphertext.  Returns the total words.
 static uint64_t wide_tasks(const mm_ctx &c, const int *ids, size_t count, std::vector<dev::WideTask> &tasks,
                            std::vector<uint64_t> &offs)
 {
@@ -686,7 +706,7 @@ static uint64_t wide_tasks(const mm_ctx &c, const int *ids, size_t count, std::v
         offs[i] = words;
         for (uint32_t j = 0; j < tb.r; j++)
             tasks.push_back({(int32_t)i, j, tb.r, tb.q_in, (uint32_t)tb.dev_offset, 0, words});
-        words += (uint64_t)tb.r * 4 * N;
+        words += (uint64_t)tb.r * 2 * primes_of(c) * N;
     }
     return words;
 }
@@ -713,12 +733,12 @@ static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_
     const uint32_t N = c.p.N;
     uint32_t *buf[2] = {buf0, buf1};
     A.acc_wr = buf[0];
-    dev::launch_wide_init(N, A, num_tasks, s);
+    dev::launch_wide_init(N, primes_of(c), A, num_tasks, s);
     for (uint32_t i = 0; i < steps; i++) {
         A.step = i;
         A.acc_rd = buf[i & 1];
         A.acc_wr = buf[(i + 1) & 1];
-        dev::launch_wide_step(N, c.keys, A, num_tasks, s);
+        dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s);
     }
     return buf[steps & 1];
 }
@@ -753,7 +773,7 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
         [&](hipStream_t s) {
             dev::WideArgs B = A;
             B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s);
-            dev::launch_wide_extract(N, B, doff, count, ext, s);
+            dev::launch_wide_extract(N, primes_of(c), B, doff, count, ext, s);
         },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, ks, part, s); });
 }
@@ -774,7 +794,8 @@ static void blind_rotate_wide(mm_ctx &c, Device &d, const int *ids, const uint32
     A.ct_in = d_in;
     const uint32_t nt = (uint32_t)tasks.size();
     A.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, steps, st);
-    dev::launch_wide_export(c.p.N, A, nt, d_acc, st);
+    if (c.wide) dev::launch_wide_export(c.p.N, A, nt, d_acc, st);
+    else HIPC(hipMemcpyAsync(d_acc, A.acc_rd, words * 4, hipMemcpyDeviceToDevice, st));  // already [comp][part][N]
     HIPC(hipGetLastError());
 }
 
@@ -841,10 +862,11 @@ void run_blind_rotate(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t c
         words += (uint64_t)c.tables[ids[i]].r * 2 * N;
     }
     const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * (c.p.n + 1), dptr, st);
-    if (c.wide) {  // uint64 entries: two words each
-        uint32_t *d_out = stage_out(d, WS_OUT, acc_out, 2 * words, dptr);
+    if (use_global(c, ids, count)) {  // with the wide modulus uint64 entries: two words each
+        const uint64_t out_words = c.wide ? 2 * words : words;
+        uint32_t *d_out = stage_out(d, WS_OUT, acc_out, out_words, dptr);
         blind_rotate_wide(c, d, ids, d_in, count, steps, d_out, st);
-        finish_out(acc_out, d_out, 2 * words, dptr, st);
+        finish_out(acc_out, d_out, out_words, dptr, st);
         return;
     }
     uint32_t *d_acc = stage_out(d, WS_ACC, acc_out, words, dptr);
@@ -865,6 +887,7 @@ void run_external_product(mm_ctx &c, uint32_t i, const uint32_t *in, size_t coun
                           void *stream)
 {
     MM_REQUIRE(!c.wide, "mm_external_product is not available with a wide ring modulus");
+    MM_REQUIRE(dev::device_supports_n(c.p.N), "mm_external_product supports N up to 8192");
     MM_REQUIRE(i < c.p.n * c.keys, "key index must be < K n");
     if (count == 0) return;
     Device &d = ensure_device(c);
@@ -882,6 +905,7 @@ void run_external_product(mm_ctx &c, uint32_t i, const uint32_t *in, size_t coun
 void run_negacyclic_mul(mm_ctx &c, const uint32_t *a, const uint32_t *b, size_t count, uint32_t *out, uint32_t flags,
                         void *stream)
 {
+    MM_REQUIRE(dev::device_supports_n(c.p.N), "mm_negacyclic_mul supports N up to 8192");
     if (count == 0) return;
     Device &d = ensure_device(c);
     hipStream_t st = (hipStream_t)stream;
@@ -984,6 +1008,8 @@ int schedule_count(mm_ctx &c, const int *ids, size_t count)
     MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no schedule calls)");
     MM_REQUIRE(check_ids(c, ids, count) == 0, "schedules are per nega-cyclic table batch");
     MM_REQUIRE(count > 0, "empty batch");
+    MM_REQUIRE(!use_global(c, ids, count),
+               "this batch runs the global-accumulator path (one schedule, no schedule calls)");
     Device &d = ensure_device(c);
     return (int)candidates(c, d, ids, count).size();
 }
@@ -1019,6 +1045,8 @@ int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
     MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no autotuning)");
     MM_REQUIRE(check_ids(c, ids, count) == 0, "autotuning takes nega-cyclic tables");
     MM_REQUIRE(count > 0, "empty batch");
+    MM_REQUIRE(!use_global(c, ids, count),
+               "this batch runs the global-accumulator path (one schedule, no autotuning)");
     Device &d = ensure_device(c);
     const size_t W = c.p.n + 1;
     hipStream_t st = d.own;

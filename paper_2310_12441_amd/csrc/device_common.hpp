@@ -43,8 +43,8 @@ struct Geo {
     __host__ __device__ static constexpr int R(int p) { return LL - p * LE < 0 ? 0 : LL - p * LE; }
     // highest idx bit whose butterflies run in phase p
     __host__ __device__ static constexpr int HI(int p) { return p == 0 ? LOGN - 1 : R(p - 1) - 1; }
-    static_assert(N == LANES * E && E >= 4 && E <= 16 && WPP <= 8,
-                  "device path supports N in {256, 512, ..., 8192}");
+    static_assert(N == LANES * E && E >= 4 && E <= 16 && WPP <= 16,
+                  "device path supports N in {256, 512, ..., 16384}");
 };
 
 // LDS word address of coefficient idx: one pad word per 16 keeps all phase
@@ -255,12 +255,127 @@ __device__ __forceinline__ void lane_swap_45(uint32_t (&x)[NP][E])
 // bit-reversed order out) of NP polys held in phase-0 layout; returns them in
 // the last phase's layout, reduced to [0, Q) (inputs in [0, Q)).
 // twf[k] = psi^bitrev(k) 2^32 mod Q.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false>
+// The butterflies of NTT phase p for one polynomial (forward: Cooley-Tukey,
+// merged psi powers) and, for p > 0, the reduction of the values the previous
+// phase left unreduced that are not multiplicands of this phase's first stage.
+template <int N, int W, bool PL>
+__device__ __forceinline__ void fwd_phase(uint32_t (&x)[(Geo<N, W>::E)], int p, const uint32_t *twf, int L,
+                                          const ModQ &m)
+{
+    using G = Geo<N, W>;
+    const int R = G::R(p);
+    const int Lp = phase_lane<N, W, PL>(p, L);
+    if (p > 0) {
+        const int kt = G::HI(p) - R;
+#pragma unroll
+        for (int k = 0; k < G::E; k++)
+            if (!((k >> kt) & 1)) {
+                uint32_t &v = x[phase_reg<N, W, PL>(p, k)];
+                v = min(v, v - m.Q);
+            }
+    }
+    const int Lhi = (p == 0) ? 0 : (Lp >> R);
+#pragma unroll
+    for (int b = G::HI(p); b >= R; b--) {
+        const int kb = b - R, s = G::LOGN - 1 - b;
+#pragma unroll
+        for (int k0 = 0; k0 < G::E; k0++) {
+            if (k0 & (1 << kb)) continue;
+            const int k1 = k0 | (1 << kb);
+            const uint32_t w = twf[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
+            // Both outputs differ from each other only in bit b, so they agree on bit
+            // b - 1: when that bit is 1 both are multiplicands of the next stage, where
+            // any 32-bit value is a valid Montgomery input (x w < 2^32 Q), and they
+            // stay unreduced in [0, 2Q).  In the last stage of a phase bit b - 1 is a
+            // lane bit, so all outputs stay unreduced and the next phase reduces its
+            // non-multiplicands after the relayout; the last phase ends reduced.
+            const bool lazy = kb > 0 ? ((k0 >> (kb - 1)) & 1) != 0 : p + 1 < G::NPH;
+            const int r0 = phase_reg<N, W, PL>(p, k0), r1 = phase_reg<N, W, PL>(p, k1);
+            const uint32_t u = x[r0];
+            const uint32_t v = mont_mul(x[r1], w, m);
+            if (lazy) {
+                x[r0] = u + v;
+                x[r1] = u - v + m.Q;
+            } else {
+                x[r0] = add_q(u, v, m.Q);
+                x[r1] = sub_q(u, v, m.Q);
+            }
+        }
+    }
+}
+
+// Inverse butterflies (Gentleman-Sande) of phase p for one polynomial.
+template <int N, int W, bool PL>
+__device__ __forceinline__ void inv_phase(uint32_t (&x)[(Geo<N, W>::E)], int p, const uint32_t *twi, int L,
+                                          const ModQ &m)
+{
+    using G = Geo<N, W>;
+    const int R = G::R(p);
+    const int Lp = phase_lane<N, W, PL>(p, L);
+    const int Lhi = (p == 0) ? 0 : (Lp >> R);
+#pragma unroll
+    for (int b = R; b <= G::HI(p); b++) {
+        const int kb = b - R, s = G::LOGN - 1 - b;
+#pragma unroll
+        for (int k0 = 0; k0 < G::E; k0++) {
+            if (k0 & (1 << kb)) continue;
+            const int k1 = k0 | (1 << kb);
+            const uint32_t w = twi[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
+            const int r0 = phase_reg<N, W, PL>(p, k0), r1 = phase_reg<N, W, PL>(p, k1);
+            const uint32_t u = x[r0], v = x[r1];
+            x[r0] = add_q(u, v, m.Q);
+            x[r1] = mont_mul(u - v + m.Q, w, m);
+        }
+    }
+}
+
+// One polynomial's half of a wave-private relayout (one wave per polynomial):
+// the writes of its layout in phase `from`, then the reads of phase `to`.  LDS
+// operations of one wave complete in order, so the reads see the writes; the
+// wave barriers only keep the compiler from reordering them.
+template <int N, int W>
+__device__ __forceinline__ void swap_layout_1(uint32_t (&x)[(Geo<N, W>::E)], uint32_t *slot, int L, int from, int to)
+{
+    using G = Geo<N, W>;
+    static_assert(W == 1, "wave-private relayout");
+    uint32_t *sf = slot + swz_base<N, W>(from, L), *st = slot + swz_base<N, W>(to, L);
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < G::E; k++) sf[swz_off(G::R(from), k)] = x[k];
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < G::E; k++) x[k] = st[swz_off(G::R(to), k)];
+}
+
+// Forward negacyclic NTT (Cooley-Tukey, merged psi powers, natural order in,
+// bit-reversed order out) of NP polys held in phase-0 layout; returns them in
+// the last phase's layout, reduced to [0, Q) (inputs in [0, Q)).
+// twf[k] = psi^bitrev(k) 2^32 mod Q.
+//
+// ST (staggered, one wave per polynomial, NP = 2): the two polynomials take
+// turns so that each one's relayout is in flight while the other one's
+// butterflies run: phase p of poly 0, its writes and the reads of phase p + 1,
+// then phase p of poly 1 and its relayout, then phase p + 1 of poly 0, whose
+// data has arrived meanwhile.  The same instructions as the lockstep order,
+// which waits for every relayout's reads right after issuing them.
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false,
+          bool ST = false>
 __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twf,
                                         int L, const ModQ &m, uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
     static_assert(!PL || pl_ok<N, W>(), "lane-swap exchange needs one wave per polynomial and R = 2 before the last phase");
+    static_assert(!ST || (W == 1 && NP == 2 && !PL && !DS), "staggered relayouts: one wave per polynomial, two polys");
+    if constexpr (ST) {
+#pragma unroll
+        for (int p = 0; p < G::NPH; p++)
+#pragma unroll
+            for (int q = 0; q < NP; q++) {
+                fwd_phase<N, W, false>(x[q], p, twf, L, m);
+                if (p + 1 < G::NPH) swap_layout_1<N, W>(x[q], slot + q * G::POLYW, L, p, p + 1);
+            }
+        return;
+    }
 #pragma unroll
     for (int p = 0; p < G::NPH; p++) {
         const int R = G::R(p);
@@ -280,6 +395,7 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
                         v = min(v, v - m.Q);
                     }
         }
+        // the polys in lockstep, butterfly by butterfly (lazy outputs as in fwd_phase)
         const int Lhi = (p == 0) ? 0 : (Lp >> R);
 #pragma unroll
         for (int b = G::HI(p); b >= R; b--) {
@@ -289,12 +405,6 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
                 if (k0 & (1 << kb)) continue;
                 const int k1 = k0 | (1 << kb);
                 const uint32_t w = twf[(1 << s) + ((Lhi << (G::LE - kb - 1)) | (k0 >> (kb + 1)))];
-                // Both outputs differ from each other only in bit b, so they agree on bit
-                // b - 1: when that bit is 1 both are multiplicands of the next stage, where
-                // any 32-bit value is a valid Montgomery input (x w < 2^32 Q), and they
-                // stay unreduced in [0, 2Q).  In the last stage of a phase bit b - 1 is a
-                // lane bit, so all outputs stay unreduced and the next phase reduces its
-                // non-multiplicands after the relayout; the last phase ends reduced.
                 const bool lazy = kb > 0 ? ((k0 >> (kb - 1)) & 1) != 0 : p + 1 < G::NPH;
                 const int r0 = phase_reg<N, W, PL>(p, k0), r1 = phase_reg<N, W, PL>(p, k1);
 #pragma unroll
@@ -316,18 +426,31 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[NP][(Geo<N, W>::E)], uint3
 
 // Inverse negacyclic NTT (Gentleman-Sande, bit-reversed in, natural out),
 // without the 1/N factor: polys arrive in the last phase's layout and leave in
-// phase-0 layout.  twi[k] = psi^-bitrev(k) 2^32 mod Q.
-template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false>
+// phase-0 layout.  twi[k] = psi^-bitrev(k) 2^32 mod Q.  ST as in ntt_fwd.
+template <int N, int NP, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false,
+          bool ST = false>
 __device__ __forceinline__ void ntt_inv(uint32_t (&x)[NP][(Geo<N, W>::E)], uint32_t *slot, const uint32_t *twi,
                                         int L, const ModQ &m, uint32_t *slot2 = nullptr, int *par = nullptr)
 {
     using G = Geo<N, W>;
     static_assert(!PL || pl_ok<N, W>(), "lane-swap exchange needs one wave per polynomial and R = 2 before the last phase");
+    static_assert(!ST || (W == 1 && NP == 2 && !PL && !DS), "staggered relayouts: one wave per polynomial, two polys");
+    if constexpr (ST) {
+#pragma unroll
+        for (int p = G::NPH - 1; p >= 0; p--)
+#pragma unroll
+            for (int q = 0; q < NP; q++) {
+                inv_phase<N, W, false>(x[q], p, twi, L, m);
+                if (p > 0) swap_layout_1<N, W>(x[q], slot + q * G::POLYW, L, p, p - 1);
+            }
+        return;
+    }
 #pragma unroll
     for (int p = G::NPH - 1; p >= 0; p--) {
         const int R = G::R(p);
         const int Lp = phase_lane<N, W, PL>(p, L);
         const int Lhi = (p == 0) ? 0 : (Lp >> R);
+        // the polys in lockstep, butterfly by butterfly
 #pragma unroll
         for (int b = R; b <= G::HI(p); b++) {
             const int kb = b - R, s = G::LOGN - 1 - b;
@@ -394,7 +517,8 @@ __device__ __forceinline__ uint32_t gadget_field_start(uint32_t x, uint32_t off_
 // (eq. def:gsw).  out stays in the last phase's layout.  With OFF the digits
 // enter shifted by +B/2 (g.off then holds (B/2)(1 + ... + B^(l-1))) and the
 // caller starts out from minus (B/2) sum_rows K.
-template <int N, bool OFF = false, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false>
+template <int N, bool OFF = false, int W = default_wpp(N), bool PRIO = (W == 1), bool DS = false, bool PL = false,
+          bool ST = false>
 __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], const uint32_t (&Db)[(Geo<N, W>::E)],
                                         const uint32_t *__restrict__ K, uint32_t *slot, const uint32_t *twf, int L,
                                         const ModQ &m, const GadgetC &g, uint32_t (&out)[2][(Geo<N, W>::E)],
@@ -428,7 +552,7 @@ __device__ __forceinline__ void ext_mac(const uint32_t (&Da)[(Geo<N, W>::E)], co
                 pd[1][k] = gadget_digit((int32_t)ya[k], u, g, m.Q);
             }
         }
-        ntt_fwd<N, 2, W, PRIO, DS, PL>(pd, slot, twf, L, m, slot2, par);
+        ntt_fwd<N, 2, W, PRIO, DS, PL, ST>(pd, slot, twf, L, m, slot2, par);
         // the lane now holds NTT positions E Lk .. E Lk + E - 1 (Lk its lane in the
         // last phase), position E Lk + v in register phase_reg(last, v)
         const int Lk = phase_lane<N, W, PL>(G::NPH - 1, L);

@@ -92,8 +92,10 @@ struct KsSched {
 
 // A batch schedule: blind-rotation group width (8 or 4 waves), waves per
 // component polynomial (0: the ring's default), key switch, and the NTT stage
-// schedule (0: every cross-lane exchange through LDS; 1: the last exchange by
-// wavefront lane swaps).
+// schedule (0: every cross-lane exchange through LDS, the two polys of an NTT
+// in lockstep; 1: the last exchange by wavefront lane swaps; 2: LDS exchanges
+// with the two polys staggered so that one's relayout overlaps the other's
+// butterflies).
 struct Sched {
     int gw = 8;
     KsSched ks;

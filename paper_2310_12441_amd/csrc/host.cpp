@@ -117,7 +117,7 @@ void NttTables::inverse(uint32_t *a) const
 void validate_params(const mm_params &p)
 {
     MM_REQUIRE(p.n >= 1 && p.n <= 4096, "n must be in [1, 4096]");
-    MM_REQUIRE(p.N >= 64 && p.N <= 8192 && (p.N & (p.N - 1)) == 0, "N must be a power of two in [64, 8192]");
+    MM_REQUIRE(p.N >= 64 && p.N <= 16384 && (p.N & (p.N - 1)) == 0, "N must be a power of two in [64, 16384]");
     MM_REQUIRE(p.Q > 2 && p.Q < (1u << 31), "Q must be below 2^31");
     MM_REQUIRE((p.Q - 1) % (2 * p.N) == 0, "Q must be 1 mod 2N");
     MM_REQUIRE(is_prime(p.Q), "Q must be prime");
@@ -347,7 +347,7 @@ void decrypt(const mm_ctx &c, uint32_t q, uint32_t t, const uint32_t *ct, size_t
 int table_create(mm_ctx &c, uint32_t t, uint32_t t_out, uint32_t r, uint32_t q_in, const uint32_t *f)
 {
     const uint32_t N = c.p.N;
-    MM_REQUIRE(r >= 1 && r <= (c.wide ? 1024u : 8u), c.wide ? "r must be in [1, 1024]" : "r must be in [1, 8]");
+    MM_REQUIRE(r >= 1 && r <= 1024u, "r must be in [1, 1024]");
     const uint64_t M = 2ull * N * r;
     MM_REQUIRE(M <= (1ull << 31), "2Nr must be <= 2^31");
     MM_REQUIRE(t >= 2 && t % 2 == 0 && M % t == 0, "t must be even and divide 2Nr");

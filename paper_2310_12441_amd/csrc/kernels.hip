@@ -80,7 +80,7 @@ struct BrLds {
     static_assert(BUF_WORDS == Geo<N>::SLOTW, "an accumulator buffer doubles as the exchange slot");
 };
 
-template <int N, int GW, int KEYS, int W = default_wpp(N), bool PL = false>
+template <int N, int GW, int KEYS, int W = default_wpp(N), bool PL = false, bool ST = false>
 __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
 {
     using G = Geo<N, W>;
@@ -190,17 +190,17 @@ __global__ void __launch_bounds__(64 * GW, 8 / GW) k_blind_rotate(BrArgs A)
                     o[0][k] = C0[v];
                     o[1][k] = C0[N + v];
                 }
-                ext_mac<N, true, W, (W == 1), DS, PL>(D[0], D[1], K, nxt, A.twf, L, m, g, o, slot2, &par);
+                ext_mac<N, true, W, (W == 1), DS, PL, ST>(D[0], D[1], K, nxt, A.twf, L, m, g, o, slot2, &par);
             }
             if (KEYS == 2) {
                 if (active) rotated_diff(ai, accl, D);  // +a'_i from the same accumulator
                 if (run)
-                    ext_mac<N, true, W, (W == 1), DS, PL>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o, slot2,
-                                                          &par);
+                    ext_mac<N, true, W, (W == 1), DS, PL, ST>(D[0], D[1], K + 4u * A.l * N, nxt, A.twf, L, m, g, o,
+                                                              slot2, &par);
             }
             if (run) {
                 __asm__ volatile("" ::: "memory");
-                ntt_inv<N, 2, W, (W == 1), DS, PL>(o, nxt, A.twi, L, m, slot2, &par);
+                ntt_inv<N, 2, W, (W == 1), DS, PL, ST>(o, nxt, A.twi, L, m, slot2, &par);
             }
             if (WPP > 1) __syncthreads();  // every lane of the slot has left the exchange slot
             if (active) {
@@ -662,10 +662,10 @@ void launch_lwe_combine(const uint32_t *ct, const uint32_t *tmp, uint32_t *out, 
 // wave: lower latency for batches too small to fill the chip).
 constexpr bool br_wide_slots(int N) { return N == 512 || N == 1024; }
 
-template <int N, int GW, int KEYS, int W = default_wpp(N), bool PL = false>
+template <int N, int GW, int KEYS, int W = default_wpp(N), bool PL = false, bool ST = false>
 static hipError_t br_attr_n()
 {
-    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS, W, PL>,
+    return hipFuncSetAttribute((const void *)k_blind_rotate<N, GW, KEYS, W, PL, ST>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(N, GW, W));
 }
 
@@ -696,6 +696,12 @@ static hipError_t br_attr_all()
         if (e == hipSuccess) e = br_attr_n<N, 8, 2, 1, true>();
         if (e == hipSuccess) e = br_attr_n<N, 4, 1, 1, true>();
         if (e == hipSuccess) e = br_attr_n<N, 4, 2, 1, true>();
+    }
+    if constexpr (Geo<N>::WPP == 1) {
+        if (e == hipSuccess) e = br_attr_n<N, 8, 1, 1, false, true>();
+        if (e == hipSuccess) e = br_attr_n<N, 8, 2, 1, false, true>();
+        if (e == hipSuccess) e = br_attr_n<N, 4, 1, 1, false, true>();
+        if (e == hipSuccess) e = br_attr_n<N, 4, 2, 1, false, true>();
     }
     return e;
 }
@@ -740,6 +746,17 @@ int waves_per_poly(uint32_t N) { return N > 1024 ? (int)(N / 1024) : 1; }
 template <int N, int KEYS>
 static void launch_br_nk(const BrArgs &A, int gw, int grid, hipStream_t st, int wpp, int ntt)
 {
+    if constexpr (Geo<N>::WPP == 1) {
+        if (ntt == 2 && (wpp == 0 || wpp == 1)) {
+            if (gw == 4)
+                hipLaunchKernelGGL((k_blind_rotate<N, 4, KEYS, 1, false, true>), dim3(grid), dim3(256),
+                                   br_lds_bytes(N, 4), st, A);
+            else
+                hipLaunchKernelGGL((k_blind_rotate<N, 8, KEYS, 1, false, true>), dim3(grid), dim3(512),
+                                   br_lds_bytes(N, 8), st, A);
+            return;
+        }
+    }
     if constexpr (br_lane_swap<N>()) {
         if (ntt == 1 && (wpp == 0 || wpp == 1)) {
             if (gw == 4)

@@ -114,9 +114,9 @@ void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows
                          hipStream_t st);
 // wpp: waves per polynomial (0: one up to N = 1024, N / 1024 above; 2 is also
 // available at N = 512 and 1024, see br_supports_wpp).
-// ntt: the NTT stage schedule, 0 (every exchange through LDS) or 1 (the last
-// exchange by wavefront lane swaps; where br_supports_lane_swap(N), one wave per
-// polynomial).
+// ntt: the NTT stage schedule, 0 (every exchange through LDS), 1 (the last
+// exchange by wavefront lane swaps; where br_supports_lane_swap(N)) or 2 (LDS
+// exchanges, the two polys of an NTT staggered; one wave per polynomial).
 void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp = 0, int ntt = 0);
 bool br_supports_wpp(uint32_t N, int wpp);
 bool br_supports_lane_swap(uint32_t N);
@@ -124,11 +124,15 @@ bool br_supports_lane_swap(uint32_t N);
 // A.acc_rd into A.acc_wr; extraction of component 0 switched to Q[0]
 // (ext[c] from the component at acc_off[c]); the accumulator as uint64 values
 // [component][part][N] at the same word offsets.
-void launch_wide_init(uint32_t N, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
-void launch_wide_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
-void launch_wide_extract(uint32_t N, const WideArgs &A, const uint64_t *acc_off, size_t count, uint32_t *ext,
-                         hipStream_t st);
+// npr: primes of the ring modulus (2: the wide modulus Q Q2, N <= 4096; 1: the
+// global-accumulator path of the 31-bit modulus, N <= 16384); with one prime the
+// accumulator is already in the output layout [component][part][N] (no export).
+void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
+void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
+void launch_wide_extract(uint32_t N, int npr, const WideArgs &A, const uint64_t *acc_off, size_t count,
+                         uint32_t *ext, hipStream_t st);
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st);
+bool wide_supports_n(uint32_t N, int npr);
 size_t br_lds_bytes(uint32_t N, int gw, int wpp = 0);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
                              const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,

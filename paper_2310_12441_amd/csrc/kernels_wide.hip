@@ -17,9 +17,17 @@
 //   4. writes ACC_j + D x BSK_i into the other buffer.
 // A ternary secret adds the second term of Alg. 1 (Phi(+a'_i), BSK_i^-) from
 // the same ACC before step 3's inverse NTT.
+//
+// The same kernels, instantiated for one prime (NPR = 1), are the global-
+// accumulator path of the default 31-bit ring modulus: for tables whose r
+// components do not fit one workgroup's LDS (r N / 1024 > 8, e.g. r = 16 at
+// N = 1024) and for rings of degree 16384 (one polynomial over 16 waves), which
+// the fused persistent kernel cannot hold.  Layouts are the wide ones with the
+// prime index dropped: a component is [part][N], key blocks [n][keys][2l][2][N].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -61,7 +69,7 @@ __device__ __forceinline__ uint32_t wide_rot_load(const uint32_t *p, uint32_t id
     return (flip && v) ? Q - v : v;
 }
 
-template <int N>
+template <int N, int NPR>
 __global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
 {
     const WideTask T = A.tasks[blockIdx.x];
@@ -69,13 +77,13 @@ __global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
     const uint32_t *ct = A.ct_in + (size_t)T.ct * A.ct_stride;
     const uint32_t b = wide_modswitch(ct[A.ct_stride - 1], T.q_in, M);
     const WideRow w = wide_row(b, T.r, T.comp, N);
-    uint32_t *acc = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
+    uint32_t *acc = A.acc_wr + T.acc_off + (size_t)T.comp * 2 * NPR * N;
     for (uint32_t idx = threadIdx.x; idx < (uint32_t)N; idx += blockDim.x) {
 #pragma unroll
-        for (int pr = 0; pr < 2; pr++) {
-            const uint32_t *v = A.tv + T.tv_off + ((size_t)w.src * 2 + pr) * N;
-            acc[pr * N + idx] = 0;                                          // part a
-            acc[2 * N + pr * N + idx] = wide_rot_load(v, idx, w, N, A.Q[pr]);  // part b
+        for (int pr = 0; pr < NPR; pr++) {
+            const uint32_t *v = A.tv + T.tv_off + ((size_t)w.src * NPR + pr) * N;
+            acc[pr * N + idx] = 0;                                              // part a
+            acc[NPR * N + pr * N + idx] = wide_rot_load(v, idx, w, N, A.Q[pr]);  // part b
         }
     }
 }
@@ -86,13 +94,21 @@ __global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
 // steps: 982 ms with 16 coefficients per lane and 2 waves per SIMD, 904 ms with
 // 8 and 2, 794 ms with 8 and 3 (735 ms once relayouts addressed LDS from one base
 // per side), 810 ms with 8 and 4 (spills).
-constexpr int wide_wpp(int N) { return N > 512 ? N / 512 : 1; }
+// At N >= 8192 (one prime only) 16 coefficients per lane: N / 1024 waves, 16
+// at N = 16384, the most one workgroup holds.
+constexpr int wide_wpp(int N) { return N > 4096 ? N / 1024 : (N > 512 ? N / 512 : 1); }
 
-template <int N, int KEYS, int W = wide_wpp(N)>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_wide_step(WideArgs A)
+// Waves per EU the compiler is asked to leave room for: three (measured best at
+// N = 2048), or what a workgroup of 16 waves leaves anyway.
+constexpr int wide_min_waves(int W) { return W >= 16 ? 4 : 3; }
+
+template <int N, int KEYS, int NPR, int W = wide_wpp(N)>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min_waves(W)))) void k_wide_step(WideArgs A)
 {
     using G = Geo<N, W>;
     constexpr int E = G::E;
+    // digit fields: l log2 B bits fit 32 with one prime (31-bit Q), up to 62 with two
+    using Y = typename std::conditional<NPR == 1, uint32_t, uint64_t>::type;
     // a ternary secret keeps the first key's digit fields in LDS (each lane reads
     // back only its own), so each key's fields are formed once per step
     // (one array for both, so no alignment gap: three workgroups per CU at N = 2048)
@@ -103,8 +119,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     constexpr bool PRIO = W == 1 || KEYS == 2;
     // a binary secret leaves LDS to spare: a second exchange slot, so that
     // consecutive relayouts alternate and each needs one workgroup barrier, not two
-    // (a third of the LDS a ternary workgroup needs, so occupancy is unchanged)
-    constexpr bool DS = KEYS == 1 && W > 1;
+    // (a third of the LDS a ternary workgroup needs, so occupancy is unchanged);
+    // not at N = 16384, where one slot takes 136 KB
+    constexpr bool DS = KEYS == 1 && W > 1 && 2 * G::SLOTW * 4 <= 160 * 1024;
     __shared__ uint64_t lds64[G::SLOTW / 2 + (Y_LDS ? 2 * N : 0) + (DS ? G::SLOTW / 2 : 0)];
     uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64);
     uint64_t *const ylds = lds64 + G::SLOTW / 2;
@@ -116,36 +133,43 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const uint32_t am = wide_modswitch(A.ct_in[(size_t)T.ct * A.ct_stride + A.step], T.q_in, M);
     // per-prime constants by selection (no private arrays: those would be placed in LDS)
     auto mod = [&](int pr) { return ModQ{pr ? A.Q[1] : A.Q[0], pr ? A.qn[1] : A.qn[0]}; };
-    const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * 4 * N;
+    constexpr size_t CW = (size_t)2 * NPR * N, PW = (size_t)NPR * N;  // words per component, per part
+    const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * CW;
 
     // y'' = round(centred(D) / 2^sg) + goff per coefficient of parts a (0) and b
-    // (1), D = Phi(c) ACC_j - ACC_j joined from its two residues
+    // (1), D = Phi(c) ACC_j - ACC_j (joined from its two residues with two primes)
     const uint64_t half = (A.Qw - 1) / 2;
-    uint64_t y[2][E];
+    Y y[2][E];
     auto digit_fields = [&](int key) {
         const uint32_t c = key == 0 ? (M - am) % M : am;
         const WideRow w = wide_row(c, T.r, T.comp, N);
-        const uint32_t *src = A.acc_rd + T.acc_off + (size_t)w.src * 4 * N;
+        const uint32_t *src = A.acc_rd + T.acc_off + (size_t)w.src * CW;
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
             for (int k = 0; k < E; k++) {
                 const uint32_t idx = G::LANES * k + L;
-                const uint32_t *o = own + part * 2 * N, *s = src + part * 2 * N;
+                const uint32_t *o = own + part * PW, *s = src + part * PW;
                 const uint32_t d0 = sub_q(wide_rot_load(s, idx, w, N, A.Q[0]), o[idx], A.Q[0]);
-                const uint32_t d1 = sub_q(wide_rot_load(s + N, idx, w, N, A.Q[1]), o[N + idx], A.Q[1]);
-                // x = d0 + Q0 ((d1 - d0) Q0^-1 mod Q1), in [0, Q0 Q1)
-                const uint32_t kk = mont_mul(d1 + A.crt_cq - d0, A.crt_inv, mod(1));
-                const uint64_t x = d0 + (uint64_t)A.Q[0] * kk;
-                int64_t xc = x > half ? (int64_t)(x - A.Qw) : (int64_t)x;
-                if (A.sg) xc = (xc + (1ll << (A.sg - 1))) >> A.sg;
-                y[part][k] = (uint64_t)xc + A.goff;
+                if constexpr (NPR == 1) {
+                    int32_t xc = d0 > (uint32_t)half ? (int32_t)(d0 - A.Q[0]) : (int32_t)d0;
+                    if (A.sg) xc = (xc + (1 << (A.sg - 1))) >> A.sg;
+                    y[part][k] = (uint32_t)xc + (uint32_t)A.goff;
+                } else {
+                    const uint32_t d1 = sub_q(wide_rot_load(s + N, idx, w, N, A.Q[1]), o[N + idx], A.Q[1]);
+                    // x = d0 + Q0 ((d1 - d0) Q0^-1 mod Q1), in [0, Q0 Q1)
+                    const uint32_t kk = mont_mul(d1 + A.crt_cq - d0, A.crt_inv, mod(1));
+                    const uint64_t x = d0 + (uint64_t)A.Q[0] * kk;
+                    int64_t xc = x > half ? (int64_t)(x - A.Qw) : (int64_t)x;
+                    if (A.sg) xc = (xc + (1ll << (A.sg - 1))) >> A.sg;
+                    y[part][k] = (uint64_t)xc + A.goff;
+                }
             }
     };
-    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * 4 * N;
+    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * CW;
     // NTT-domain output of one prime from the digit-offset correction
     auto start = [&](int pr, uint32_t (&out)[2][E]) {
-        const uint32_t *corr = A.bsk_corr + ((size_t)A.step * 2 + pr) * 2 * N + L * E;
+        const uint32_t *corr = A.bsk_corr + ((size_t)A.step * NPR + pr) * 2 * N + L * E;
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
@@ -153,16 +177,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     };
     // out += the digits of y times BSK_{i,key} for one prime (eq. def:gsw)
     auto mac = [&](int pr, int key, uint32_t (&out)[2][E], bool from_lds = false) {
-        const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * 2 + pr) * (2 * A.l * 2 * N);
+        const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * NPR + pr) * (2 * A.l * 2 * N);
         for (uint32_t u = 0; u < A.l; u++) {
             __asm__ volatile("" ::: "memory");
             const uint32_t sh = u * A.log2B;
-            const uint64_t mask = u + 1 == A.l ? ~0ull : (1ull << A.log2B) - 1;
+            const Y mask = u + 1 == A.l ? ~(Y)0 : (Y)(((Y)1 << A.log2B) - 1);
             uint32_t pd[2][E];
 #pragma unroll
             for (int k = 0; k < E; k++) {
-                const uint64_t ya = from_lds ? ylds[k * G::LANES + L] : y[0][k];
-                const uint64_t yb = from_lds ? ylds[(E + k) * G::LANES + L] : y[1][k];
+                const Y ya = from_lds ? (Y)ylds[k * G::LANES + L] : y[0][k];
+                const Y yb = from_lds ? (Y)ylds[(E + k) * G::LANES + L] : y[1][k];
                 pd[0][k] = (uint32_t)((yb >> sh) & mask);  // digit of b meets rows u
                 pd[1][k] = (uint32_t)((ya >> sh) & mask);  // digit of a meets rows l + u
             }
@@ -189,7 +213,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
 #pragma unroll
             for (int k = 0; k < E; k++) {
                 const uint32_t idx = G::LANES * k + L;
-                const size_t at = (size_t)part * 2 * N + pr * N + idx;
+                const size_t at = (size_t)part * PW + pr * N + idx;
                 wr[at] = add_q(out[part][k], own[at], mod(pr).Q);
             }
     };
@@ -197,7 +221,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         // one prime at a time: only one prime's outputs are live
         digit_fields(0);
 #pragma unroll
-        for (int pr = 0; pr < 2; pr++) {
+        for (int pr = 0; pr < NPR; pr++) {
             uint32_t out[2][E];
             start(pr, out);
             mac(pr, 0, out);
@@ -212,7 +236,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             for (int k = 0; k < E; k++) ylds[(part * E + k) * G::LANES + L] = y[part][k];
         digit_fields(1);
 #pragma unroll
-        for (int pr = 0; pr < 2; pr++) {
+        for (int pr = 0; pr < NPR; pr++) {
             uint32_t out[2][E];
             start(pr, out);
             mac(pr, 1, out);
@@ -223,7 +247,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         // one prime at a time as well; each key's digit fields are formed again
         // for the second prime (cheaper than keeping both primes' outputs live)
 #pragma unroll
-        for (int pr = 0; pr < 2; pr++) {
+        for (int pr = 0; pr < NPR; pr++) {
             uint32_t out[2][E];
             start(pr, out);
             for (int key = 0; key < 2; key++) {
@@ -241,30 +265,39 @@ __device__ __forceinline__ uint64_t wide_join(uint32_t d0, uint32_t d1, const Wi
     return d0 + (uint64_t)A.Q[0] * mont_mul(d1 + A.crt_cq - d0, A.crt_inv, m1);
 }
 
-// Extraction of component 0 (eq. equ-sam-extr), then round(x Q0 / Q_w) =
-// floor((2 x + Q1) / (2 Q1)) mod Q0 for each coefficient.
-template <int N>
+// Extraction of component 0 (eq. equ-sam-extr); with two primes then
+// round(x Q0 / Q_w) = floor((2 x + Q1) / (2 Q1)) mod Q0 for each coefficient.
+template <int N, int NPR>
 __global__ __launch_bounds__(256) void k_wide_extract(WideArgs A, const uint64_t *__restrict__ acc_off,
                                                       uint32_t *__restrict__ ext)
 {
     const uint32_t *acc = A.acc_rd + acc_off[blockIdx.x];
     uint32_t *o = ext + (size_t)blockIdx.x * (N + 1);
-    const uint64_t den = 2ull * A.Q[1];
     for (uint32_t k = threadIdx.x; k <= (uint32_t)N; k += blockDim.x) {
-        uint64_t x;
-        if (k == N) {
-            x = wide_join(acc[2 * N], acc[3 * N], A);  // b_0
+        if constexpr (NPR == 1) {
+            uint32_t v;
+            if (k == N) v = acc[N];  // b_0
+            else if (k == 0) v = acc[0];
+            else v = acc[N - k] ? A.Q[0] - acc[N - k] : 0u;  // -a_{N-k}
+            o[k] = v;
         } else {
-            const uint32_t src = k ? N - k : 0;
-            x = wide_join(acc[src], acc[N + src], A);
-            if (k && x) x = A.Qw - x;                  // -a_{N-k}
+            const uint64_t den = 2ull * A.Q[1];
+            uint64_t x;
+            if (k == N) {
+                x = wide_join(acc[2 * N], acc[3 * N], A);  // b_0
+            } else {
+                const uint32_t src = k ? N - k : 0;
+                x = wide_join(acc[src], acc[N + src], A);
+                if (k && x) x = A.Qw - x;  // -a_{N-k}
+            }
+            o[k] = (uint32_t)(((2 * x + A.Q[1]) / den) % A.Q[0]);
         }
-        o[k] = (uint32_t)(((2 * x + A.Q[1]) / den) % A.Q[0]);
     }
 }
 
 // The accumulator as uint64 values: component j of a task -> [part][N] at the
-// same word offset (a component is 4N words in both layouts).
+// same word offset (a component is 4N words in both layouts).  One prime needs
+// no such kernel: its accumulator layout is the output layout.
 template <int N>
 __global__ __launch_bounds__(256) void k_wide_export(WideArgs A, uint32_t *__restrict__ out)
 {
@@ -281,48 +314,68 @@ __global__ __launch_bounds__(256) void k_wide_export(WideArgs A, uint32_t *__res
 
 // ------------------------------------------------------------------ launchers
 
-#define WIDE_DISPATCH(N_, CALL)             \
-    switch (N_) {                           \
-    case 256: CALL(256); break;             \
-    case 512: CALL(512); break;             \
-    case 1024: CALL(1024); break;           \
-    case 2048: CALL(2048); break;           \
-    case 4096: CALL(4096); break;           \
-    default: break;                         \
+// Two primes: N <= 4096 (the second prime is 1 mod 2^13); one prime: up to 16384.
+#define WIDE_DISPATCH(N_, NPR_, CALL)                 \
+    if (NPR_ == 2) {                                  \
+        switch (N_) {                                 \
+        case 256: CALL(256, 2); break;                \
+        case 512: CALL(512, 2); break;                \
+        case 1024: CALL(1024, 2); break;              \
+        case 2048: CALL(2048, 2); break;              \
+        case 4096: CALL(4096, 2); break;              \
+        default: break;                               \
+        }                                             \
+    } else {                                          \
+        switch (N_) {                                 \
+        case 256: CALL(256, 1); break;                \
+        case 512: CALL(512, 1); break;                \
+        case 1024: CALL(1024, 1); break;              \
+        case 2048: CALL(2048, 1); break;              \
+        case 4096: CALL(4096, 1); break;              \
+        case 8192: CALL(8192, 1); break;              \
+        case 16384: CALL(16384, 1); break;            \
+        default: break;                               \
+        }                                             \
     }
 
-void launch_wide_init(uint32_t N, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
+void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
 {
-#define C_(n) hipLaunchKernelGGL(k_wide_init<n>, dim3(num_tasks), dim3(256), 0, st, A)
-    WIDE_DISPATCH(N, C_)
+#define C_(n, p) hipLaunchKernelGGL((k_wide_init<n, p>), dim3(num_tasks), dim3(256), 0, st, A)
+    WIDE_DISPATCH(N, npr, C_)
 #undef C_
 }
 
-void launch_wide_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
+void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
 {
-#define C_(n)                                                                                              \
-    if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A); \
-    else hipLaunchKernelGGL((k_wide_step<n, 1>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A)
-    WIDE_DISPATCH(N, C_)
+#define C_(n, p)                                                                                                   \
+    if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2, p>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A); \
+    else hipLaunchKernelGGL((k_wide_step<n, 1, p>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A)
+    WIDE_DISPATCH(N, npr, C_)
 #undef C_
 }
 
-void launch_wide_extract(uint32_t N, const WideArgs &A, const uint64_t *acc_off, size_t count, uint32_t *ext,
-                         hipStream_t st)
+void launch_wide_extract(uint32_t N, int npr, const WideArgs &A, const uint64_t *acc_off, size_t count,
+                         uint32_t *ext, hipStream_t st)
 {
-#define C_(n) hipLaunchKernelGGL(k_wide_extract<n>, dim3((uint32_t)count), dim3(256), 0, st, A, acc_off, ext)
-    WIDE_DISPATCH(N, C_)
+#define C_(n, p) hipLaunchKernelGGL((k_wide_extract<n, p>), dim3((uint32_t)count), dim3(256), 0, st, A, acc_off, ext)
+    WIDE_DISPATCH(N, npr, C_)
 #undef C_
 }
 
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st)
 {
-#define C_(n) hipLaunchKernelGGL(k_wide_export<n>, dim3(num_tasks), dim3(256), 0, st, A, out)
-    WIDE_DISPATCH(N, C_)
+#define C_(n, p) hipLaunchKernelGGL(k_wide_export<n>, dim3(num_tasks), dim3(256), 0, st, A, out)
+    WIDE_DISPATCH(N, 2, C_)
 #undef C_
 }
 
 #undef WIDE_DISPATCH
+
+bool wide_supports_n(uint32_t N, int npr)
+{
+    if (N < 256 || N > (npr == 2 ? 4096u : 16384u)) return false;
+    return (N & (N - 1)) == 0;
+}
 
 }  // namespace dev
 }  // namespace mm

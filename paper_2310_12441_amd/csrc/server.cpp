@@ -190,6 +190,7 @@ Server::~Server()
 Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
 {
     MM_REQUIRE(!c.wide, "the server takes the default ring modulus (Q2 = 0)");
+    MM_REQUIRE(dev::device_supports_n(c.p.N), "the server takes rings of degree up to 8192");
     MM_REQUIRE(chunk >= 1 && chunk <= c.p.n, "chunk_steps must be in [1, n]");
     Device &d = ensure_device(c);
     const size_t N = c.p.N, W = c.p.n + 1;

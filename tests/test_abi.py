@@ -91,7 +91,8 @@ def test_error_paths():
     with pytest.raises(b.MMError):
         ctx.table_create(12, 16, 2, negacyclic_table(12, 16, 1))  # 12 does not divide 2Nr = 1024
     with pytest.raises(b.MMError):
-        ctx.table_create(16, 16, 9, f)  # r > 8
+        ctx.table_create(16, 16, 1025, f)  # r > 1024
+    assert ctx.table_create(16, 16, 9, f) >= 0  # r = 9 runs the global-accumulator path
     bad = dict(dr)
     bad["s"] = dr["s"] + 2
     with pytest.raises(b.MMError):
@@ -143,11 +144,16 @@ def test_keygen_and_test_vector_match_oracle_large_ring(N):
 
 def test_ring_degree_limits():
     b = _binding()
-    for N in (32, 16384):
+    for N in (32, 32768):
         p = Params(n=4, N=N)
         with pytest.raises(b.MMError) as e:
             b.Context(p, key_draws(p, 1))
         assert e.value.code == b.MM_EINVAL
+    # 16384 is the largest ring (the global-accumulator path, one polynomial over 16 waves)
+    p = Params(n=2, N=16384)
+    dr = key_draws(p, 1)
+    ctx = b.Context(p, dr)
+    np.testing.assert_array_equal(ctx.export_bsk(), oracle.keygen_bsk(p, dr))
 
 
 @pytest.mark.parametrize("N,ternary", [(256, False), (2048, True)])

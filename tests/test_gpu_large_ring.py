@@ -1,5 +1,6 @@
 """GPU parity at ring degrees above 1024, where one polynomial spans several
-waves (N / 1024 of them) and the NTT relayouts synchronise the workgroup.
+waves (N / 1024 of them) and the NTT relayouts synchronise the workgroup, and
+on the global-accumulator path (components beyond one workgroup, N = 16384).
 
 N = 2048, 4096, 8192 with r = 1 is the TFHE-shaped comparison point of
 Sec. 5 (one ring of degree N r instead of r components of degree N); MMPM
@@ -219,14 +220,80 @@ def test_bootstrap_mmpm_r2_at_4096_and_schedules():
     np.testing.assert_array_equal(ref[:2], want)
 
 
-def test_r_too_wide_for_a_workgroup_is_rejected():
+def test_r_too_wide_for_a_workgroup_runs_the_global_path():
+    """r = 4 at N = 4096 needs 16 waves, more than one fused workgroup holds: the
+    batch (with an r = 1 ciphertext beside it) runs the global-accumulator path,
+    accumulators in device memory and one launch per CMux step, bit-exact."""
     b = _gpu()
-    c = case(4096)
-    tid, f, V = c.table(64, 64, 4, 81)  # r = 4 at N = 4096 needs 16 waves
-    ct = c.encrypt(2 * 4096 * 4, 64, messages(64, 1, 82), 83)
+    c = case(4096, n=6)
+    tid, f, V = c.table(64, 64, 4, 81)
+    tid1, f1, V1 = c.table(64, 64, 1, 84)
+    ct = c.encrypt(2 * 4096 * 4, 64, messages(64, 2, 82), 83)
+    ct1 = c.encrypt(2 * 4096, 64, messages(64, 1, 85), 86)
+    cts = np.concatenate([ct, ct1])
+    ids = [tid, tid, tid1]
+    say("global path N=4096 r=4 + r=1: 3 steps")
+    got = c.ctx.blind_rotate(ids, cts, 3)
+    size4 = 4 * 2 * 4096
+    for j in range(2):
+        np.testing.assert_array_equal(got[j * size4:(j + 1) * size4].reshape(4, 2, 4096),
+                                      oracle.blind_rotate(c.p, 4, c.keys.bsk, V, ct[j], 3), err_msg=f"ct {j}")
+    np.testing.assert_array_equal(got[2 * size4:].reshape(1, 2, 4096),
+                                  oracle.blind_rotate(c.p, 1, c.keys.bsk, V1, ct1[0], 3))
+    out = c.ctx.bootstrap(ids, cts)
+    np.testing.assert_array_equal(c.ctx.bootstrap(ids, cts, plain=True), out)
+    q = 2 * 4096 * 4
+    np.testing.assert_array_equal(out[:2], oracle.bootstrap_many(c.p, 4, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    np.testing.assert_array_equal(out[2:], oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V1, 2 * 4096,
+                                                                 2 * 4096, ct1))
     with pytest.raises(b.MMError) as e:
-        c.ctx.bootstrap([tid], ct)
+        c.ctx.schedule_count(ids)  # one schedule on this path
     assert e.value.code == b.MM_EINVAL
+
+
+@pytest.mark.parametrize("ternary,r", [(False, 16), (True, 12)])
+def test_mmpm_more_components_than_a_workgroup(ternary, r):
+    """MMPM with r = 16 at N = 1024 (the t = 2^15 class: 2Nr = t) and, ternary,
+    r = 12: more components than the 8 slots of a fused workgroup, through the
+    global-accumulator path; whole bootstraps against the oracle."""
+    from dataclasses import replace
+    p = replace(Params(n=8, N=1024, log2_B=7, l=4), ternary=ternary)
+    c = Case(p, 970 + r)
+    t = 2 * 1024 * r if not ternary else 1024 * r // 2  # 2Nr / t = 1 or 4
+    tid, f, V = c.table(t, t, r, 99)
+    q = 2 * 1024 * r
+    ct = c.encrypt(q, t, messages(t, 3, 100), 101)
+    say("global path N=1024 r", r, "ternary", ternary)
+    got = c.ctx.bootstrap([tid] * 3, ct)
+    np.testing.assert_array_equal(got, oracle.bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    got2 = c.ctx.blind_rotate([tid], ct[:1], 2)
+    np.testing.assert_array_equal(got2.reshape(r, 2, 1024), oracle.blind_rotate(c.p, r, c.keys.bsk, V, ct[0], 2))
+    c.ctx.close()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_bootstrap_16384(plain):
+    """N = 16384, r = 1, t = 2^15 (the TFHE-shaped point for t = 2^15): one
+    polynomial over 16 waves on the global-accumulator path; the accumulator
+    after 2 steps and whole bootstraps (at q and at Q) against the oracle."""
+    b = _gpu()
+    c = case(16384, n=4)
+    t = 32768
+    tid, f, V = c.table(t, t, 1, 111)
+    q = 2 * 16384
+    ct = c.encrypt(q, t, messages(t, 2, 112), 113)
+    say("N=16384 plain", plain)
+    if not plain:
+        got = c.ctx.blind_rotate([tid] * 2, ct, 2)
+        for j in range(2):
+            np.testing.assert_array_equal(got[j * 2 * 16384:(j + 1) * 2 * 16384].reshape(1, 2, 16384),
+                                          oracle.blind_rotate(c.p, 1, c.keys.bsk, V, ct[j], 2), err_msg=f"ct {j}")
+        with pytest.raises(b.MMError):
+            c.ctx.server_start(64 << 20)
+    out = c.ctx.bootstrap([tid] * 2, ct, plain=plain)
+    np.testing.assert_array_equal(out, oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    np.testing.assert_array_equal(c.ctx.bootstrap([tid] * 2, ct, q_out=Q, plain=plain),
+                                  oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, Q, ct))
 
 
 def test_serving_at_2048_matches_alone():

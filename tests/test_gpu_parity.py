@@ -339,6 +339,8 @@ def test_every_schedule_gives_the_same_bits(paper):
     # both LDS-staged key switches
     assert {paper.ctx.schedule_describe(ids, k)[3] for k in range(n)} == {1, 2}
     assert {paper.ctx.schedule_describe(ids, k)[4] for k in range(n)} == {1, 2}
+    # the three NTT stage schedules (LDS lockstep, lane swaps, staggered LDS)
+    assert {paper.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2}
     ref = None
     for choice in range(n):
         paper.ctx.set_schedule(ids, choice)
@@ -414,6 +416,24 @@ def test_ternary_tiny_all_messages(tiny_ternary, plain):
     want = oracle.bootstrap_many(case.p, 2, case.keys.bsk, case.keys.ksk, V, q, q, ct)
     np.testing.assert_array_equal(got, want)
     np.testing.assert_array_equal(oracle.decrypt(case.p.n, q, 16, case.keys.s, got), f[m])
+
+
+def test_ternary_every_schedule():
+    """Ternary secret at the paper-shaped ring (N = 1024, n = 10, r = 4): every
+    candidate schedule -- group widths, two-wave slots, the three NTT stage
+    schedules, key-switch kernels -- gives the oracle's bits."""
+    from dataclasses import replace
+    case = Case(replace(PRESETS["paper_shaped"]["params"], n=10, ternary=True), 15)
+    tid, f, V = case.table(4096, 4096, 4, 25)
+    ct = case.encrypt(8192, 4096, messages(4096, 40, 26), 27)
+    ids = np.full(40, tid, np.int32)
+    want = oracle.bootstrap_many(case.p, 4, case.keys.bsk, case.keys.ksk, V, 8192, 8192, ct)
+    n = case.ctx.schedule_count(ids)
+    assert {case.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2}
+    for choice in range(n):
+        case.ctx.set_schedule(ids, choice)
+        np.testing.assert_array_equal(case.ctx.bootstrap(ids, ct), want, err_msg=f"schedule {choice}")
+    case.ctx.close()
 
 
 @pytest.mark.parametrize("steps", [1, 4])
