@@ -122,6 +122,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
     // (a third of the LDS a ternary workgroup needs, so occupancy is unchanged);
     // not at N = 16384, where one slot takes 136 KB
     constexpr bool DS = KEYS == 1 && W > 1 && 2 * G::SLOTW * 4 <= 160 * 1024;
+    // 16 waves (N = 16384): the forward NTTs take one digit polynomial at a time
+    constexpr bool ONE_AT_A_TIME = W >= 16;
     __shared__ uint64_t lds64[G::SLOTW / 2 + (Y_LDS ? 2 * N : 0) + (DS ? G::SLOTW / 2 : 0)];
     uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64);
     uint64_t *const ylds = lds64 + G::SLOTW / 2;
@@ -182,6 +184,30 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
             __asm__ volatile("" ::: "memory");
             const uint32_t sh = u * A.log2B;
             const Y mask = u + 1 == A.l ? ~(Y)0 : (Y)(((Y)1 << A.log2B) - 1);
+            if constexpr (ONE_AT_A_TIME) {
+                // one digit polynomial at a time (16 waves leave 128 registers per lane):
+                // the digit of b meets rows u, then the digit of a rows l + u
+#pragma unroll
+                for (int part = 1; part >= 0; part--) {
+                    __asm__ volatile("" ::: "memory");
+                    uint32_t pd[1][E];
+#pragma unroll
+                    for (int k = 0; k < E; k++) {
+                        const Y yv = from_lds ? (Y)ylds[(part * E + k) * G::LANES + L] : y[part][k];
+                        pd[0][k] = (uint32_t)((yv >> sh) & mask);
+                    }
+                    ntt_fwd<N, 1, W, PRIO, DS>(pd, slot, pr ? A.twf1 : A.twf0, L, mod(pr), slot2, &par);
+                    const size_t row = part == 1 ? (size_t)u : (size_t)(A.l + u);
+                    const uint32_t *k_a = Kp + (row * 2 + 0) * N + L * E;
+                    const uint32_t *k_b = Kp + (row * 2 + 1) * N + L * E;
+#pragma unroll
+                    for (int k = 0; k < E; k++) {
+                        out[0][k] = add_q(out[0][k], redc((uint64_t)pd[0][k] * k_a[k], mod(pr)), mod(pr).Q);
+                        out[1][k] = add_q(out[1][k], redc((uint64_t)pd[0][k] * k_b[k], mod(pr)), mod(pr).Q);
+                    }
+                }
+                continue;
+            }
             uint32_t pd[2][E];
 #pragma unroll
             for (int k = 0; k < E; k++) {
