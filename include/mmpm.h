@@ -317,13 +317,25 @@ int mm_poll(mm_server *s, uint64_t ticket, uint32_t *ct_out);
 int mm_server_stats(mm_server *s, double *p50_ms, double *p99_ms, double *boots_per_s,
                     uint64_t *completed);
 
+/* Admission by expected queueing delay (load shedding): with max_wait_ms > 0,
+ * mm_submit refuses a request with MM_EBUSY when the requests already queued
+ * would take longer than max_wait_ms to be admitted at the server's recent
+ * completion rate (its last 512 completions); 0 (the default) admits every
+ * request while the queue has room.  mm_server_refused reports how many
+ * requests admission has refused since the server started. */
+int mm_server_set_admission(mm_server *s, double max_wait_ms);
+int mm_server_refused(mm_server *s, uint64_t *refused);
+
 /* Stop the server after its in-flight work completes. */
 int mm_server_stop(mm_server *s);
 
 /* Replay a request trace: request k (table table_ids[k], ciphertext
  * ct_in + k(n+1)) arrives arrival_ns[k] ns after the call starts; the call
  * submits each at its time, collects every result into ct_out + k(n+1) and
- * latency_ms[k], and returns when all are done. */
+ * latency_ms[k], and returns when all are done.  A request the queue cannot
+ * take is submitted again until it can; with admission on
+ * (mm_server_set_admission) a refused request is not retried: its latency is
+ * -1 and its output words are zero. */
 int mm_server_replay(mm_server *s, const int *table_ids, const uint32_t *ct_in,
                      const int64_t *arrival_ns, size_t count, uint32_t *ct_out,
                      double *latency_ms);

@@ -25,7 +25,7 @@ SYMBOLS = [
     "mm_bootstrap", "mm_modswitch", "mm_blind_rotate", "mm_external_product", "mm_sample_extract",
     "mm_keyswitch", "mm_keyswitch_noalloc", "mm_negacyclic_mul", "mm_set_timing", "mm_last_timing", "mm_autotune",
     "mm_schedule_count", "mm_set_schedule", "mm_schedule_describe", "mm_server_start", "mm_submit", "mm_poll",
-    "mm_server_stats", "mm_server_stop", "mm_server_replay",
+    "mm_server_stats", "mm_server_stop", "mm_server_replay", "mm_server_set_admission", "mm_server_refused",
 ]
 
 
@@ -85,6 +85,8 @@ def _load():
                                   C.POINTER(u64)]),
         "mm_server_stop": (i32, [vp]),
         "mm_server_replay": (i32, [vp, vp, vp, vp, sz, vp, vp]),
+        "mm_server_set_admission": (i32, [vp, C.c_double]),
+        "mm_server_refused": (i32, [vp, C.POINTER(C.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -385,6 +387,15 @@ class Server:
         done = C.c_uint64()
         self._check(lib.mm_server_stats(self.h, C.byref(p50), C.byref(p99), C.byref(bps), C.byref(done)))
         return {"p50_ms": p50.value, "p99_ms": p99.value, "boots_per_s": bps.value, "completed": done.value}
+
+    def set_admission(self, max_wait_ms: float):
+        """Refuse requests whose expected queueing delay exceeds max_wait_ms (0: off)."""
+        self._check(lib.mm_server_set_admission(self.h, float(max_wait_ms)))
+
+    def refused(self) -> int:
+        n = C.c_uint64()
+        self._check(lib.mm_server_refused(self.h, C.byref(n)))
+        return n.value
 
     def replay(self, table_ids, cts, arrival_ns):
         ids = _i32(table_ids)

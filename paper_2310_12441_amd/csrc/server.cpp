@@ -146,7 +146,13 @@ struct Server {
     std::vector<double> lat;            // latencies of the last LAT_CAP completed requests (a ring)
     size_t lat_next = 0;
     static constexpr size_t LAT_CAP = size_t(1) << 20;
-    uint64_t next_ticket = 1, completed = 0;
+    uint64_t next_ticket = 1, completed = 0, refused = 0;
+    // admission by expected queueing delay (0: off): a request is refused when the
+    // requests already queued would take longer than max_wait_ms to be admitted at
+    // the recent completion rate (the last RECENT completions)
+    double max_wait_ms = 0.0;
+    std::deque<clk::time_point> recent;
+    static constexpr size_t RECENT = 512;
     bool have_first = false;
     clk::time_point t_first, t_last;
     std::atomic<bool> stop{false};
@@ -257,6 +263,16 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
         *rc = MM_EBUSY;
         return 0;
     }
+    if (max_wait_ms > 0 && recent.size() >= 64) {
+        const double span = std::chrono::duration<double, std::milli>(recent.back() - recent.front()).count();
+        const double per_ms = span > 0 ? (double)(recent.size() - 1) / span : 0.0;
+        const double queued = (double)(pending[0].size() + pending[1].size());
+        if (per_ms > 0 && queued / per_ms > max_wait_ms) {
+            refused++;
+            *rc = MM_EBUSY;
+            return 0;
+        }
+    }
     Req r{next_ticket++, table, std::vector<uint32_t>(ct, ct + W), t0};
     live.insert(r.ticket);
     if (!have_first) {
@@ -290,6 +306,8 @@ bool Server::harvest(Part &p)
         free_slots.push_back(a.slot);
         buddy.release(a.unit, a.order);
         completed++;
+        recent.push_back(now);
+        if (recent.size() > RECENT) recent.pop_front();
     }
     if (!p.finishing.empty()) t_last = now;
     p.finishing.clear();
@@ -524,6 +542,22 @@ int mm_poll(mm_server *h, uint64_t ticket, uint32_t *ct_out)
     return MM_OK;
 }
 
+int mm_server_set_admission(mm_server *h, double max_wait_ms)
+{
+    if (!h || !h->s || !(max_wait_ms >= 0)) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(h->s->mu);
+    h->s->max_wait_ms = max_wait_ms;
+    return MM_OK;
+}
+
+int mm_server_refused(mm_server *h, uint64_t *refused)
+{
+    if (!h || !h->s || !refused) return MM_EINVAL;
+    std::lock_guard<std::mutex> g(h->s->mu);
+    *refused = h->s->refused;
+    return MM_OK;
+}
+
 int mm_server_stats(mm_server *h, double *p50_ms, double *p99_ms, double *boots_per_s, uint64_t *completed)
 {
     if (!h || !h->s) return MM_EINVAL;
@@ -564,11 +598,18 @@ int mm_server_replay(mm_server *h, const int *table_ids, const uint32_t *ct_in, 
     const size_t W = s.c->p.n + 1;
     const auto start = mm::clk::now();
     std::vector<uint64_t> tickets(count, 0);
+    std::vector<char> refused(count, 0);
     std::vector<mm::clk::time_point> t0(count);
     size_t next_poll = 0;
     auto poll_some = [&](bool all) {
         std::lock_guard<std::mutex> g(s.mu);
-        while (next_poll < count && tickets[next_poll]) {
+        while (next_poll < count && (tickets[next_poll] || refused[next_poll])) {
+            if (refused[next_poll]) {  // refused by admission: no result, latency -1
+                std::memset(ct_out + next_poll * W, 0, W * 4);
+                latency_ms[next_poll] = -1.0;
+                next_poll++;
+                continue;
+            }
             auto it = s.done.find(tickets[next_poll]);
             if (it == s.done.end()) {
                 if (!all) break;
@@ -594,7 +635,16 @@ int mm_server_replay(mm_server *h, const int *table_ids, const uint32_t *ct_in, 
             tickets[k] = s.submit(table_ids[k], ct_in + k * W, t0[k], &rc);
             if (rc == MM_OK) break;
             if (rc != MM_EBUSY) return rc;
-            std::this_thread::sleep_for(std::chrono::microseconds(100));
+            bool shedding;
+            {
+                std::lock_guard<std::mutex> g(s.mu);
+                shedding = s.max_wait_ms > 0;
+            }
+            if (shedding) {  // refused by admission: recorded, not retried
+                refused[k] = 1;
+                break;
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(100));  // the queue is full: wait
         }
         if ((k & 63) == 63) poll_some(false);
     }

@@ -93,6 +93,30 @@ def test_replay_poisson_trace_small_budget(setup):
     print("serving p50 %.2f ms p99 %.2f ms, %.0f boots/s" % (st["p50_ms"], st["p99_ms"], st["boots_per_s"]))
 
 
+def test_admission_sheds_load_and_admitted_results_are_exact(setup):
+    """Arrivals far above capacity with admission by expected queueing delay on:
+    some requests are refused (latency -1, zero output, counted by the server),
+    every admitted one equals the same ciphertext bootstrapped alone."""
+    p, ctx, tabs, keys, b = setup
+    ids, cts, cls = _requests(p, keys, tabs, 3000, 6)
+    arrivals = poisson_arrivals(50000.0, len(ids), 7)
+    srv = ctx.server_start(24 << 20, chunk_steps=63)
+    with pytest.raises(b.MMError):
+        srv.set_admission(-1.0)
+    srv.set_admission(10.0)
+    out, lat = srv.replay(ids, cts, arrivals)
+    st = srv.stats()
+    refused = srv.refused()
+    srv.stop()
+    shed = lat < 0
+    print("admission: %d of %d refused; admitted p50 %.2f ms p99 %.2f ms" %
+          (shed.sum(), len(ids), np.percentile(lat[~shed], 50), np.percentile(lat[~shed], 99)))
+    assert shed.sum() == refused > 0
+    assert st["completed"] == len(ids) - refused
+    assert np.all(out[shed] == 0)
+    np.testing.assert_array_equal(out[~shed], ctx.bootstrap(ids[~shed], cts[~shed]))
+
+
 def test_server_errors(setup):
     p, ctx, tabs, keys, b = setup
     with pytest.raises(b.MMError):
