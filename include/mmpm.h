@@ -256,8 +256,9 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
  * kernel and tiling) on the device and remember the fastest for the shape (N,
  * sum of r, count).  mm_bootstrap uses the remembered schedule.  *choice
  * receives the chosen schedule index.  A batch on the global-accumulator path
- * (see mm_params) has one schedule: this call and the mm_schedule_* calls
- * return MM_EINVAL for it. */
+ * (see mm_params; the wide modulus among others) has one blind-rotation shape:
+ * its candidates differ in the key switch only, and this call runs the batch
+ * once and then times each key switch on its extracted samples. */
 int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
                 int *choice);
 
@@ -268,10 +269,12 @@ int mm_schedule_count(mm_ctx *ctx, const int *table_ids, size_t count, int *n);
 int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice);
 
 /* What schedule `choice` of this batch shape is (choice < 0: the one in use):
- * waves per blind-rotation workgroup (8 or 4), ciphertexts per wave of the
+ * waves per blind-rotation workgroup (8 or 4; 0 on the global-accumulator
+ * path, one workgroup per component and CMux step), ciphertexts per wave of the
  * key switch (0 = the i-split key switch), the number of i splits, waves per
  * ring component (1 up to N = 1024 and N / 1024 above by default; 2 at N = 512
- * and 1024 for batches that do not fill the device, r <= 4), the key-switch
+ * and 1024 for batches that do not fill the device, r <= 4; on the global path
+ * the waves of its workgroup, N / 512 up to 4096 and N / 1024 above), the key-switch
  * kernel (0: i split over workgroups, per-thread sums; 1: KSK rows staged in
  * LDS, one output column per lane; 2: KSK rows staged in LDS, one ciphertext
  * per lane) and the NTT stage schedule of the blind rotation (0: every
@@ -294,7 +297,14 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
  * every resident ciphertext of its partition by chunk_steps CMux steps (2/3 of
  * that for the wider ones when a partition holds both kinds), so a request
  * admitted while others run joins them at the next launch.  Tables of general
- * f, or with r N/1024 > 8, are not served.
+ * f are not served, nor, at the default modulus and N <= 8192, tables with
+ * r N/1024 > 8.  A context on the global-accumulator path (Q2 != 0, or
+ * N = 16384) is served with that path's kernels: each launch ("tick") is
+ * chunk_steps CMux launches over every resident component, each ciphertext at
+ * its own step, with accumulators in two device arenas (the budget then counts
+ * 2 x 2 x N words per component and residue); any r up to 1024 whose block of
+ * 2^ceil(log2 r) components fits the budget is served (MM_EINVAL at submission
+ * otherwise).
  * The handle stays valid until mm_server_stop; mm_free of the context stops a
  * running server too, after which the handle must not be used. */
 int mm_server_start(mm_ctx *ctx, size_t hbm_budget_bytes, uint32_t chunk_steps, mm_server **out);

@@ -341,7 +341,7 @@ class Context:
         self._check(lib.mm_set_schedule(self.h, ids.ctypes.data_as(C.c_void_p), ids.size, choice))
 
     def schedule_describe(self, table_ids, choice: int = -1):
-        """(waves per blind-rotation workgroup, key-switch ciphertexts per wave, key-switch splits,
+        """(waves per blind-rotation workgroup (0: the global-accumulator path), key-switch ciphertexts per wave, key-switch splits,
         waves per ring component, key-switch kernel (0 i-split, 1 columns in lanes, 2 one ciphertext
         per lane), NTT schedule)."""
         ids = _i32(np.atleast_1d(table_ids))

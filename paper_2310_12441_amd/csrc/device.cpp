@@ -475,7 +475,7 @@ static bool use_global(const mm_ctx &c, const int *ids, size_t count)
     return c.wide || !dev::device_supports_n(c.p.N) || max_r(c, ids, count) * (uint32_t)dev::waves_per_poly(c.p.N) > 8;
 }
 
-static int primes_of(const mm_ctx &c) { return c.wide ? 2 : 1; }
+int primes_of(const mm_ctx &c) { return c.wide ? 2 : 1; }
 
 // Two waves per component (N = 512, 1024, r <= 4): for batches that do not
 // fill every compute unit, both waves of a slot share one component's work.
@@ -510,6 +510,12 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
     if (rows <= (uint32_t)dev::KS_TILED_MAX_ROWS && count >= 256)
         for (uint32_t P : {2u, 3u, 4u, 6u}) add(KsSched{KS_LANES, P});
     if (count < 256) ks.push_back(KsSched{0, ks_splits(c, d, count)});
+    if (use_global(c, ids, count)) {
+        // one blind-rotation shape (a workgroup per component and CMux step): the
+        // candidates differ in the key switch only
+        for (auto &k : ks) out.push_back(Sched{0, k});
+        return out;
+    }
     for (int gw : {8, 4}) {
         if (gw == 4 && !narrow_ok) continue;
         for (auto &k : ks) out.push_back(Sched{gw, k});
@@ -536,6 +542,7 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         auto cand = candidates(c, d, ids, count);
         if (it->second >= 0 && (size_t)it->second < cand.size()) return cand[it->second];
     }
+    if (use_global(c, ids, count)) return Sched{0, ks_default(c, d, count)};
     // untuned: 2-wave slots while the components fit half-full groups on every
     // compute unit (the chip is not full), else the full-width default
     const bool light = sum_r(c, ids, count) <= 4ull * (uint64_t)d.num_cu;
@@ -617,14 +624,15 @@ static void run_sequence(Device &d, const std::string &key, bool use_graph, hipS
 }
 
 static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
-                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st);
+                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st, const KsSched &ks);
 
 // The batched path for ciphertexts already on the device.
 static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
                             uint32_t q_out, bool use_graph, hipStream_t st, const Sched *force = nullptr)
 {
     if (use_global(c, ids, count)) {
-        bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st);
+        const Sched S = force ? *force : schedule_for(c, d, ids, count);
+        bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st, S.ks);
         return;
     }
     const uint32_t N = c.p.N;
@@ -661,11 +669,12 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
 
 // ------------------------------------------------------------------ wide ring modulus
 
-static dev::WideArgs wide_args(const mm_ctx &c, const Device &d)
+dev::WideArgs wide_args(const mm_ctx &c, const Device &d)
 {
     const mm_params &p = c.p;
     dev::WideArgs A{};
     A.ct_stride = p.n + 1;
+    A.n = p.n;
     A.Q[0] = p.Q;
     A.qn[0] = d.qn;
     A.log2B = p.log2_B;
@@ -744,7 +753,7 @@ static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_
 }
 
 static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
-                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st)
+                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st, const KsSched &ks)
 {
     const uint32_t N = c.p.N;
     std::vector<dev::WideTask> tasks;
@@ -752,7 +761,6 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
     const uint64_t words = wide_tasks(c, ids, count, tasks, offs);
     uint32_t q_scalar = q_out;
     const uint32_t *qv = resolve_q_out(c, d, ids, count, q_scalar, st);
-    const KsSched ks = ks_default(c, d, count);
     uint32_t *ext = (uint32_t *)ws(d, WS_EXT, count * (N + 1) * 4);
     uint64_t *part = (uint64_t *)ws(d, WS_PART, ks_part_words(c, ks, count) * 8);
     uint32_t *acc0 = (uint32_t *)ws(d, WS_ACC, words * 4);
@@ -1005,11 +1013,8 @@ void last_timing(mm_ctx &c, float *br_ms, float *ks_ms)
 
 int schedule_count(mm_ctx &c, const int *ids, size_t count)
 {
-    MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no schedule calls)");
     MM_REQUIRE(check_ids(c, ids, count) == 0, "schedules are per nega-cyclic table batch");
     MM_REQUIRE(count > 0, "empty batch");
-    MM_REQUIRE(!use_global(c, ids, count),
-               "this batch runs the global-accumulator path (one schedule, no schedule calls)");
     Device &d = ensure_device(c);
     return (int)candidates(c, d, ids, count).size();
 }
@@ -1033,7 +1038,52 @@ void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int 
     if (ks_kernel) *ks_kernel = S.ks.cpw == KS_LANES ? 2 : (S.ks.cpw > 0 ? 1 : 0);
     if (ntt) *ntt = S.ntt;
     if (P) *P = (int)S.ks.P;
-    if (wpp) *wpp = S.wpp ? S.wpp : dev::waves_per_poly(c.p.N);
+    if (wpp) *wpp = S.wpp ? S.wpp : (S.gw == 0 ? dev::wide_waves_per_poly(c.p.N) : dev::waves_per_poly(c.p.N));
+}
+
+// The global-accumulator path has one blind-rotation shape: run the batch once,
+// then time each key-switch candidate on its extracted samples.
+static int autotune_global(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, uint32_t *d_out,
+                           size_t count)
+{
+    hipStream_t st = d.own;
+    auto cand = candidates(c, d, ids, count);
+    bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &cand[0]);
+    // the samples extracted by that run stay in the workspace (allocated before any
+    // later workspace request of this function, so not moved)
+    const uint32_t *ext = (const uint32_t *)ws(d, WS_EXT, count * (c.p.N + 1) * 4);
+    size_t part_words = 0;
+    for (auto &S : cand) part_words = std::max(part_words, ks_part_words(c, S.ks, count));
+    uint64_t *part = (uint64_t *)ws(d, WS_PART, part_words * 8);
+    HIPC(hipStreamSynchronize(st));
+    hipEvent_t ev[2];
+    HIPC(hipEventCreate(&ev[0]));
+    HIPC(hipEventCreate(&ev[1]));
+    int choice = 0;
+    float best = 1e30f;
+    try {
+        for (size_t k = 0; k < cand.size(); k++) {
+            enqueue_keyswitch(c, d, ext, nullptr, count, d_out, nullptr, c.p.Q, cand[k].ks, part, st);
+            HIPC(hipEventRecord(ev[0], st));
+            enqueue_keyswitch(c, d, ext, nullptr, count, d_out, nullptr, c.p.Q, cand[k].ks, part, st);
+            HIPC(hipEventRecord(ev[1], st));
+            HIPC(hipEventSynchronize(ev[1]));
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            if (ms < best) {
+                best = ms;
+                choice = (int)k;
+            }
+        }
+    } catch (...) {
+        hipEventDestroy(ev[0]);
+        hipEventDestroy(ev[1]);
+        throw;
+    }
+    HIPC(hipEventDestroy(ev[0]));
+    HIPC(hipEventDestroy(ev[1]));
+    d.tuned[shape_key(c, ids, count)] = choice;
+    return choice;
 }
 
 // Time each blind-rotation shape (group width, waves per component; with the
@@ -1042,17 +1092,15 @@ void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int 
 // the batch shape.
 int run_autotune(mm_ctx &c, const int *ids, const uint32_t *ct_in, size_t count)
 {
-    MM_REQUIRE(!c.wide, "a wide ring modulus has one schedule (no autotuning)");
     MM_REQUIRE(check_ids(c, ids, count) == 0, "autotuning takes nega-cyclic tables");
     MM_REQUIRE(count > 0, "empty batch");
-    MM_REQUIRE(!use_global(c, ids, count),
-               "this batch runs the global-accumulator path (one schedule, no autotuning)");
     Device &d = ensure_device(c);
     const size_t W = c.p.n + 1;
     hipStream_t st = d.own;
     const uint32_t *d_in = stage_in(d, WS_IN, ct_in, count * W, false, st);
     uint32_t *d_out = stage_out(d, WS_OUT, nullptr, count * W, false);
     HIPC(hipStreamSynchronize(st));
+    if (use_global(c, ids, count)) return autotune_global(c, d, ids, d_in, d_out, count);
     auto cand = candidates(c, d, ids, count);
     const bool was_timed = d.timing;
     if (!d.tev[0])

@@ -90,7 +90,8 @@ struct KsSched {
     uint32_t P = 1;
 };
 
-// A batch schedule: blind-rotation group width (8 or 4 waves), waves per
+// A batch schedule: blind-rotation group width (8 or 4 waves; 0 on the
+// global-accumulator path, which has one blind-rotation shape), waves per
 // component polynomial (0: the ring's default), key switch, and the NTT stage
 // schedule (0: every cross-lane exchange through LDS, the two polys of an NTT
 // in lockstep; 1: the last exchange by wavefront lane swaps; 2: LDS exchanges
@@ -113,5 +114,10 @@ uint32_t ks_splits(const mm_ctx &c, const Device &d, size_t count);
 void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const int32_t *rows, size_t count,
                        uint32_t *out, const uint32_t *q_out_per_ct, uint32_t q_out, const KsSched &ks, uint64_t *part,
                        hipStream_t st);
+// The global-accumulator path: the kernel arguments (tasks, inputs and buffers
+// left to the caller) and the number of residues per coefficient (2 with the
+// wide modulus, else 1).
+dev::WideArgs wide_args(const mm_ctx &c, const Device &d);
+int primes_of(const mm_ctx &c);
 
 }  // namespace mm

@@ -55,7 +55,7 @@ struct WideTask {
     uint32_t r;        // vector length of the ciphertext's table
     uint32_t q_in;     // ciphertext modulus
     uint32_t tv_off;   // word offset of the table's test vector ([r][2][N]) in the arena
-    uint32_t pad;
+    uint32_t i0;       // CMux step of the ciphertext at the first launch of a sequence (0 for a batch)
     uint64_t acc_off;  // word offset of the ciphertext's component 0; a component is [2 parts][2 primes][N]
 };
 
@@ -65,12 +65,12 @@ struct WideArgs {
     const WideTask *tasks;
     const uint32_t *ct_in;     // ciphertexts at their q_in
     uint32_t ct_stride;        // n + 1
-    uint32_t step;             // CMux step i of this launch
+    uint32_t step;             // launch index within a sequence: a task takes CMux step i = i0 + step
     uint32_t Q[2], qn[2];      // the two primes and -Q^-1 mod 2^32
     uint32_t log2B, l, sg;
     uint32_t crt_cq;           // the smallest multiple of Q[1] that is >= Q[0]
     uint32_t crt_inv;          // Q[0]^-1 mod Q[1], times 2^32 mod Q[1]
-    uint32_t pad;
+    uint32_t n;                // LWE dimension: a task at i >= n carries its accumulator over
     uint64_t Qw, goff;         // Q[0] Q[1]; (B/2)(1 + B + ... + B^(l-1))
     const uint32_t *bsk;       // [n][keys][prime][2l][2][N], NTT domain, x 2^32 / N mod that prime
     const uint32_t *bsk_corr;  // [n][prime][2][N]: the digit-offset correction, summed over keys
@@ -120,7 +120,8 @@ void launch_scatter_rows(const uint32_t *src, uint32_t *dst, const int32_t *rows
 void launch_blind_rotate(uint32_t N, const BrArgs &A, int gw, int grid, hipStream_t st, int wpp = 0, int ntt = 0);
 bool br_supports_wpp(uint32_t N, int wpp);
 bool br_supports_lane_swap(uint32_t N);
-// wide modulus: ACC = Phi(b')(0, V) into A.acc_wr; one CMux step (A.step) from
+// wide modulus: ACC = Phi(b')(0, V) into A.acc_wr; one CMux step (step i0 +
+// A.step of each task; a task past step n - 1 copies its component) from
 // A.acc_rd into A.acc_wr; extraction of component 0 switched to Q[0]
 // (ext[c] from the component at acc_off[c]); the accumulator as uint64 values
 // [component][part][N] at the same word offsets.
@@ -133,6 +134,7 @@ void launch_wide_extract(uint32_t N, int npr, const WideArgs &A, const uint64_t 
                          uint32_t *ext, hipStream_t st);
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st);
 bool wide_supports_n(uint32_t N, int npr);
+int wide_waves_per_poly(uint32_t N);  // waves of one k_wide_step workgroup
 size_t br_lds_bytes(uint32_t N, int gw, int wpp = 0);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
                              const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,

@@ -131,12 +131,20 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
     int par = 0;                              // relayouts so far: which slot the next one uses
     const WideTask T = A.tasks[blockIdx.x];
     const int L = threadIdx.x;
-    const uint32_t M = 2u * N * T.r;
-    const uint32_t am = wide_modswitch(A.ct_in[(size_t)T.ct * A.ct_stride + A.step], T.q_in, M);
-    // per-prime constants by selection (no private arrays: those would be placed in LDS)
-    auto mod = [&](int pr) { return ModQ{pr ? A.Q[1] : A.Q[0], pr ? A.qn[1] : A.qn[0]}; };
     constexpr size_t CW = (size_t)2 * NPR * N, PW = (size_t)NPR * N;  // words per component, per part
     const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * CW;
+    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * CW;
+    const uint32_t i = T.i0 + A.step;  // this task's CMux step
+    if (i >= A.n) {
+        // past step n - 1 (a ciphertext that finishes inside a sequence of launches):
+        // carry the component over to the buffer the next launch reads
+        for (uint32_t w = threadIdx.x; w < (uint32_t)CW; w += blockDim.x) wr[w] = own[w];
+        return;
+    }
+    const uint32_t M = 2u * N * T.r;
+    const uint32_t am = wide_modswitch(A.ct_in[(size_t)T.ct * A.ct_stride + i], T.q_in, M);
+    // per-prime constants by selection (no private arrays: those would be placed in LDS)
+    auto mod = [&](int pr) { return ModQ{pr ? A.Q[1] : A.Q[0], pr ? A.qn[1] : A.qn[0]}; };
 
     // y'' = round(centred(D) / 2^sg) + goff per coefficient of parts a (0) and b
     // (1), D = Phi(c) ACC_j - ACC_j (joined from its two residues with two primes)
@@ -168,10 +176,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
                 }
             }
     };
-    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * CW;
     // NTT-domain output of one prime from the digit-offset correction
     auto start = [&](int pr, uint32_t (&out)[2][E]) {
-        const uint32_t *corr = A.bsk_corr + ((size_t)A.step * NPR + pr) * 2 * N + L * E;
+        const uint32_t *corr = A.bsk_corr + ((size_t)i * NPR + pr) * 2 * N + L * E;
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
     };
     // out += the digits of y times BSK_{i,key} for one prime (eq. def:gsw)
     auto mac = [&](int pr, int key, uint32_t (&out)[2][E], bool from_lds = false) {
-        const uint32_t *Kp = A.bsk + (((size_t)A.step * KEYS + key) * NPR + pr) * (2 * A.l * 2 * N);
+        const uint32_t *Kp = A.bsk + (((size_t)i * KEYS + key) * NPR + pr) * (2 * A.l * 2 * N);
         for (uint32_t u = 0; u < A.l; u++) {
             __asm__ volatile("" ::: "memory");
             const uint32_t sh = u * A.log2B;
@@ -396,6 +403,8 @@ void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint3
 }
 
 #undef WIDE_DISPATCH
+
+int wide_waves_per_poly(uint32_t N) { return wide_wpp((int)N); }
 
 bool wide_supports_n(uint32_t N, int npr)
 {

@@ -9,6 +9,12 @@
 // partition's tick runs, the host harvests and relaunches the other, so the
 // two overlap on the device.  Ciphertexts that reach step n are key-switched in
 // the same tick and their results copied back.
+//
+// Contexts whose bootstraps run the global-accumulator path (the wide ring
+// modulus, rings of degree 16384) are served the same way with that path's
+// kernels: a tick is `chunk` CMux launches over every resident component, each
+// ciphertext at its own step (a ciphertext that reaches step n inside the tick
+// carries its accumulator over), the accumulators in two device arenas.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -29,20 +35,35 @@ using clk = std::chrono::steady_clock;
 namespace {
 
 // Buddy allocator over accumulator units (one unit = the (a, b) pair of one
-// ring component, 2N words); a ciphertext with vector length r takes a block
-// of 2^ceil(log2 r) units, r <= 8.
+// ring component); a ciphertext with vector length r takes a block of
+// 2^ceil(log2 r) units, r <= 2^top.
 struct Buddy {
-    std::set<uint32_t> free_[4];
-    void init(uint32_t units)
+    std::vector<std::set<uint32_t>> free_;
+    uint32_t top = 3;
+    // aligned blocks of at most 2^top units, largest first, cover [0, units)
+    void init(uint32_t units, uint32_t top_order)
     {
-        for (auto &f : free_) f.clear();
-        for (uint32_t u = 0; u + 8 <= units; u += 8) free_[3].insert(u);
+        top = top_order;
+        free_.assign(top + 1, {});
+        uint32_t u = 0;
+        for (int o = (int)top; o >= 0; o--)
+            while (u + (1u << o) <= units) {
+                free_[o].insert(u);
+                u += 1u << o;
+            }
+    }
+    // the largest order that init left a block of
+    uint32_t largest() const
+    {
+        for (int o = (int)top; o >= 0; o--)
+            if (!free_[o].empty()) return (uint32_t)o;
+        return 0;
     }
     int64_t alloc(uint32_t order)
     {
         uint32_t o = order;
-        while (o < 4 && free_[o].empty()) o++;
-        if (o == 4) return -1;
+        while (o <= top && free_[o].empty()) o++;
+        if (o > top) return -1;
         uint32_t start = *free_[o].begin();
         free_[o].erase(free_[o].begin());
         while (o > order) {  // split, keep the lower half
@@ -53,7 +74,7 @@ struct Buddy {
     }
     void release(uint32_t start, uint32_t order)
     {
-        while (order < 3) {
+        while (order < top) {
             const uint32_t buddy = start ^ (1u << order);
             auto it = free_[order].find(buddy);
             if (it == free_[order].end()) break;
@@ -126,6 +147,15 @@ struct Part {
     DevHost<uint32_t> out, stage, qout;
     uint64_t *part = nullptr;
     size_t part_cap = 0;
+    // global-accumulator path: task list (fresh components' initialisations, then
+    // every resident component's steps), component-0 offsets of the finishing
+    // ciphertexts, their extracted samples, and the arena holding this partition's
+    // current accumulators
+    DevHost<dev::WideTask> wtasks;
+    DevHost<uint64_t> woff;
+    uint32_t *ext = nullptr;
+    size_t ext_cap = 0;
+    int cur = 0;
 };
 
 }  // namespace
@@ -133,6 +163,9 @@ struct Part {
 struct Server {
     mm_ctx *c = nullptr;
     uint32_t chunk = 64, max_cts = 0, units = 0;
+    bool global = false;     // the global-accumulator path (one launch per CMux step)
+    size_t unit_words = 0;   // words of one unit in one arena
+    uint32_t top_block = 3;  // order of the largest block the arena holds
     uint32_t *d_acc = nullptr, *d_ct = nullptr, *d_ext = nullptr;
     Buddy buddy;
     std::vector<uint32_t> free_slots;
@@ -162,6 +195,7 @@ struct Server {
     void loop();
     bool harvest(Part &p);
     void launch(Part &p);
+    void launch_global(Part &p, const std::vector<Active> &fresh);
     uint64_t submit(int table, const uint32_t *ct, clk::time_point t0, int *rc);
     ~Server();
 };
@@ -177,7 +211,10 @@ Server::~Server()
         p.out.release();
         p.stage.release();
         p.qout.release();
+        p.wtasks.release();
+        p.woff.release();
         if (p.part) hipFree(p.part);
+        if (p.ext) hipFree(p.ext);
         if (p.ev) hipEventDestroy(p.ev);
         if (p.st) hipStreamDestroy(p.st);
     }
@@ -195,27 +232,32 @@ Server::~Server()
 
 Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
 {
-    MM_REQUIRE(!c.wide, "the server takes the default ring modulus (Q2 = 0)");
-    MM_REQUIRE(dev::device_supports_n(c.p.N), "the server takes rings of degree up to 8192");
     MM_REQUIRE(chunk >= 1 && chunk <= c.p.n, "chunk_steps must be in [1, n]");
     Device &d = ensure_device(c);
     const size_t N = c.p.N, W = c.p.n + 1;
-    // per ciphertext slot: input, extracted sample, key-switch partial row; per unit: one (a, b) pair
+    const bool global = c.wide || !dev::device_supports_n(c.p.N);
+    // per ciphertext slot: input, extracted sample, key-switch partial row; per unit:
+    // one (a, b) pair (global path: with every residue, in each of the two arenas)
     const size_t per_ct = (W + N + 1) * 4 + W * 8;
-    const size_t per_unit = 2 * N * 4;
-    const size_t units = (budget / (per_ct + per_unit)) / 8 * 8;
-    MM_REQUIRE(units >= 8, "HBM budget too small for one slot group");
+    const size_t unit_words = 2 * (size_t)primes_of(c) * N;
+    const size_t per_unit = (global ? 2 : 1) * unit_words * 4;
+    const size_t fit = budget / (per_ct + per_unit);
+    const size_t units = global ? std::min<size_t>(fit, size_t(1) << 24) : fit / 8 * 8;
+    MM_REQUIRE(units >= (global ? 1 : 8), "HBM budget too small for one slot group");
     auto *s = new Server();
     s->c = &c;
     s->chunk = chunk;
+    s->global = global;
+    s->unit_words = unit_words;
     s->units = (uint32_t)units;
     s->max_cts = (uint32_t)units;
     try {
         if (hipMalloc((void **)&s->d_acc, units * per_unit) != hipSuccess ||
             hipMalloc((void **)&s->d_ct, (size_t)s->max_cts * W * 4) != hipSuccess ||
-            hipMalloc((void **)&s->d_ext, (size_t)s->max_cts * (N + 1) * 4) != hipSuccess)
+            (!global && hipMalloc((void **)&s->d_ext, (size_t)s->max_cts * (N + 1) * 4) != hipSuccess))
             throw Error(MM_ENOMEM, "server arena allocation failed");
-        s->buddy.init(s->units);
+        s->buddy.init(s->units, global ? 10 : 3);
+        s->top_block = s->buddy.largest();
         s->free_slots.resize(s->max_cts);
         for (uint32_t i = 0; i < s->max_cts; i++) s->free_slots[i] = s->max_cts - 1 - i;
         for (auto &p : s->part) {
@@ -246,13 +288,18 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
     int cls = 0;
     {
         std::lock_guard<std::mutex> gc(c->lock);  // the table list may grow under this lock
-        ok = table >= 0 && (size_t)table < c->tables.size() && c->tables[table].g_id < 0 &&
-             c->tables[table].r * (uint32_t)dev::waves_per_poly(c->p.N) <= 8;
-        if (ok) cls = c->tables[table].r > 4 ? 1 : 0;
+        ok = table >= 0 && (size_t)table < c->tables.size() && c->tables[table].g_id < 0;
+        if (ok) {
+            const uint32_t r = c->tables[table].r;
+            ok = global ? order_of(r) <= top_block : r * (uint32_t)dev::waves_per_poly(c->p.N) <= 8;
+            cls = r > 4 ? 1 : 0;
+        }
     }
     std::lock_guard<std::mutex> g(mu);
     if (!ok) {
-        *rc = MM_EINVAL;  // unknown table, a general table (two bootstraps; not served), or too wide a group
+        // unknown table, a general table (two bootstraps; not served), too wide a
+        // group, or (global path) more components than the arena holds
+        *rc = MM_EINVAL;
         return 0;
     }
     if (stop) {
@@ -358,6 +405,10 @@ void Server::launch(Part &p)
         dev::launch_scatter_rows(p.stage.d, d_ct, p.stage_rows.d, fresh.size(), W, p.st);
         p.active.insert(p.active.end(), fresh.begin(), fresh.end());
     }
+    if (global) {
+        launch_global(p, fresh);
+        return;
+    }
     // one task per resident ciphertext, packed into 8-wave groups; under light
     // load the groups hold at most 4 components (one wave per SIMD), and a
     // ciphertext that still needs all 8 slots (two waves per SIMD, about 1.5x
@@ -436,6 +487,97 @@ void Server::launch(Part &p)
             p.part_cap = need * 2;
         }
         enqueue_keyswitch(*c, d, d_ext, p.rows.d, F, p.out.d, p.qout.d, 0, ks, p.part, p.st);
+        SRV_HIP(hipMemcpyAsync(p.out.h, p.out.d, F * W * 4, hipMemcpyDeviceToHost, p.st));
+    }
+    SRV_HIP(hipGetLastError());
+    SRV_HIP(hipEventRecord(p.ev, p.st));
+    p.busy = true;
+}
+
+// One tick on the global-accumulator path: initialise the fresh ciphertexts'
+// accumulators in the partition's current arena, `chunk` CMux launches over every
+// resident component (each from its own ciphertext's step), then extraction, key
+// switch and copy-back of the ciphertexts that reached step n.
+void Server::launch_global(Part &p, const std::vector<Active> &fresh)
+{
+    const uint32_t N = c->p.N, W = c->p.n + 1, n = c->p.n;
+    Device &d = *c->dev;
+    const int npr = primes_of(*c);
+    uint32_t *arena[2] = {d_acc, d_acc + (size_t)units * unit_words};
+    auto task = [&](const Active &a, uint32_t j, uint32_t i0) {
+        const Table &t = c->tables[a.table];
+        return dev::WideTask{(int32_t)a.slot, j, t.r, t.q_in, (uint32_t)t.dev_offset, i0, (uint64_t)a.unit * unit_words};
+    };
+    std::vector<dev::WideTask> list;
+    for (auto &a : fresh)
+        for (uint32_t j = 0; j < c->tables[a.table].r; j++) list.push_back(task(a, j, 0));
+    const size_t n_init = list.size();
+    for (auto &a : p.active)
+        for (uint32_t j = 0; j < c->tables[a.table].r; j++) list.push_back(task(a, j, a.step));
+    const size_t n_step = list.size() - n_init;
+    p.wtasks.reserve(list.size());
+    std::memcpy(p.wtasks.h, list.data(), list.size() * sizeof(dev::WideTask));
+    SRV_HIP(hipMemcpyAsync(p.wtasks.d, p.wtasks.h, list.size() * sizeof(dev::WideTask), hipMemcpyHostToDevice, p.st));
+    dev::WideArgs A = wide_args(*c, d);
+    A.ct_in = d_ct;
+    if (n_init) {
+        A.tasks = p.wtasks.d;
+        A.acc_wr = arena[p.cur];
+        dev::launch_wide_init(N, npr, A, (uint32_t)n_init, p.st);
+    }
+    A.tasks = p.wtasks.d + n_init;
+    for (uint32_t s = 0; s < chunk; s++) {
+        A.step = s;
+        A.acc_rd = arena[p.cur];
+        A.acc_wr = arena[p.cur ^ 1];
+        dev::launch_wide_step(N, npr, c->keys, A, (uint32_t)n_step, p.st);
+        p.cur ^= 1;
+    }
+    std::vector<Active> keep;
+    p.finishing.clear();
+    for (auto &a : p.active) {
+        if (a.step + chunk >= n) p.finishing.push_back(a);
+        else {
+            a.step += chunk;
+            keep.push_back(a);
+        }
+    }
+    p.active.swap(keep);
+    const size_t F = p.finishing.size();
+    if (F) {
+        p.woff.reserve(F);
+        p.qout.reserve(F);
+        p.out.reserve(F * W);
+        for (size_t k = 0; k < F; k++) {
+            p.woff.h[k] = (uint64_t)p.finishing[k].unit * unit_words;
+            p.qout.h[k] = c->tables[p.finishing[k].table].q_in;
+        }
+        SRV_HIP(hipMemcpyAsync(p.woff.d, p.woff.h, F * 8, hipMemcpyHostToDevice, p.st));
+        SRV_HIP(hipMemcpyAsync(p.qout.d, p.qout.h, F * 4, hipMemcpyHostToDevice, p.st));
+        const KsSched ks = ks_default(*c, d, F);
+        const size_t need = ks_part_words(*c, ks, F);
+        if (p.part_cap < need || p.ext_cap < F) {
+            SRV_HIP(hipStreamSynchronize(p.st));
+            if (p.part_cap < need) {
+                if (p.part) SRV_HIP(hipFree(p.part));
+                p.part = nullptr;
+                p.part_cap = 0;
+                if (hipMalloc((void **)&p.part, need * 2 * 8) != hipSuccess)
+                    throw Error(MM_ENOMEM, "server key-switch buffer");
+                p.part_cap = need * 2;
+            }
+            if (p.ext_cap < F) {
+                if (p.ext) SRV_HIP(hipFree(p.ext));
+                p.ext = nullptr;
+                p.ext_cap = 0;
+                if (hipMalloc((void **)&p.ext, F * 2 * (N + 1) * 4) != hipSuccess)
+                    throw Error(MM_ENOMEM, "server extraction buffer");
+                p.ext_cap = F * 2;
+            }
+        }
+        A.acc_rd = arena[p.cur];
+        dev::launch_wide_extract(N, npr, A, p.woff.d, F, p.ext, p.st);
+        enqueue_keyswitch(*c, d, p.ext, nullptr, F, p.out.d, p.qout.d, 0, ks, p.part, p.st);
         SRV_HIP(hipMemcpyAsync(p.out.h, p.out.d, F * W * 4, hipMemcpyDeviceToHost, p.st));
     }
     SRV_HIP(hipGetLastError());

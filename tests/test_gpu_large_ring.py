@@ -246,9 +246,11 @@ def test_r_too_wide_for_a_workgroup_runs_the_global_path():
     np.testing.assert_array_equal(out[:2], oracle.bootstrap_many(c.p, 4, c.keys.bsk, c.keys.ksk, V, q, q, ct))
     np.testing.assert_array_equal(out[2:], oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V1, 2 * 4096,
                                                                  2 * 4096, ct1))
-    with pytest.raises(b.MMError) as e:
-        c.ctx.schedule_count(ids)  # one schedule on this path
-    assert e.value.code == b.MM_EINVAL
+    n = c.ctx.schedule_count(ids)  # one blind-rotation shape: key-switch candidates only
+    assert all(c.ctx.schedule_describe(ids, k)[0] == 0 for k in range(n))
+    for k in range(n):
+        c.ctx.set_schedule(ids, k)
+        np.testing.assert_array_equal(c.ctx.bootstrap(ids, cts), out, err_msg=f"schedule {k}")
 
 
 @pytest.mark.parametrize("ternary,r", [(False, 16), (True, 12)])
@@ -288,10 +290,16 @@ def test_bootstrap_16384(plain):
         for j in range(2):
             np.testing.assert_array_equal(got[j * 2 * 16384:(j + 1) * 2 * 16384].reshape(1, 2, 16384),
                                           oracle.blind_rotate(c.p, 1, c.keys.bsk, V, ct[j], 2), err_msg=f"ct {j}")
-        with pytest.raises(b.MMError):
-            c.ctx.server_start(64 << 20)
     out = c.ctx.bootstrap([tid] * 2, ct, plain=plain)
     np.testing.assert_array_equal(out, oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    if not plain:
+        # served on the global-accumulator path (chunk 3 does not divide n = 4)
+        srv = c.ctx.server_start(64 << 20, chunk_steps=3)
+        try:
+            got, lat = srv.replay(np.full(2, tid, np.int32), ct, np.array([0, 1000000], np.int64))
+        finally:
+            srv.stop()
+        np.testing.assert_array_equal(got, out)
     np.testing.assert_array_equal(c.ctx.bootstrap([tid] * 2, ct, q_out=Q, plain=plain),
                                   oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, Q, ct))
 

@@ -222,9 +222,67 @@ def test_wide_empty_and_rejected_calls():
     with pytest.raises(b.MMError):
         c.ctx.external_product(0, np.zeros((1, 2, 256), np.uint32))
     with pytest.raises(b.MMError):
-        c.ctx.server_start(64 << 20)
-    with pytest.raises(b.MMError):
-        c.ctx.schedule_count([tid])
+        c.ctx.server_start(1 << 10)  # below one component's two accumulators
+
+
+def test_wide_schedules_give_the_same_bits_and_autotune():
+    """At the wide modulus the blind rotation has one shape (reported as 0 waves per
+    fused group, one workgroup of N / 512 waves per component); the schedules differ in
+    the key switch, every one gives the oracle's bits, and autotuning picks one of them."""
+    c = case(256, 8)
+    r, t = 2, 16
+    q = 2 * 256 * r
+    tid, f, V = c.table(t, r, 31)
+    ct = c.encrypt(q, t, messages(t, 70, 32), 33)
+    ids = np.full(len(ct), tid, np.int32)
+    n = c.ctx.schedule_count(ids)
+    desc = [c.ctx.schedule_describe(ids, k) for k in range(n)]
+    say("wide schedules:", desc)
+    assert n >= 2 and all(d[0] == 0 and d[3] == 1 and d[5] == 0 for d in desc)
+    assert {d[4] for d in desc} >= {0, 1}  # i-split and LDS-tiled key switches
+    want = oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct)
+    for k in range(n):
+        c.ctx.set_schedule(ids, k)
+        np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), want, err_msg=f"schedule {k}")
+    choice = c.ctx.autotune(ids, ct)
+    assert 0 <= choice < n
+    assert c.ctx.schedule_describe(ids) == desc[choice]
+    np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), want)
+
+
+@pytest.mark.parametrize("N,ternary", [(256, False), (512, True)])
+def test_wide_serving_matches_alone_and_oracle(N, ternary):
+    """Continuous batching at the wide modulus: a Poisson trace over tables of r = 1, 3
+    and 16 through a server whose budget holds fewer components than arrive, so requests
+    wait for memory and join running ticks; chunk_steps = 3 does not divide n = 8, so
+    ciphertexts finish inside a tick.  Every result equals the same ciphertext
+    bootstrapped alone and, for two per table, the oracle's."""
+    from synth import poisson_arrivals
+    c = case(N, 8, ternary)
+    tabs = []
+    for k, r in enumerate((1, 3, 16)):
+        t = max(2, 2 * N * r // 128)
+        tid, f, V = c.table(t, r, 140 + k)
+        q = 2 * N * r
+        tabs.append((tid, t, r, q, V, c.encrypt(q, t, messages(t, 12, 150 + k), 160 + k)))
+    order = np.random.default_rng(170).permutation(36)
+    ids = np.array([tabs[k // 12][0] for k in order], np.int32)
+    cts = np.stack([tabs[k // 12][5][k % 12] for k in order])
+    per_comp = 2 * 2 * 2 * N * 4  # two arenas x (a, b) x two residues
+    budget = 40 * (per_comp + (9 + N + 1) * 4 + 9 * 8)  # 40 components for 36 requests of up to 16
+    srv = c.ctx.server_start(budget, chunk_steps=3)
+    try:
+        say("wide serving N", N, "ternary", ternary)
+        out, lat = srv.replay(ids, cts, poisson_arrivals(2000.0, len(ids), 171))
+        st = srv.stats()
+    finally:
+        srv.stop()
+    assert st["completed"] == len(ids) and np.all(lat > 0)
+    for tid, t, r, q, V, ct in tabs:
+        sel = ids == tid
+        np.testing.assert_array_equal(out[sel], c.ctx.bootstrap(ids[sel], cts[sel]), err_msg=f"r = {r}")
+        np.testing.assert_array_equal(out[sel][:2], oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q,
+                                                                          cts[sel][:2]), err_msg=f"oracle r = {r}")
 
 
 @pytest.fixture(scope="module")
@@ -280,6 +338,29 @@ def test_paper_margin_noisy_batch_decrypts_at_t_4096(margin):
     err = (ph - f[m].astype(np.int64) * (q // t)) % q
     err = np.where(err > q // 2, err - q, err)
     assert np.max(np.abs(err)) < 32
+
+
+def test_paper_margin_serving_matches_alone_and_decrypts(margin):
+    """The paper-margin shape served: noisy requests at t = 2^12 (r = 128, n = 512,
+    N = 2048, ternary, 54-bit ring) through the server in ticks of 64 CMux steps;
+    every result equals the batched bootstrap of the same ciphertexts and decrypts."""
+    from synth import poisson_arrivals
+    c, pre = margin
+    t, r = pre["t"], pre["r"]
+    q = 2 * c.p.N * r
+    tid, f, V = c.table(t, r, 35)
+    m = messages(t, 6, 36)
+    ct = c.encrypt(q, t, m, 37)
+    ids = np.full(len(m), tid, np.int32)
+    srv = c.ctx.server_start(256 << 20, chunk_steps=64)
+    try:
+        say("paper-margin serving of", len(m))
+        out, lat = srv.replay(ids, ct, poisson_arrivals(100.0, len(m), 38))
+    finally:
+        srv.stop()
+    say("latency ms", np.round(lat, 1))
+    np.testing.assert_array_equal(out, c.ctx.bootstrap(ids, ct))
+    np.testing.assert_array_equal(oracle.decrypt(c.p.n, q, t, c.keys.s, out), f[m])
 
 
 def test_wide_maximum_r_1024():
