@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--margin", type=int, default=16384,
                     help="ring components per batch of the paper-margin sweep (0: no such leg)")
     ap.add_argument("--margin-logt", default="5,6,7,8,9,10,11,12,13,14,15", help="log2 t of the paper-margin sweep")
+    ap.add_argument("--margin-serve-requests", type=int, default=64,
+                    help="requests of the paper-margin serving run at t = 2^12 (0: none)")
+    ap.add_argument("--margin-serve-rate", type=float, default=50.0, help="its Poisson arrival rate, req/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -332,11 +335,9 @@ def main():
             ids_c = np.full(C, tid_c, np.int32)
             din = torch.from_numpy(cts.view(np.int32)).cuda()
             dout = torch.empty_like(din)
-            try:
-                cx.autotune(ids_c, cts)
-                path = "fused"
-            except binding.MMError:  # the global-accumulator path has one schedule
-                path = "global accumulator"
+            cx.autotune(ids_c, cts)
+            # 0 waves per fused group: the global-accumulator path (key-switch schedules only)
+            path = "global accumulator" if cx.schedule_describe(ids_c)[0] == 0 else "fused"
             cx.bootstrap(ids_c, din, out=dout)
             torch.cuda.synchronize()
             reps = max(1, min(args.steps, 3))
@@ -565,6 +566,32 @@ def margin_leg(args, binding, torch):
             row["paper_identity_s"] = {"value": sec, "source": where, "hardware": "one CPU thread (PALISADE)"}
         rows.append(row)
         print(json.dumps({"paper_margin_row": row}), file=sys.stderr, flush=True)
+    # serving at t = 2^12 (r = 128): continuous batching on the global-accumulator path
+    serve = None
+    if args.margin_serve_requests > 0:
+        from synth import poisson_arrivals
+        t, R = 1 << 12, args.margin_serve_requests
+        r = t * 128 // (2 * pw.N)
+        q = 2 * pw.N * r
+        f = negacyclic_table(t, t, 512)
+        tid = mctx.table_create(t, t, r, f)
+        ed = enc_draws(pw.n, q, R, 950)
+        m = messages(t, R, 951)
+        cts = mctx.encrypt(q, t, m, ed["a"], ed["e"])
+        ids = np.full(R, tid, np.int32)
+        batched = mctx.bootstrap(ids, cts)
+        srv = mctx.server_start(8 << 30, chunk_steps=64)
+        try:
+            out, lat = srv.replay(ids, cts, poisson_arrivals(args.margin_serve_rate, R, 952))
+            st = srv.stats()
+        finally:
+            srv.stop()
+        serve = {"t": t, "r": r, "requests": R, "rate_req_s": args.margin_serve_rate, "chunk_steps": 64,
+                 "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                 "completed_per_s": round(st["boots_per_s"], 2),
+                 "identical_to_batched": bool(np.array_equal(out, batched)),
+                 "correct": bool(np.array_equal(mctx.decrypt(q, t, out), f[m]))}
+        print(json.dumps({"paper_margin_serving": serve}), file=sys.stderr, flush=True)
     mctx.close()
     return {"params": {"n": pw.n, "N": pw.N, "log2_Q": int(pw.Q_ring).bit_length(), "Q": [pw.Q, pw.Q2],
                        "log2_B": pw.log2_B, "l": pw.l, "log2_Bks": pw.log2_Bks, "l_ks": pw.l_ks,
@@ -573,7 +600,7 @@ def margin_leg(args, binding, torch):
             "parity": ("rows are checked by decryption only; the kernels they time are compared bit for bit with "
                        "the oracle in tests/test_gpu_wide.py: this preset's r = 128 (3 CMux steps) and r = 1024 "
                        "(2 steps), and whole ternary bootstraps at N = 2048 with small n"),
-            "rows": rows}
+            "rows": rows, "serving": serve}
 
 
 if __name__ == "__main__":
