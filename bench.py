@@ -133,8 +133,8 @@ def main():
                     help="batch of the MMPM vs TFHE-shaped comparison per class (0: no comparison leg)")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
-    ap.add_argument("--serve-max-wait", type=float, default=20.0,
-                    help="admission bound on the expected queueing delay, ms, for the load-shedding runs (0: none)")
+    ap.add_argument("--serve-max-latency", type=float, default=50.0,
+                    help="admission bound on the expected latency, ms, for the load-shedding runs (0: none)")
     ap.add_argument("--margin", type=int, default=16384,
                     help="ring components per batch of the paper-margin sweep (0: no such leg)")
     ap.add_argument("--margin-logt", default="5,6,7,8,9,10,11,12,13,14,15", help="log2 t of the paper-margin sweep")
@@ -384,7 +384,7 @@ def main():
         alone = None
         serving = {"rates_req_s": [], "p50_ms": [], "p99_ms": [], "completed_per_s": [], "requests_per_rate": R,
                    "classes": [list(c) for c in CLASS_MIX], "chunk_steps": 63, "hbm_budget_bytes": 4 << 30}
-        serving["admission"] = {"max_wait_ms": args.serve_max_wait, "rates_req_s": [], "admitted_fraction": [],
+        serving["admission"] = {"max_latency_ms": args.serve_max_latency, "rates_req_s": [], "admitted_fraction": [],
                                 "p50_ms": [], "p99_ms": [], "completed_per_s": [], "identical_to_alone": True}
         for rate in [float(x) for x in args.serve_rates.split(",") if x]:
             srv = ctx.server_start(4 << 30, chunk_steps=63)
@@ -402,11 +402,11 @@ def main():
             if alone is None:
                 alone = ctx.bootstrap(s_ids, s_ct)
                 serving["identical_to_alone"] = bool(np.array_equal(out_s, alone))
-            if args.serve_max_wait > 0:
-                # the same trace with load shedding: requests whose expected queueing delay
-                # exceeds the bound are refused at submission
+            if args.serve_max_latency > 0:
+                # the same trace with load shedding: requests whose expected latency exceeds
+                # the bound are refused at submission
                 srv = ctx.server_start(4 << 30, chunk_steps=63)
-                srv.set_admission(args.serve_max_wait)
+                srv.set_admission(args.serve_max_latency)
                 out_a, lat_a = srv.replay(s_ids, s_ct, poisson_arrivals(rate, R, 12))
                 st_a = srv.stats()
                 srv.stop()

@@ -327,13 +327,15 @@ int mm_poll(mm_server *s, uint64_t ticket, uint32_t *ct_out);
 int mm_server_stats(mm_server *s, double *p50_ms, double *p99_ms, double *boots_per_s,
                     uint64_t *completed);
 
-/* Admission by expected queueing delay (load shedding): with max_wait_ms > 0,
- * mm_submit refuses a request with MM_EBUSY when the requests already queued
- * would take longer than max_wait_ms to be admitted at the server's recent
- * completion rate (its last 512 completions); 0 (the default) admits every
- * request while the queue has room.  mm_server_refused reports how many
- * requests admission has refused since the server started. */
-int mm_server_set_admission(mm_server *s, double max_wait_ms);
+/* Admission by expected latency (load shedding): with max_latency_ms > 0,
+ * mm_submit refuses a request with MM_EBUSY when the requests queued and in
+ * flight, divided by the server's recent completion rate (its last 4096
+ * completions, counted up to the time of the call), exceed max_latency_ms: by Little's law the time a request
+ * admitted now can expect to wait for its result.  The check starts after 64
+ * completions; 0 (the default) admits every request while the queue has room.
+ * mm_server_refused reports how many requests admission has refused since the
+ * server started. */
+int mm_server_set_admission(mm_server *s, double max_latency_ms);
 int mm_server_refused(mm_server *s, uint64_t *refused);
 
 /* Stop the server after its in-flight work completes. */

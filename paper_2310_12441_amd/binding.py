@@ -388,9 +388,10 @@ class Server:
         self._check(lib.mm_server_stats(self.h, C.byref(p50), C.byref(p99), C.byref(bps), C.byref(done)))
         return {"p50_ms": p50.value, "p99_ms": p99.value, "boots_per_s": bps.value, "completed": done.value}
 
-    def set_admission(self, max_wait_ms: float):
-        """Refuse requests whose expected queueing delay exceeds max_wait_ms (0: off)."""
-        self._check(lib.mm_server_set_admission(self.h, float(max_wait_ms)))
+    def set_admission(self, max_latency_ms: float):
+        """Refuse requests whose expected latency (queued and in-flight requests over the recent
+        completion rate) exceeds max_latency_ms (0: off)."""
+        self._check(lib.mm_server_set_admission(self.h, float(max_latency_ms)))
 
     def refused(self) -> int:
         n = C.c_uint64()

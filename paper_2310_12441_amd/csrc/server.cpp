@@ -180,12 +180,14 @@ struct Server {
     size_t lat_next = 0;
     static constexpr size_t LAT_CAP = size_t(1) << 20;
     uint64_t next_ticket = 1, completed = 0, refused = 0;
-    // admission by expected queueing delay (0: off): a request is refused when the
-    // requests already queued would take longer than max_wait_ms to be admitted at
-    // the recent completion rate (the last RECENT completions)
-    double max_wait_ms = 0.0;
+    // admission by expected latency (0: off): a request is refused when the
+    // requests queued and in flight, over the recent completion rate (the last
+    // RECENT completions up to now), exceed max_latency_ms (Little's law: that quotient is
+    // the time a request admitted now can expect to wait for its result)
+    double max_latency_ms = 0.0;
+    uint64_t in_flight = 0;  // admitted to device slots, result not harvested
     std::deque<clk::time_point> recent;
-    static constexpr size_t RECENT = 512;
+    static constexpr size_t RECENT = 4096;
     bool have_first = false;
     clk::time_point t_first, t_last;
     std::atomic<bool> stop{false};
@@ -310,11 +312,13 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
         *rc = MM_EBUSY;
         return 0;
     }
-    if (max_wait_ms > 0 && recent.size() >= 64) {
-        const double span = std::chrono::duration<double, std::milli>(recent.back() - recent.front()).count();
-        const double per_ms = span > 0 ? (double)(recent.size() - 1) / span : 0.0;
-        const double queued = (double)(pending[0].size() + pending[1].size());
-        if (per_ms > 0 && queued / per_ms > max_wait_ms) {
+    if (max_latency_ms > 0 && recent.size() >= 64) {
+        // completions arrive in bursts (a tick at a time): the rate is taken up to now,
+        // not up to the last burst, over a window of several ticks
+        const double span = std::chrono::duration<double, std::milli>(clk::now() - recent.front()).count();
+        const double per_ms = span > 0 ? (double)recent.size() / span : 0.0;
+        const double backlog = (double)(pending[0].size() + pending[1].size() + in_flight);
+        if (per_ms > 0 && backlog / per_ms > max_latency_ms) {
             refused++;
             *rc = MM_EBUSY;
             return 0;
@@ -353,6 +357,7 @@ bool Server::harvest(Part &p)
         free_slots.push_back(a.slot);
         buddy.release(a.unit, a.order);
         completed++;
+        in_flight--;
         recent.push_back(now);
         if (recent.size() > RECENT) recent.pop_front();
     }
@@ -385,6 +390,7 @@ void Server::launch(Part &p)
                 if (unit < 0) break;  // no accumulator memory: wait for completions
                 Active a{q.ticket, q.table, free_slots.back(), (uint32_t)unit, order, 0, q.t0};
                 free_slots.pop_back();
+                in_flight++;
                 fresh.push_back(a);
                 fresh_req.push_back(std::move(queue.front()));
                 queue.pop_front();
@@ -684,11 +690,11 @@ int mm_poll(mm_server *h, uint64_t ticket, uint32_t *ct_out)
     return MM_OK;
 }
 
-int mm_server_set_admission(mm_server *h, double max_wait_ms)
+int mm_server_set_admission(mm_server *h, double max_latency_ms)
 {
-    if (!h || !h->s || !(max_wait_ms >= 0)) return MM_EINVAL;
+    if (!h || !h->s || !(max_latency_ms >= 0)) return MM_EINVAL;
     std::lock_guard<std::mutex> g(h->s->mu);
-    h->s->max_wait_ms = max_wait_ms;
+    h->s->max_latency_ms = max_latency_ms;
     return MM_OK;
 }
 
@@ -780,7 +786,7 @@ int mm_server_replay(mm_server *h, const int *table_ids, const uint32_t *ct_in, 
             bool shedding;
             {
                 std::lock_guard<std::mutex> g(s.mu);
-                shedding = s.max_wait_ms > 0;
+                shedding = s.max_latency_ms > 0;
             }
             if (shedding) {  // refused by admission: recorded, not retried
                 refused[k] = 1;

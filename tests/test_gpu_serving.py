@@ -94,7 +94,7 @@ def test_replay_poisson_trace_small_budget(setup):
 
 
 def test_admission_sheds_load_and_admitted_results_are_exact(setup):
-    """Arrivals far above capacity with admission by expected queueing delay on:
+    """Arrivals far above capacity with admission by expected latency on:
     some requests are refused (latency -1, zero output, counted by the server),
     every admitted one equals the same ciphertext bootstrapped alone."""
     p, ctx, tabs, keys, b = setup
@@ -103,7 +103,7 @@ def test_admission_sheds_load_and_admitted_results_are_exact(setup):
     srv = ctx.server_start(24 << 20, chunk_steps=63)
     with pytest.raises(b.MMError):
         srv.set_admission(-1.0)
-    srv.set_admission(10.0)
+    srv.set_admission(40.0)
     out, lat = srv.replay(ids, cts, arrivals)
     st = srv.stats()
     refused = srv.refused()
