@@ -131,6 +131,8 @@ def main():
                     help="ciphertexts of the uneven-class batch (0: no mixed leg)")
     ap.add_argument("--compare", type=int, default=4096,
                     help="batch of the MMPM vs TFHE-shaped comparison per class (0: no comparison leg)")
+    ap.add_argument("--compare-max-logt", type=int, default=16,
+                    help="largest log2 t of the TFHE-shaped comparison (15: N = 16384, 16: 32768, 17: 65536)")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
     ap.add_argument("--serve-max-latency", type=float, default=50.0,
@@ -148,6 +150,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); ciphertexts are independent, "
               "so more GPUs would each bootstrap their own share with a replica of the keys", flush=True)
         sys.exit(2)
+    t_start = time.perf_counter()
 
     import torch
 
@@ -254,6 +257,15 @@ def main():
         "kernel_source_sha256_16": source_hash(),
     }
 
+    legs = {"main_and_plain": round(time.perf_counter() - t_start, 1)}
+    t_leg = time.perf_counter()
+
+    def leg(name):
+        nonlocal t_leg
+        legs[name] = round(time.perf_counter() - t_leg, 1)
+        t_leg = time.perf_counter()
+        print(json.dumps({"leg_done": name, "seconds": legs[name]}), file=sys.stderr, flush=True)
+
     # ---- uneven classes: one table per (t, k), classes drawn uniformly per ciphertext
     from synth import CLASS_MIX, class_mix, poisson_arrivals
     tabs = []
@@ -321,6 +333,7 @@ def main():
                  "schedule": {"index": x_sched, "group_waves": x_desc[0], "ks_cts_per_wave": x_desc[1],
                               "ks_splits": x_desc[2], "waves_per_component": x_desc[3]}}
 
+    leg("mixed")
     # ---- Sec. 5 comparison: each class (t, k) by MMPM (N = 1024, r = k) and by one
     # ring of degree N k (r = 1, TFHE-shaped), same n, gadget and key switch
     comparison = None
@@ -347,9 +360,11 @@ def main():
             torch.cuda.synchronize()
             return round(C * reps / (time.perf_counter() - tt0), 1), path
 
-        # the four classes of the uneven batch, then t = 2^15 (r = 16 components at
-        # N = 1024 against one ring of degree 16384): both on the global-accumulator path
-        for k, (tt, rr) in enumerate(list(CLASS_MIX) + [(32768, 16)]):
+        # the four classes of the uneven batch, then t = 2^15 and up (r = 16, 32, ...
+        # components at N = 1024 against one ring of degree 1024 r): both on the
+        # global-accumulator path, rings above 16384 split into sub-rings of 8192
+        big = [(1 << lt, 1 << (lt - 11)) for lt in range(15, args.compare_max_logt + 1)]
+        for k, (tt, rr) in enumerate(list(CLASS_MIX) + big):
             row = {"t": tt, "k": rr}
             tid_m = tabs[k][0] if k < len(tabs) else ctx.table_create(tt, tt, rr, negacyclic_table(tt, tt, 100 + k))
             bps, path = timed_batch(ctx, tid_m, tt, rr, p.N, 700 + k)
@@ -372,10 +387,13 @@ def main():
             row["parity"] = {256: "same ring as the MMPM side", 1024: "tests: N = 2048 end to end",
                              4096: "tests: N = 4096 samples of a batch", 16384: "tests: the bench batch's samples "
                              "(stored oracle outputs) and N = 8192 end to end",
-                             32768: "tests: r = 16 at N = 1024 and N = 16384 end to end"}[tt]
+                             32768: "tests: r = 16 at N = 1024 and N = 16384 end to end",
+                             65536: "tests: N = 32768 end to end (split ring)",
+                             131072: "tests: N = 65536 end to end (split ring)"}[tt]
             comparison.append(row)
             print(json.dumps({"comparison_row": row}), file=sys.stderr, flush=True)
 
+    leg("comparison")
     # ---- serving: Poisson arrivals of single bootstraps with mixed (t, k), keys resident
     serving = None
     if args.serve_requests > 0:
@@ -419,6 +437,7 @@ def main():
                 adm["completed_per_s"].append(round(st_a["boots_per_s"], 1))
                 adm["identical_to_alone"] = adm["identical_to_alone"] and bool(np.array_equal(out_a[ok], alone[ok]))
 
+    leg("serving")
     # ---- the parameters of the experiments in Sec. 5 (Tables 1-2): n = 512, N = 2048,
     # ring modulus of 54 bits (two primes), gadget 2^15 x 4, q = 2Nr = 128 t, the
     # identity function on Z_t by two bootstraps (plaintext modulus 2t), noisy inputs
@@ -426,6 +445,7 @@ def main():
     if args.margin > 0:
         margin = margin_leg(args, binding, torch)
 
+    leg("paper_margin")
     # ---- CPU oracle on the host cores, on a bounded sample of the same batch
     cpu = None
     if not args.no_cpu:
@@ -450,6 +470,7 @@ def main():
                "seconds": round(cpu_s, 2), "single_thread_s_per_bootstrap": round(single_s, 3),
                "parity_with_gpu": bool(np.array_equal(want, batched_out[idx]) and np.array_equal(one, want[:1]))}
 
+    leg("cpu_baseline")
     line = {
         "metric": "bootstraps/sec at t=2^12 (batched vs plain, bit-exact); serving p50/p99 ms",
         "value": round(value, 2),
@@ -485,6 +506,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "paper_margin": margin,
+        "leg_seconds": legs,
     }
     print(json.dumps(line), flush=True)
 

@@ -132,7 +132,7 @@ void device_init(mm_ctx &c, int id)
     const mm_params &p = c.p;
     const uint32_t N = p.N, Q = p.Q;
     MM_REQUIRE(dev::device_supports_n(N) || dev::wide_supports_n(N, 1),
-               "device path supports N in {256, 512, ..., 16384}");
+               "device path supports N in {256, 512, ..., 65536}");
     MM_REQUIRE(!c.wide || dev::wide_supports_n(N, 2), "the wide-modulus path supports N in {256, ..., 4096}");
     d->qn = neg_inv_2_32(Q);
     // 2^64 / N mod Q, for the pointwise product of two forward NTTs
@@ -157,6 +157,19 @@ void device_init(mm_ctx &c, int id)
     twiddles(c.ntt, twf, twi);
     upload(&d->twf, twf.data(), N);
     upload(&d->twi, twi.data(), N);
+    if (!c.wide && dev::split_supports_n(N)) {
+        // sub-ring h's stage with m' groups uses the full table's entry M m' + h m' + i'
+        const uint32_t NS = dev::SPLIT_NS, M = N / NS;
+        std::vector<uint32_t> sf((size_t)M * NS, 0), si((size_t)M * NS, 0);
+        for (uint32_t h = 0; h < M; h++)
+            for (uint32_t mm = 1; mm < NS; mm <<= 1)
+                for (uint32_t g = 0; g < mm; g++) {
+                    sf[(size_t)h * NS + mm + g] = twf[M * mm + h * mm + g];
+                    si[(size_t)h * NS + mm + g] = twi[M * mm + h * mm + g];
+                }
+        upload(&d->twf_sub, sf.data(), sf.size());
+        upload(&d->twi_sub, si.data(), si.size());
+    }
     std::vector<uint32_t> kb, corr;
     if (!c.wide) {
         ntt_domain_keys(c, c.ntt, c.bsk.data(), kb, corr);
@@ -477,6 +490,16 @@ static bool use_global(const mm_ctx &c, const int *ids, size_t count)
 
 int primes_of(const mm_ctx &c) { return c.wide ? 2 : 1; }
 
+// Blind-rotation shapes of the global path: one workgroup per component and
+// CMux step (NTT schedule 0; rings up to 16384), or the ring split into
+// sub-rings of 8192 (schedule 3; one prime, rings of 16384 and more).
+static std::vector<int> global_shapes(const mm_ctx &c)
+{
+    if (c.wide || !dev::split_supports_n(c.p.N)) return {0};
+    if (c.p.N > 16384) return {3};
+    return {0, 3};
+}
+
 // Two waves per component (N = 512, 1024, r <= 4): for batches that do not
 // fill every compute unit, both waves of a slot share one component's work.
 static bool wide_slots_ok(const mm_ctx &c, const int *ids, size_t count)
@@ -511,9 +534,8 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
         for (uint32_t P : {2u, 3u, 4u, 6u}) add(KsSched{KS_LANES, P});
     if (count < 256) ks.push_back(KsSched{0, ks_splits(c, d, count)});
     if (use_global(c, ids, count)) {
-        // one blind-rotation shape (a workgroup per component and CMux step): the
-        // candidates differ in the key switch only
-        for (auto &k : ks) out.push_back(Sched{0, k});
+        for (int shape : global_shapes(c))
+            for (auto &k : ks) out.push_back(Sched{0, k, shape == 3 ? dev::SPLIT_WAVES : 0, shape});
         return out;
     }
     for (int gw : {8, 4}) {
@@ -542,7 +564,10 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         auto cand = candidates(c, d, ids, count);
         if (it->second >= 0 && (size_t)it->second < cand.size()) return cand[it->second];
     }
-    if (use_global(c, ids, count)) return Sched{0, ks_default(c, d, count)};
+    if (use_global(c, ids, count)) {
+        const int shape = global_shapes(c).front();
+        return Sched{0, ks_default(c, d, count), shape == 3 ? dev::SPLIT_WAVES : 0, shape};
+    }
     // untuned: 2-wave slots while the components fit half-full groups on every
     // compute unit (the chip is not full), else the full-width default
     const bool light = sum_r(c, ids, count) <= 4ull * (uint64_t)d.num_cu;
@@ -624,7 +649,7 @@ static void run_sequence(Device &d, const std::string &key, bool use_graph, hipS
 }
 
 static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
-                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st, const KsSched &ks);
+                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st, const Sched &S);
 
 // The batched path for ciphertexts already on the device.
 static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
@@ -632,7 +657,7 @@ static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t
 {
     if (use_global(c, ids, count)) {
         const Sched S = force ? *force : schedule_for(c, d, ids, count);
-        bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st, S.ks);
+        bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st, S);
         return;
     }
     const uint32_t N = c.p.N;
@@ -735,7 +760,20 @@ static void upload_wide(Device &d, const std::vector<dev::WideTask> &tasks, cons
     HIPC(hipEventRecord(d.pin[0].ev, st));
 }
 
-// ACC init and `steps` CMux launches; returns the buffer holding the result.
+// The split-ring buffers (digit polynomials, sub-ring products) of num_tasks
+// components, from the workspace, into A; before any capture.
+static void split_buffers(const mm_ctx &c, Device &d, dev::WideArgs &A, size_t num_tasks)
+{
+    const size_t N = c.p.N;
+    A.M = (uint32_t)(N / dev::SPLIT_NS);
+    A.dig = (uint32_t *)ws(d, WS_DIG, num_tasks * c.keys * c.p.l * 2 * N * 4);
+    A.outb = (uint32_t *)ws(d, WS_OUTB, num_tasks * 2 * N * 4);
+    A.twf_sub = d.twf_sub;
+    A.twi_sub = d.twi_sub;
+}
+
+// ACC init and `steps` CMux launches (three per step for a split ring, A.M > 0);
+// returns the buffer holding the result.
 static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_t *buf0, uint32_t *buf1,
                                        uint32_t num_tasks, uint32_t steps, hipStream_t s)
 {
@@ -747,15 +785,17 @@ static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_
         A.step = i;
         A.acc_rd = buf[i & 1];
         A.acc_wr = buf[(i + 1) & 1];
-        dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s);
+        if (A.M) dev::launch_split_step(N, c.keys, A, num_tasks, s);
+        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s);
     }
     return buf[steps & 1];
 }
 
 static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count,
-                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st, const KsSched &ks)
+                           uint32_t *d_out, uint32_t q_out, bool use_graph, hipStream_t st, const Sched &S)
 {
     const uint32_t N = c.p.N;
+    const KsSched &ks = S.ks;
     std::vector<dev::WideTask> tasks;
     std::vector<uint64_t> offs;
     const uint64_t words = wide_tasks(c, ids, count, tasks, offs);
@@ -765,14 +805,15 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
     uint64_t *part = (uint64_t *)ws(d, WS_PART, ks_part_words(c, ks, count) * 8);
     uint32_t *acc0 = (uint32_t *)ws(d, WS_ACC, words * 4);
     uint32_t *acc1 = (uint32_t *)ws(d, WS_ACC2, words * 4);
+    dev::WideArgs A = wide_args(c, d);
+    if (S.ntt == 3) split_buffers(c, d, A, tasks.size());
     dev::WideTask *dt;
     uint64_t *doff;
     upload_wide(d, tasks, offs, &dt, &doff, st);
-    dev::WideArgs A = wide_args(c, d);
     A.tasks = dt;
     A.ct_in = d_in;
     const uint32_t nt = (uint32_t)tasks.size();
-    const std::string key = "wide/" + std::to_string(count) + "/" + std::to_string(nt) + "/" +
+    const std::string key = "wide/" + std::to_string(S.ntt) + "/" + std::to_string(count) + "/" + std::to_string(nt) + "/" +
                             std::to_string(ks.cpw) + "/" + std::to_string(ks.P) + "/" + std::to_string(q_scalar) +
                             "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
                             std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
@@ -794,10 +835,11 @@ static void blind_rotate_wide(mm_ctx &c, Device &d, const int *ids, const uint32
     const uint64_t words = wide_tasks(c, ids, count, tasks, offs);
     uint32_t *acc0 = (uint32_t *)ws(d, WS_ACC, words * 4);
     uint32_t *acc1 = (uint32_t *)ws(d, WS_ACC2, words * 4);
+    dev::WideArgs A = wide_args(c, d);
+    if (schedule_for(c, d, ids, count).ntt == 3) split_buffers(c, d, A, tasks.size());
     dev::WideTask *dt;
     uint64_t *doff;
     upload_wide(d, tasks, offs, &dt, &doff, st);
-    dev::WideArgs A = wide_args(c, d);
     A.tasks = dt;
     A.ct_in = d_in;
     const uint32_t nt = (uint32_t)tasks.size();
@@ -1041,28 +1083,49 @@ void describe_schedule(mm_ctx &c, const int *ids, size_t count, int choice, int 
     if (wpp) *wpp = S.wpp ? S.wpp : (S.gw == 0 ? dev::wide_waves_per_poly(c.p.N) : dev::waves_per_poly(c.p.N));
 }
 
-// The global-accumulator path has one blind-rotation shape: run the batch once,
-// then time each key-switch candidate on its extracted samples.
+// The global-accumulator path: time each blind-rotation shape (at N = 16384 one
+// workgroup per component, or the ring split into sub-rings) with the default key
+// switch, one untimed run first; then each key-switch candidate on the samples the
+// last run extracted.
 static int autotune_global(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, uint32_t *d_out,
                            size_t count)
 {
     hipStream_t st = d.own;
     auto cand = candidates(c, d, ids, count);
-    bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &cand[0]);
-    // the samples extracted by that run stay in the workspace (allocated before any
-    // later workspace request of this function, so not moved)
-    const uint32_t *ext = (const uint32_t *)ws(d, WS_EXT, count * (c.p.N + 1) * 4);
-    size_t part_words = 0;
-    for (auto &S : cand) part_words = std::max(part_words, ks_part_words(c, S.ks, count));
-    uint64_t *part = (uint64_t *)ws(d, WS_PART, part_words * 8);
-    HIPC(hipStreamSynchronize(st));
     hipEvent_t ev[2];
     HIPC(hipEventCreate(&ev[0]));
     HIPC(hipEventCreate(&ev[1]));
-    int choice = 0;
-    float best = 1e30f;
+    int best_shape = cand[0].ntt;
+    size_t best_k = 0;
     try {
+        const std::vector<int> shapes = global_shapes(c);
+        float best = 1e30f;
+        for (int shape : shapes) {
+            size_t k0 = 0;
+            while (cand[k0].ntt != shape) k0++;  // the shape's first candidate: the default key switch
+            bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &cand[k0]);
+            if (shapes.size() == 1) break;
+            HIPC(hipEventRecord(ev[0], st));
+            bootstrap_batch(c, d, ids, d_in, count, d_out, 0, false, st, &cand[k0]);
+            HIPC(hipEventRecord(ev[1], st));
+            HIPC(hipEventSynchronize(ev[1]));
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            if (ms < best) {
+                best = ms;
+                best_shape = shape;
+            }
+        }
+        // the extracted samples of the last run stay in the workspace (a later
+        // request for the same slot and size returns the same buffer)
+        const uint32_t *ext = (const uint32_t *)ws(d, WS_EXT, count * (c.p.N + 1) * 4);
+        size_t part_words = 0;
+        for (auto &S : cand) part_words = std::max(part_words, ks_part_words(c, S.ks, count));
+        uint64_t *part = (uint64_t *)ws(d, WS_PART, part_words * 8);
+        HIPC(hipStreamSynchronize(st));
+        float best_ks = 1e30f;
         for (size_t k = 0; k < cand.size(); k++) {
+            if (cand[k].ntt != best_shape) continue;
             enqueue_keyswitch(c, d, ext, nullptr, count, d_out, nullptr, c.p.Q, cand[k].ks, part, st);
             HIPC(hipEventRecord(ev[0], st));
             enqueue_keyswitch(c, d, ext, nullptr, count, d_out, nullptr, c.p.Q, cand[k].ks, part, st);
@@ -1070,9 +1133,9 @@ static int autotune_global(mm_ctx &c, Device &d, const int *ids, const uint32_t 
             HIPC(hipEventSynchronize(ev[1]));
             float ms = 0;
             HIPC(hipEventElapsedTime(&ms, ev[0], ev[1]));
-            if (ms < best) {
-                best = ms;
-                choice = (int)k;
+            if (ms < best_ks) {
+                best_ks = ms;
+                best_k = k;
             }
         }
     } catch (...) {
@@ -1082,8 +1145,8 @@ static int autotune_global(mm_ctx &c, Device &d, const int *ids, const uint32_t 
     }
     HIPC(hipEventDestroy(ev[0]));
     HIPC(hipEventDestroy(ev[1]));
-    d.tuned[shape_key(c, ids, count)] = choice;
-    return choice;
+    d.tuned[shape_key(c, ids, count)] = (int)best_k;
+    return (int)best_k;
 }
 
 // Time each blind-rotation shape (group width, waves per component; with the

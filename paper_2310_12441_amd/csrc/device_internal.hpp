@@ -23,6 +23,7 @@ namespace mm {
 enum WsSlot {
     WS_IN, WS_IN2, WS_OUT, WS_TASKS, WS_EXT, WS_PART, WS_ACC, WS_QOUT, WS_GEN1, WS_GEN2, WS_GENQ,
     WS_ACC2, WS_WOFF,  // wide modulus: second accumulator buffer, per-ciphertext accumulator offsets
+    WS_DIG, WS_OUTB,   // split rings: digit polynomials, sub-ring products
     WS_COUNT
 };
 
@@ -42,6 +43,7 @@ struct Device {
     uint32_t qn = 0, c_fix = 0;
     uint32_t *bsk = nullptr, *bsk_corr = nullptr, *ksk = nullptr, *twf = nullptr, *twi = nullptr, *tv = nullptr;
     uint32_t *twf2 = nullptr, *twi2 = nullptr, qn2 = 0;  // second prime of a wide ring modulus
+    uint32_t *twf_sub = nullptr, *twi_sub = nullptr;     // split rings: per-sub-ring twiddles
     size_t tv_words = 0, tables_uploaded = 0;
     DevBuf ws[WS_COUNT];
     PinBuf pin[2];
@@ -70,7 +72,7 @@ struct Device {
             if (b.ev) hipEventDestroy(b.ev);
         }
         for (void *p : {(void *)bsk, (void *)bsk_corr, (void *)ksk, (void *)twf, (void *)twi, (void *)tv,
-                        (void *)twf2, (void *)twi2})
+                        (void *)twf2, (void *)twi2, (void *)twf_sub, (void *)twi_sub})
             if (p) hipFree(p);
         for (auto &e : tev)
             if (e) hipEventDestroy(e);
@@ -91,12 +93,13 @@ struct KsSched {
 };
 
 // A batch schedule: blind-rotation group width (8 or 4 waves; 0 on the
-// global-accumulator path, which has one blind-rotation shape), waves per
+// global-accumulator path), waves per
 // component polynomial (0: the ring's default), key switch, and the NTT stage
 // schedule (0: every cross-lane exchange through LDS, the two polys of an NTT
 // in lockstep; 1: the last exchange by wavefront lane swaps; 2: LDS exchanges
 // with the two polys staggered so that one's relayout overlaps the other's
-// butterflies).
+// butterflies; 3, global path only: the ring split into sub-rings of 8192, the
+// stages that mix them in separate kernels through device memory).
 struct Sched {
     int gw = 8;
     KsSched ks;

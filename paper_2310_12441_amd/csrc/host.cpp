@@ -117,7 +117,7 @@ void NttTables::inverse(uint32_t *a) const
 void validate_params(const mm_params &p)
 {
     MM_REQUIRE(p.n >= 1 && p.n <= 4096, "n must be in [1, 4096]");
-    MM_REQUIRE(p.N >= 64 && p.N <= 16384 && (p.N & (p.N - 1)) == 0, "N must be a power of two in [64, 16384]");
+    MM_REQUIRE(p.N >= 64 && p.N <= 65536 && (p.N & (p.N - 1)) == 0, "N must be a power of two in [64, 65536]");
     MM_REQUIRE(p.Q > 2 && p.Q < (1u << 31), "Q must be below 2^31");
     MM_REQUIRE((p.Q - 1) % (2 * p.N) == 0, "Q must be 1 mod 2N");
     MM_REQUIRE(is_prime(p.Q), "Q must be prime");

@@ -78,7 +78,18 @@ struct WideArgs {
     const uint32_t *tv;        // test-vector arena
     const uint32_t *acc_rd;    // accumulators after step i (read)
     uint32_t *acc_wr;          // accumulators after step i + 1 (written)
+    // rings split into M sub-rings of SPLIT_NS coefficients (one prime only):
+    uint32_t M;                // sub-rings per ring (0: not split)
+    uint32_t *dig;             // digit polynomials after the stages that mix sub-rings, [task][key][u][part][N]
+    uint32_t *outb;            // products after the inverse stages within sub-rings, [task][part][N]
+    const uint32_t *twf_sub;   // [M][SPLIT_NS]: the forward twiddles of each sub-ring's remaining stages
+    const uint32_t *twi_sub;   // [M][SPLIT_NS]: the same for the inverse
 };
+
+// Sub-ring size of the split blind rotation: rings of 16384 coefficients and
+// more run their NTT stages that mix sub-rings in separate kernels through
+// device memory, and every sub-ring of 8192 coefficients in one workgroup.
+constexpr uint32_t SPLIT_NS = 8192;
 
 constexpr int KS_CTS_PER_WAVE = 4;
 constexpr int KS_TILED_MAX_ROWS = 128;  // l_ks * B_ks handled by the LDS-tiled key switch
@@ -135,6 +146,14 @@ void launch_wide_extract(uint32_t N, int npr, const WideArgs &A, const uint64_t 
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st);
 bool wide_supports_n(uint32_t N, int npr);
 int wide_waves_per_poly(uint32_t N);  // waves of one k_wide_step workgroup
+// The split CMux step (one prime, N = M SPLIT_NS with M in {2, 4, 8}): digits and
+// the forward stages that mix sub-rings into A.dig; per (task, sub-ring) the
+// remaining forward stages, the product with BSK_i and the inverse stages within
+// the sub-ring into A.outb; the inverse stages that mix sub-rings and ACC + product
+// into A.acc_wr.  A task past step n - 1 carries its component over.
+void launch_split_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st);
+bool split_supports_n(uint32_t N);
+constexpr int SPLIT_WAVES = (int)SPLIT_NS / 1024;  // waves of one sub-ring workgroup
 size_t br_lds_bytes(uint32_t N, int gw, int wpp = 0);
 void launch_external_product(uint32_t N, const uint32_t *in, uint32_t *out, size_t count, const uint32_t *K,
                              const uint32_t *twf, const uint32_t *twi, uint32_t Q, uint32_t qn, uint32_t log2B,

@@ -345,6 +345,197 @@ __global__ __launch_bounds__(256) void k_wide_export(WideArgs A, uint32_t *__res
     }
 }
 
+// ------------------------------------------------------------------ split rings
+//
+// A ring of N = M NS coefficients (NS = 8192, M = 2, 4, 8: the TFHE-shaped rings
+// of 16384 to 65536) is too large for one workgroup.  Its negacyclic NTT is the
+// standard Cooley-Tukey network (bit-reversed output, the host's order): the
+// first log2 M stages mix the M sub-rings {h NS, ..., (h + 1) NS - 1}, after which
+// sub-ring h is an NTT of NS points whose stage with m' groups uses the full
+// table's twiddles psi^bitrev(M m' + h m' + i') (twf_sub).  The inverse mirrors
+// it.  So one CMux step is three launches: digits + mixing stages (column by
+// column), the sub-ring NTTs + product + inverse sub-ring stages (one
+// workgroup per sub-ring, as k_wide_step), and the inverse mixing stages +
+// accumulation (column by column).
+
+// Stage 1 of a split CMux step: for column j (positions j + h NS of the M
+// sub-rings) the difference D = Phi(c) ACC_j - ACC_j, its digit fields, and per
+// digit polynomial the Cooley-Tukey stages with m = 1, ..., M/2 groups.
+template <int M, int KEYS>
+__global__ __launch_bounds__(256) void k_split_digits(WideArgs A)
+{
+    constexpr uint32_t NS = SPLIT_NS, N = M * NS;
+    const uint32_t task = blockIdx.y;
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;  // grid.x covers NS columns exactly
+    const WideTask T = A.tasks[task];
+    const uint32_t i = T.i0 + A.step;
+    if (i >= A.n) return;
+    const uint32_t Q = A.Q[0];
+    const ModQ m{Q, A.qn[0]};
+    const uint32_t Mr = 2u * N * T.r;
+    const uint32_t am = wide_modswitch(A.ct_in[(size_t)T.ct * A.ct_stride + i], T.q_in, Mr);
+    const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * 2 * N;
+    uint32_t *dig = A.dig + (size_t)task * KEYS * A.l * 2 * N + j;
+    const uint32_t half = (Q - 1) / 2;
+    for (int key = 0; key < KEYS; key++) {
+        const uint32_t c = key == 0 ? (Mr - am) % Mr : am;
+        const WideRow w = wide_row(c, T.r, T.comp, N);
+        const uint32_t *src = A.acc_rd + T.acc_off + (size_t)w.src * 2 * N;
+        for (int part = 0; part < 2; part++) {
+            uint32_t y[M];
+#pragma unroll
+            for (int h = 0; h < M; h++) {
+                const uint32_t idx = j + h * NS;
+                const uint32_t d = sub_q(wide_rot_load(src + part * N, idx, w, N, Q), own[part * N + idx], Q);
+                int32_t xc = d > half ? (int32_t)(d - Q) : (int32_t)d;
+                if (A.sg) xc = (xc + (1 << (A.sg - 1))) >> A.sg;
+                y[h] = (uint32_t)xc + (uint32_t)A.goff;
+            }
+            for (uint32_t u = 0; u < A.l; u++) {
+                const uint32_t sh = u * A.log2B;
+                const uint32_t mask = u + 1 == A.l ? ~0u : (1u << A.log2B) - 1;
+                uint32_t x[M];
+#pragma unroll
+                for (int h = 0; h < M; h++) x[h] = (y[h] >> sh) & mask;
+#pragma unroll
+                for (int mm = 1; mm < M; mm <<= 1) {
+                    const int tb = M / (2 * mm);  // pair distance in sub-rings
+#pragma unroll
+                    for (int g = 0; g < mm; g++) {
+                        const uint32_t wt = A.twf0[mm + g];
+#pragma unroll
+                        for (int hh = 2 * g * tb; hh < 2 * g * tb + tb; hh++) {
+                            const uint32_t uu = x[hh], v = mont_mul(x[hh + tb], wt, m);
+                            x[hh] = add_q(uu, v, Q);
+                            x[hh + tb] = sub_q(uu, v, Q);
+                        }
+                    }
+                }
+                uint32_t *o = dig + ((size_t)(key * A.l + u) * 2 + part) * N;
+#pragma unroll
+                for (int h = 0; h < M; h++) o[h * NS] = x[h];
+            }
+        }
+    }
+}
+
+// Stage 2: one workgroup per (task, sub-ring h): the remaining forward stages of
+// every digit polynomial, the product with sub-ring h of BSK_i (eq. def:gsw)
+// from the digit-offset correction, and the inverse stages within the sub-ring.
+template <int KEYS>
+__global__ __launch_bounds__(64 * SPLIT_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_split_sub(WideArgs A)
+{
+    constexpr int NS = (int)SPLIT_NS, W = SPLIT_WAVES;
+    using G = Geo<NS, W>;
+    constexpr int E = G::E;
+    // a second exchange slot, so that consecutive relayouts alternate (one barrier each)
+    constexpr bool DS = 2 * G::SLOTW * 4 <= 160 * 1024;
+    static_assert(G::SLOTW % 2 == 0, "the slot ends on an 8-byte boundary");
+    __shared__ uint64_t lds64[G::SLOTW / 2 * (DS ? 2 : 1)];
+    uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64);
+    uint32_t *const slot2 = slot + G::SLOTW;
+    int par = 0;
+    const uint32_t M = A.M, N = M * (uint32_t)NS;
+    const uint32_t task = blockIdx.x / M, h = blockIdx.x % M;
+    const WideTask T = A.tasks[task];
+    const uint32_t i = T.i0 + A.step;
+    if (i >= A.n) return;
+    const int L = threadIdx.x;
+    const ModQ m{A.Q[0], A.qn[0]};
+    const uint32_t *twf = A.twf_sub + (size_t)h * NS, *twi = A.twi_sub + (size_t)h * NS;
+    const uint32_t *dig = A.dig + (size_t)task * KEYS * A.l * 2 * N + (size_t)h * NS;
+    uint32_t out[2][E];
+    {
+        const uint32_t *corr = A.bsk_corr + (size_t)i * 2 * N + (size_t)h * NS + L * E;
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int k = 0; k < E; k++) out[part][k] = corr[part * N + k];
+    }
+    for (int key = 0; key < KEYS; key++) {
+        const uint32_t *Kp = A.bsk + ((size_t)i * KEYS + key) * (2 * A.l * 2 * N) + (size_t)h * NS + L * E;
+        for (uint32_t u = 0; u < A.l; u++) {
+            __asm__ volatile("" ::: "memory");
+            const uint32_t *db = dig + ((size_t)(key * A.l + u) * 2 + 1) * N;  // digit of b meets rows u
+            const uint32_t *da = dig + ((size_t)(key * A.l + u) * 2 + 0) * N;  // digit of a meets rows l + u
+            uint32_t pd[2][E];
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                pd[0][k] = db[G::LANES * k + L];
+                pd[1][k] = da[G::LANES * k + L];
+            }
+            ntt_fwd<NS, 2, W, false, DS>(pd, slot, twf, L, m, slot2, &par);
+            const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N;
+            const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N;
+            const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N;
+            const uint32_t *ka_b = Kp + ((size_t)(A.l + u) * 2 + 1) * N;
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint64_t xa = (uint64_t)pd[0][k] * kb_a[k] + (uint64_t)pd[1][k] * ka_a[k];
+                const uint64_t xb = (uint64_t)pd[0][k] * kb_b[k] + (uint64_t)pd[1][k] * ka_b[k];
+                out[0][k] = add_q(out[0][k], redc(xa, m), m.Q);
+                out[1][k] = add_q(out[1][k], redc(xb, m), m.Q);
+            }
+        }
+    }
+    __asm__ volatile("" ::: "memory");
+    ntt_inv<NS, 2, W, false, DS>(out, slot, twi, L, m, slot2, &par);
+    uint32_t *ob = A.outb + (size_t)task * 2 * N + (size_t)h * NS;
+#pragma unroll
+    for (int part = 0; part < 2; part++)
+#pragma unroll
+        for (int k = 0; k < E; k++) ob[(size_t)part * N + G::LANES * k + L] = out[part][k];
+}
+
+// Stage 3: for column j the Gentleman-Sande stages with m = M/2, ..., 1 groups,
+// then ACC_j + product into the other buffer; a task past step n - 1 copies.
+template <int M>
+__global__ __launch_bounds__(256) void k_split_post(WideArgs A)
+{
+    constexpr uint32_t NS = SPLIT_NS, N = M * NS;
+    const uint32_t task = blockIdx.y;
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const WideTask T = A.tasks[task];
+    const uint32_t i = T.i0 + A.step;
+    const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * 2 * N;
+    uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * 2 * N;
+    const uint32_t Q = A.Q[0];
+    if (i >= A.n) {
+#pragma unroll
+        for (int part = 0; part < 2; part++)
+#pragma unroll
+            for (int h = 0; h < M; h++) wr[part * N + j + h * NS] = own[part * N + j + h * NS];
+        return;
+    }
+    const ModQ m{Q, A.qn[0]};
+    const uint32_t *ob = A.outb + (size_t)task * 2 * N + j;
+#pragma unroll
+    for (int part = 0; part < 2; part++) {
+        uint32_t x[M];
+#pragma unroll
+        for (int h = 0; h < M; h++) x[h] = ob[part * N + h * NS];
+#pragma unroll
+        for (int mm = M / 2; mm >= 1; mm >>= 1) {
+            const int tb = M / (2 * mm);
+#pragma unroll
+            for (int g = 0; g < mm; g++) {
+                const uint32_t wt = A.twi0[mm + g];
+#pragma unroll
+                for (int hh = 2 * g * tb; hh < 2 * g * tb + tb; hh++) {
+                    const uint32_t uu = x[hh], v = x[hh + tb];
+                    x[hh] = add_q(uu, v, Q);
+                    x[hh + tb] = mont_mul(sub_q(uu, v, Q), wt, m);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < M; h++) {
+            const uint32_t idx = part * N + j + h * NS;
+            wr[idx] = add_q(own[idx], x[h], Q);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 // Two primes: N <= 4096 (the second prime is 1 mod 2^13); one prime: up to 16384.
@@ -371,10 +562,22 @@ __global__ __launch_bounds__(256) void k_wide_export(WideArgs A, uint32_t *__res
         }                                             \
     }
 
+// Rings above 16384 (one prime): only the per-coefficient kernels exist at that size.
+#define BIG_DISPATCH(N_, CALL)          \
+    switch (N_) {                       \
+    case 32768: CALL(32768, 1); break;  \
+    case 65536: CALL(65536, 1); break;  \
+    default: break;                     \
+    }
+
 void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
 {
 #define C_(n, p) hipLaunchKernelGGL((k_wide_init<n, p>), dim3(num_tasks), dim3(256), 0, st, A)
-    WIDE_DISPATCH(N, npr, C_)
+    if (N > 16384 && npr == 1) {
+        BIG_DISPATCH(N, C_)
+    } else {
+        WIDE_DISPATCH(N, npr, C_)
+    }
 #undef C_
 }
 
@@ -391,9 +594,34 @@ void launch_wide_extract(uint32_t N, int npr, const WideArgs &A, const uint64_t 
                          uint32_t *ext, hipStream_t st)
 {
 #define C_(n, p) hipLaunchKernelGGL((k_wide_extract<n, p>), dim3((uint32_t)count), dim3(256), 0, st, A, acc_off, ext)
-    WIDE_DISPATCH(N, npr, C_)
+    if (N > 16384 && npr == 1) {
+        BIG_DISPATCH(N, C_)
+    } else {
+        WIDE_DISPATCH(N, npr, C_)
+    }
 #undef C_
 }
+
+void launch_split_step(uint32_t N, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
+{
+    const uint32_t M = N / SPLIT_NS;
+    const dim3 cols(SPLIT_NS / 256, num_tasks);
+#define D_(mm)                                                                                           \
+    if (keys == 2) hipLaunchKernelGGL((k_split_digits<mm, 2>), cols, dim3(256), 0, st, A);            \
+    else hipLaunchKernelGGL((k_split_digits<mm, 1>), cols, dim3(256), 0, st, A);                       \
+    if (keys == 2) hipLaunchKernelGGL(k_split_sub<2>, dim3(num_tasks * mm), dim3(64 * SPLIT_WAVES), 0, st, A); \
+    else hipLaunchKernelGGL(k_split_sub<1>, dim3(num_tasks * mm), dim3(64 * SPLIT_WAVES), 0, st, A);            \
+    hipLaunchKernelGGL((k_split_post<mm>), cols, dim3(256), 0, st, A)
+    switch (M) {
+    case 2: D_(2); break;
+    case 4: D_(4); break;
+    case 8: D_(8); break;
+    default: break;
+    }
+#undef D_
+}
+
+bool split_supports_n(uint32_t N) { return N == 16384 || N == 32768 || N == 65536; }
 
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st)
 {
@@ -403,12 +631,13 @@ void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint3
 }
 
 #undef WIDE_DISPATCH
+#undef BIG_DISPATCH
 
 int wide_waves_per_poly(uint32_t N) { return wide_wpp((int)N); }
 
 bool wide_supports_n(uint32_t N, int npr)
 {
-    if (N < 256 || N > (npr == 2 ? 4096u : 16384u)) return false;
+    if (N < 256 || N > (npr == 2 ? 4096u : 65536u)) return false;
     return (N & (N - 1)) == 0;
 }
 

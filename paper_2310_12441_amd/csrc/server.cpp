@@ -235,6 +235,7 @@ Server::~Server()
 Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
 {
     MM_REQUIRE(chunk >= 1 && chunk <= c.p.n, "chunk_steps must be in [1, n]");
+    MM_REQUIRE(c.p.N <= 16384, "the server takes rings of up to 16384 coefficients");
     Device &d = ensure_device(c);
     const size_t N = c.p.N, W = c.p.n + 1;
     const bool global = c.wide || !dev::device_supports_n(c.p.N);

@@ -144,13 +144,14 @@ def test_keygen_and_test_vector_match_oracle_large_ring(N):
 
 def test_ring_degree_limits():
     b = _binding()
-    for N in (32, 32768):
+    for N in (32, 131072):
         p = Params(n=4, N=N)
         with pytest.raises(b.MMError) as e:
             b.Context(p, key_draws(p, 1))
         assert e.value.code == b.MM_EINVAL
-    # 16384 is the largest ring (the global-accumulator path, one polynomial over 16 waves)
-    p = Params(n=2, N=16384)
+    # 65536 is the largest ring (the global-accumulator path, split into sub-rings of 8192;
+    # 2N divides Q - 1 = 2^17 (2^14 - 1))
+    p = Params(n=2, N=65536)
     dr = key_draws(p, 1)
     ctx = b.Context(p, dr)
     np.testing.assert_array_equal(ctx.export_bsk(), oracle.keygen_bsk(p, dr))

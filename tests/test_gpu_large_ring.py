@@ -293,6 +293,18 @@ def test_bootstrap_16384(plain):
     out = c.ctx.bootstrap([tid] * 2, ct, plain=plain)
     np.testing.assert_array_equal(out, oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, q, ct))
     if not plain:
+        # both blind-rotation shapes of this ring (one 16-wave workgroup per component,
+        # or two sub-rings of 8192) with every key switch give the same bits
+        ids = np.full(2, tid, np.int32)
+        n = c.ctx.schedule_count(ids)
+        shapes = {c.ctx.schedule_describe(ids, k)[5] for k in range(n)}
+        assert shapes == {0, 3}
+        for k in range(n):
+            c.ctx.set_schedule(ids, k)
+            np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), out, err_msg=f"schedule {k}")
+            np.testing.assert_array_equal(c.ctx.blind_rotate(ids, ct, 2), got, err_msg=f"schedule {k}")
+        c.ctx.autotune(ids, ct)
+        np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), out)
         # served on the global-accumulator path (chunk 3 does not divide n = 4)
         srv = c.ctx.server_start(64 << 20, chunk_steps=3)
         try:
@@ -302,6 +314,43 @@ def test_bootstrap_16384(plain):
         np.testing.assert_array_equal(got, out)
     np.testing.assert_array_equal(c.ctx.bootstrap([tid] * 2, ct, q_out=Q, plain=plain),
                                   oracle.bootstrap_many(c.p, 1, c.keys.bsk, c.keys.ksk, V, q, Q, ct))
+
+
+@pytest.mark.parametrize("N,r,ternary", [(32768, 1, False), (65536, 1, False), (32768, 2, True)])
+def test_split_ring(N, r, ternary):
+    """Rings of 32768 and 65536 coefficients (the TFHE-shaped points t = 2^16 and 2^17)
+    split into sub-rings of 8192: the stages that mix sub-rings run column by column
+    through device memory, each sub-ring's NTT, product and inverse in one workgroup.
+    The accumulator after 2 CMux steps and whole bootstraps (at q and at Q) against
+    the oracle; r = 2 with a ternary secret covers the rotation between components and
+    both CMux terms."""
+    from dataclasses import replace
+    c = case(N, n=3) if not ternary else None
+    if ternary:
+        key = (N, 3, "ternary")
+        if key not in _cases:
+            say("keygen N", N, "ternary")
+            _cases[key] = Case(replace(Params(n=3, N=N, log2_B=7, l=4), ternary=True), 950 + N)
+        c = _cases[key]
+    t = 2 * N * r // 4
+    tid, f, V = c.table(t, t, r, 131)
+    q = 2 * N * r
+    ct = c.encrypt(q, t, messages(t, 2, 132), 133)
+    ids = np.full(2, tid, np.int32)
+    assert c.ctx.schedule_describe(ids)[5] == 3  # the split ring
+    say("split ring N", N, "r", r, "ternary", ternary)
+    got = c.ctx.blind_rotate(ids, ct, 2)
+    size = r * 2 * N
+    for j in range(2):
+        np.testing.assert_array_equal(got[j * size:(j + 1) * size].reshape(r, 2, N),
+                                      oracle.blind_rotate(c.p, r, c.keys.bsk, V, ct[j], 2), err_msg=f"ct {j}")
+    out = c.ctx.bootstrap(ids, ct)
+    np.testing.assert_array_equal(out, oracle.bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct))
+    np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct, plain=True), out)
+    np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct, q_out=Q),
+                                  oracle.bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, Q, ct))
+    c.ctx.close()
+    _cases.pop(next(k for k, v in _cases.items() if v is c))
 
 
 def test_serving_at_2048_matches_alone():
