@@ -41,6 +41,30 @@ def _rng(seed: int, tag: str) -> np.random.Generator:
     return np.random.default_rng([int(seed) & 0xFFFFFFFFFFFFFFFF, _TAGS[tag]])
 
 
+def _uniform_u32(seed: int, tag: str, bound: int, shape) -> np.ndarray:
+    """Uniform uint32 in [0, bound).  Arrays of 2^30 words or more (the
+    key-switching masks of the largest rings) are drawn in 64 blocks along the
+    first axis, each from its own stream spawned off the same (seed, tag), on
+    several threads; smaller arrays come from the one stream of (seed, tag)."""
+    if int(np.prod(shape)) < (1 << 30):
+        return _rng(seed, tag).integers(0, bound, size=shape, dtype=np.uint32)
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty(shape, dtype=np.uint32)
+    blocks = 64
+    kids = np.random.SeedSequence([int(seed) & 0xFFFFFFFFFFFFFFFF, _TAGS[tag]]).spawn(blocks)
+    edges = np.linspace(0, shape[0], blocks + 1).astype(np.int64)
+
+    def fill(b):
+        g = np.random.Generator(np.random.PCG64(kids[b]))
+        lo, hi = int(edges[b]), int(edges[b + 1])
+        out[lo:hi] = g.integers(0, bound, size=(hi - lo,) + tuple(shape[1:]), dtype=np.uint32)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(blocks)))
+    return out
+
+
 @dataclass(frozen=True)
 class Params:
     """Ring and gadget parameters shared by every table of one key set."""
@@ -122,7 +146,7 @@ def key_draws(p: Params, seed: int) -> dict:
         "bsk_a": _rng(seed, "bsk_a").integers(0, p.Q_ring, size=(n * K, 2 * l, N),
                                               dtype=np.uint64 if p.Q2 else np.uint32),
         "bsk_e": discrete_gaussian(_rng(seed, "bsk_e"), p.sigma, (n * K, 2 * l, N)),
-        "ksk_a": _rng(seed, "ksk_a").integers(0, Q, size=(N, p.l_ks, p.B_ks, n), dtype=np.uint32),
+        "ksk_a": _uniform_u32(seed, "ksk_a", Q, (N, p.l_ks, p.B_ks, n)),
         "ksk_e": discrete_gaussian(_rng(seed, "ksk_e"), p.sigma_ks, (N, p.l_ks, p.B_ks)),
     }
     return out
