@@ -52,14 +52,16 @@ typedef struct mm_ctx mm_ctx;
 typedef struct mm_server mm_server;
 
 /* Ring and gadget parameters of one key set (Alg. 1 inputs).
- * n: LWE dimension; N: ring degree, a power of two in [64, 16384] (the device
- * path takes 256 ... 16384; above 1024 one polynomial spans N / 1024 waves; a
+ * n: LWE dimension; N: ring degree, a power of two in [64, 65536] (the device
+ * path takes 256 ... 65536; above 1024 one polynomial spans N / 1024 waves; a
  * batch whose tables all have r * N / 1024 <= 8 runs the fused persistent
- * kernel, any other batch, and every batch at N = 16384, the global-
- * accumulator path: accumulators in device memory, one launch per CMux step,
- * r up to 1024 -- so the TFHE-shaped rings of the comparison in Sec. 5 reach
- * N = 16384 and MMPM tables r = 16 and beyond); Q: ring modulus (odd prime,
- * Q = 1 mod 2N, Q < 2^31); log2_B, l:
+ * kernel, any other batch, and every batch at N >= 16384, the global-
+ * accumulator path: accumulators in device memory, one launch per CMux step
+ * (three for a ring split into sub-rings of 8192 coefficients: the NTT stages
+ * that mix sub-rings run through device memory; always above 16384, a
+ * schedule choice at 16384), r up to 1024 -- so the TFHE-shaped rings of the
+ * comparison in Sec. 5 reach N = 65536 and MMPM tables r = 16 and beyond);
+ * Q: ring modulus (odd prime, Q = 1 mod 2N, Q < 2^31); log2_B, l:
  * the blind-rotation gadget base 2^log2_B and length, l * log2_B <= 32 and
  * log2_B <= 15; log2_Bks, l_ks: the key-switch base and length,
  * l_ks * log2_Bks >= bits(Q) so the key-switch digits are exact; ternary: 0 for
@@ -282,7 +284,9 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
  * 1: the last exchange between NTT phases by wavefront lane swaps
  * (v_permlane16/32_swap), the others through LDS; 2: LDS exchanges with the two
  * polynomials staggered, one's relayout in flight while the other's
- * butterflies run).  Any output pointer may be NULL. */
+ * butterflies run; 3, global path only: the ring split into sub-rings of 8192,
+ * the stages that mix them in separate launches).  Any output pointer may be
+ * NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
                          int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
                          int *ntt_schedule);
@@ -301,7 +305,8 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
  * r N/1024 > 8.  A context on the global-accumulator path (Q2 != 0, or
  * N = 16384) is served with that path's kernels: each launch ("tick") is
  * chunk_steps CMux launches over every resident component, each ciphertext at
- * its own step, with accumulators in two device arenas (the budget then counts
+ * its own step, with accumulators in two device arenas (rings up to 16384;
+ * MM_EINVAL above; the budget then counts
  * 2 x 2 x N words per component and residue); any r up to 1024 whose block of
  * 2^ceil(log2 r) components fits the budget is served (MM_EINVAL at submission
  * otherwise).
