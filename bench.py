@@ -133,6 +133,8 @@ def main():
                     help="batch of the MMPM vs TFHE-shaped comparison per class (0: no comparison leg)")
     ap.add_argument("--compare-max-logt", type=int, default=16,
                     help="largest log2 t of the TFHE-shaped comparison (15: N = 16384, 16: 32768, 17: 65536)")
+    ap.add_argument("--compare-only", default="",
+                    help="comma-separated log2 t: run only these comparison rows (for profiling one ring)")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate (0: no serving leg)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000", help="Poisson arrival rates, req/s")
     ap.add_argument("--serve-max-latency", type=float, default=50.0,
@@ -366,7 +368,10 @@ def main():
         # components at N = 1024 against one ring of degree 1024 r): both on the
         # global-accumulator path, rings above 16384 split into sub-rings of 8192
         big = [(1 << lt, 1 << (lt - 11)) for lt in range(15, args.compare_max_logt + 1)]
+        only = {int(x) for x in args.compare_only.split(",") if x}
         for k, (tt, rr) in enumerate(list(CLASS_MIX) + big):
+            if only and tt.bit_length() - 1 not in only:
+                continue
             row = {"t": tt, "k": rr}
             tid_m = tabs[k][0] if k < len(tabs) else ctx.table_create(tt, tt, rr, negacyclic_table(tt, tt, 100 + k))
             bps, path = timed_batch(ctx, tid_m, tt, rr, p.N, 700 + k)
