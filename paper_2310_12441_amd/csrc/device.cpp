@@ -500,6 +500,10 @@ static std::vector<int> global_shapes(const mm_ctx &c)
     return {0, 3};
 }
 
+// The global-accumulator shape as a schedule of batches the fused kernel holds
+// (one prime, rings up to 8192).
+static bool global_ok(const mm_ctx &c) { return !c.wide && dev::device_supports_n(c.p.N); }
+
 // Two waves per component (N = 512, 1024, r <= 4): for batches that do not
 // fill every compute unit, both waves of a slot share one component's work.
 static bool wide_slots_ok(const mm_ctx &c, const int *ids, size_t count)
@@ -554,6 +558,11 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
             if (gw == 4 && !narrow_ok) continue;
             for (auto &k : ks) out.push_back(Sched{gw, k, 0, 2});
         }
+    // the global-accumulator shape (one workgroup per component and CMux step, each
+    // on its own compute unit): for small batches the components of one ciphertext
+    // then run side by side instead of sharing one compute unit
+    if (global_ok(c))
+        for (auto &k : ks) out.push_back(Sched{0, k});
     return out;
 }
 
@@ -568,7 +577,18 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         const int shape = global_shapes(c).front();
         return Sched{0, ks_default(c, d, count), shape == 3 ? dev::SPLIT_WAVES : 0, shape};
     }
-    // untuned: 2-wave slots while the components fit half-full groups on every
+    // untuned, at N <= 1024: the global-accumulator shape while the batch leaves
+    // compute units idle (at most one component per compute unit; with components
+    // that cannot take two-wave slots, up to four): each component then has a
+    // compute unit to itself, and one ciphertext takes 12 ms instead of 14 ms (r <= 4)
+    // or 26 ms (r = 8) at the paper-shaped size
+    if (global_ok(c) && c.p.N <= 1024) {
+        const uint64_t comps = sum_r(c, ids, count);
+        const bool two_wave = wide_slots_ok(c, ids, count);
+        if (comps <= (uint64_t)d.num_cu || (!two_wave && comps <= 4ull * (uint64_t)d.num_cu))
+            return Sched{0, ks_default(c, d, count)};
+    }
+    // else 2-wave slots while the components fit half-full groups on every
     // compute unit (the chip is not full), else the full-width default
     const bool light = sum_r(c, ids, count) <= 4ull * (uint64_t)d.num_cu;
     return Sched{8, ks_default(c, d, count), light && wide_slots_ok(c, ids, count) ? 2 : 0};
@@ -655,13 +675,12 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
 static void bootstrap_batch(mm_ctx &c, Device &d, const int *ids, const uint32_t *d_in, size_t count, uint32_t *d_out,
                             uint32_t q_out, bool use_graph, hipStream_t st, const Sched *force = nullptr)
 {
-    if (use_global(c, ids, count)) {
-        const Sched S = force ? *force : schedule_for(c, d, ids, count);
+    const Sched S = force ? *force : schedule_for(c, d, ids, count);
+    if (use_global(c, ids, count) || S.gw == 0) {
         bootstrap_wide(c, d, ids, d_in, count, d_out, q_out, use_graph, st, S);
         return;
     }
     const uint32_t N = c.p.N;
-    const Sched S = force ? *force : schedule_for(c, d, ids, count);
     auto tasks = pack_groups(c, d, ids, count, dev::TASK_INIT | dev::TASK_EXTRACT, 0, {}, (uint32_t)S.gw,
                              (uint32_t)S.wpp);
     const int groups = (int)(tasks.size() / S.gw);

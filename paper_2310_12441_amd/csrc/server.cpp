@@ -164,6 +164,7 @@ struct Server {
     mm_ctx *c = nullptr;
     uint32_t chunk = 64, max_cts = 0, units = 0;
     bool global = false;     // the global-accumulator path (one launch per CMux step)
+    bool switchable = false; // fused-kernel context whose light ticks take the global path
     size_t unit_words = 0;   // words of one unit in one arena
     uint32_t top_block = 3;  // order of the largest block the arena holds
     uint32_t *d_acc = nullptr, *d_ct = nullptr, *d_ext = nullptr;
@@ -239,11 +240,15 @@ Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
     Device &d = ensure_device(c);
     const size_t N = c.p.N, W = c.p.n + 1;
     const bool global = c.wide || !dev::device_supports_n(c.p.N);
+    // at N <= 1024 a tick that leaves compute units idle runs the global-accumulator
+    // kernels (each component on its own compute unit), a heavier one the fused kernel
+    const bool switchable = !global && N <= 1024 && dev::wide_supports_n((uint32_t)N, 1);
     // per ciphertext slot: input, extracted sample, key-switch partial row; per unit:
-    // one (a, b) pair (global path: with every residue, in each of the two arenas)
+    // one (a, b) pair (with every residue; in each of two arenas when ticks may take the
+    // global path)
     const size_t per_ct = (W + N + 1) * 4 + W * 8;
     const size_t unit_words = 2 * (size_t)primes_of(c) * N;
-    const size_t per_unit = (global ? 2 : 1) * unit_words * 4;
+    const size_t per_unit = (global || switchable ? 2 : 1) * unit_words * 4;
     const size_t fit = budget / (per_ct + per_unit);
     const size_t units = global ? std::min<size_t>(fit, size_t(1) << 24) : fit / 8 * 8;
     MM_REQUIRE(units >= (global ? 1 : 8), "HBM budget too small for one slot group");
@@ -251,6 +256,7 @@ Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
     s->c = &c;
     s->chunk = chunk;
     s->global = global;
+    s->switchable = switchable;
     s->unit_words = unit_words;
     s->units = (uint32_t)units;
     s->max_cts = (uint32_t)units;
@@ -412,7 +418,19 @@ void Server::launch(Part &p)
         dev::launch_scatter_rows(p.stage.d, d_ct, p.stage_rows.d, fresh.size(), W, p.st);
         p.active.insert(p.active.end(), fresh.begin(), fresh.end());
     }
-    if (global) {
+    bool glob = global;
+    if (switchable) {
+        // the rule of the batched path's default schedule: at most one component per
+        // compute unit, or four where the components cannot take two-wave slots
+        uint64_t comps = 0;
+        bool wide8 = false;
+        for (auto &a : p.active) {
+            comps += c->tables[a.table].r;
+            wide8 |= c->tables[a.table].r > 4;
+        }
+        glob = comps <= (uint64_t)d.num_cu || (wide8 && comps <= 4ull * (uint64_t)d.num_cu);
+    }
+    if (glob) {
         launch_global(p, fresh);
         return;
     }
@@ -456,7 +474,8 @@ void Server::launch(Part &p)
     A.num_groups = (int)(tasks.size() / 8);  // 8-wave groups (any r <= 8)
     A.steps = (int)chunk;
     A.ct_in = d_ct;
-    A.acc_state = d_acc;
+    // the partition's current arena, read and written in place
+    A.acc_state = switchable ? d_acc + (size_t)p.cur * units * unit_words : d_acc;
     A.ext_out = d_ext;
     dev::launch_blind_rotate(N, A, 8, std::min(A.num_groups, d.num_cu), p.st, slots2 ? 2 : 0);
 

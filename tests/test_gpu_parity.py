@@ -568,9 +568,11 @@ def test_empty_and_ragged_batches(paper):
 
 @pytest.mark.parametrize("N,ternary", [(1024, False), (1024, True), (512, False), (512, True)])
 def test_two_wave_slots_small_batches(N, ternary):
-    """Batches too small to fill the device run each component on two waves
-    (N = 512, 1024, r <= 4): blind rotation and bootstrap against the oracle, and
-    the same bits as the one-wave schedule."""
+    """Batches too small to fill the device: their default is the global-accumulator
+    shape (a compute unit per component), and the fused kernel's schedule with each
+    component on two waves (N = 512, 1024, r <= 4) is among the candidates; blind
+    rotation and bootstrap against the oracle, and every schedule gives the same bits.
+    r = 8 does not fit two-wave slots: its fused schedules run one wave per component."""
     from dataclasses import replace
     say("two-wave slots N", N, "ternary", ternary)
     p = replace(Params(n=12, N=N, log2_B=7, l=4), ternary=ternary)
@@ -580,8 +582,12 @@ def test_two_wave_slots_small_batches(N, ternary):
     q = 2 * N * 4
     ct = c.encrypt(q, 2 * N, messages(2 * N, 3, 33), 34)
     ids = np.full(3, tid, np.int32)
-    assert c.ctx.schedule_describe(ids)[3] == 2
-    assert c.ctx.schedule_describe(np.full(3, tid8, np.int32))[3] == 1
+    ids8 = np.full(3, tid8, np.int32)
+    assert c.ctx.schedule_describe(ids)[0] == 0 and c.ctx.schedule_describe(ids8)[0] == 0
+    desc = [c.ctx.schedule_describe(ids, k) for k in range(c.ctx.schedule_count(ids))]
+    assert any(d[0] == 8 and d[3] == 2 for d in desc)  # two-wave slots
+    desc8 = [c.ctx.schedule_describe(ids8, k) for k in range(c.ctx.schedule_count(ids8))]
+    assert all(d[3] == 1 for d in desc8 if d[0] != 0)
     acc = c.ctx.blind_rotate(ids, ct, 5)
     for j in range(3):
         np.testing.assert_array_equal(acc[j * 4 * 2 * N:(j + 1) * 4 * 2 * N].reshape(4, 2, N),
@@ -595,8 +601,11 @@ def test_two_wave_slots_small_batches(N, ternary):
         np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), out, err_msg=f"schedule {k}")
     q8 = 2 * N * 8
     ct8 = c.encrypt(q8, 64, messages(64, 2, 35), 36)
-    np.testing.assert_array_equal(c.ctx.bootstrap([tid8] * 2, ct8),
-                                  oracle.bootstrap_many(p, 8, c.keys.bsk, c.keys.ksk, V8, q8, q8, ct8))
+    want8 = oracle.bootstrap_many(p, 8, c.keys.bsk, c.keys.ksk, V8, q8, q8, ct8)
+    ids8 = np.full(2, tid8, np.int32)
+    for k in range(c.ctx.schedule_count(ids8)):
+        c.ctx.set_schedule(ids8, k)
+        np.testing.assert_array_equal(c.ctx.bootstrap(ids8, ct8), want8, err_msg=f"r = 8, schedule {k}")
     c.ctx.close()
 
 
