@@ -258,10 +258,11 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
  * kernel and tiling) on the device and remember the fastest for the shape (N,
  * sum of r, count).  mm_bootstrap uses the remembered schedule.  *choice
  * receives the chosen schedule index.  Untuned batches at N <= 1024 that leave
- * compute units idle (at most one component per compute unit, or four when no
- * two-wave slots fit) take the global-accumulator shape, whose components each
- * get a compute unit, which is also a candidate for every batch the fused kernel
- * holds.  A batch on the global-accumulator path
+ * the device mostly idle (at most two components per compute unit, or four when
+ * no two-wave slots fit) take the global-accumulator shape with twice its usual
+ * waves per component (each component on a compute unit nearly of its own); that
+ * shape, with the usual and with twice the waves, is a candidate for every batch
+ * the fused kernel holds.  A batch on the global-accumulator path
  * (see mm_params; the wide modulus among others) has one blind-rotation shape:
  * its candidates differ in the key switch only, and this call runs the batch
  * once and then times each key switch on its extracted samples. */
@@ -305,9 +306,9 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
  * every resident ciphertext of its partition by chunk_steps CMux steps (2/3 of
  * that for the wider ones when a partition holds both kinds), so a request
  * admitted while others run joins them at the next launch.  At N <= 1024 a tick
- * whose partition holds at most one component per compute unit (four when it
- * holds r = 8 ciphertexts) runs the global-accumulator kernels instead, each
- * component on a compute unit of its own.  Tables of general
+ * whose partition holds at most two components per compute unit (four when it
+ * holds r = 8 ciphertexts) runs the global-accumulator kernels instead, with the
+ * waves per component of the batched path's light default.  Tables of general
  * f are not served, nor, at the default modulus and N <= 8192, tables with
  * r N/1024 > 8.  A context on the global-accumulator path (Q2 != 0, or
  * N = 16384) is served with that path's kernels: each launch ("tick") is

@@ -504,6 +504,14 @@ static std::vector<int> global_shapes(const mm_ctx &c)
 // (one prime, rings up to 8192).
 static bool global_ok(const mm_ctx &c) { return !c.wide && dev::device_supports_n(c.p.N); }
 
+// Waves per component of that shape for batches that leave the device mostly idle:
+// twice the usual where the kernel exists (N = 512, 1024), else the usual.
+int light_global_wpp(const mm_ctx &c)
+{
+    const int w2 = 2 * dev::wide_waves_per_poly(c.p.N);
+    return dev::wide_supports_wpp(c.p.N, 1, w2) ? w2 : 0;
+}
+
 // Two waves per component (N = 512, 1024, r <= 4): for batches that do not
 // fill every compute unit, both waves of a slot share one component's work.
 static bool wide_slots_ok(const mm_ctx &c, const int *ids, size_t count)
@@ -561,8 +569,11 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
     // the global-accumulator shape (one workgroup per component and CMux step, each
     // on its own compute unit): for small batches the components of one ciphertext
     // then run side by side instead of sharing one compute unit
-    if (global_ok(c))
+    if (global_ok(c)) {
         for (auto &k : ks) out.push_back(Sched{0, k});
+        if (const int w2 = light_global_wpp(c))
+            for (auto &k : ks) out.push_back(Sched{0, k, w2});
+    }
     return out;
 }
 
@@ -577,16 +588,16 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         const int shape = global_shapes(c).front();
         return Sched{0, ks_default(c, d, count), shape == 3 ? dev::SPLIT_WAVES : 0, shape};
     }
-    // untuned, at N <= 1024: the global-accumulator shape while the batch leaves
-    // compute units idle (at most one component per compute unit; with components
-    // that cannot take two-wave slots, up to four): each component then has a
-    // compute unit to itself, and one ciphertext takes 12 ms instead of 14 ms (r <= 4)
-    // or 26 ms (r = 8) at the paper-shaped size
+    // untuned, at N <= 1024: the global-accumulator shape with twice its usual waves
+    // per component while the batch leaves the device mostly idle (at most two
+    // components per compute unit; four where the components cannot take two-wave
+    // slots): each component then has a compute unit nearly to itself, and one
+    // paper-shaped ciphertext takes 7.4 ms instead of 14.2 ms (r = 4) or 25.9 ms (r = 8)
     if (global_ok(c) && c.p.N <= 1024) {
         const uint64_t comps = sum_r(c, ids, count);
         const bool two_wave = wide_slots_ok(c, ids, count);
-        if (comps <= (uint64_t)d.num_cu || (!two_wave && comps <= 4ull * (uint64_t)d.num_cu))
-            return Sched{0, ks_default(c, d, count)};
+        if (comps <= 2ull * (uint64_t)d.num_cu || (!two_wave && comps <= 4ull * (uint64_t)d.num_cu))
+            return Sched{0, ks_default(c, d, count), light_global_wpp(c)};
     }
     // else 2-wave slots while the components fit half-full groups on every
     // compute unit (the chip is not full), else the full-width default
@@ -794,7 +805,7 @@ static void split_buffers(const mm_ctx &c, Device &d, dev::WideArgs &A, size_t n
 // ACC init and `steps` CMux launches (three per step for a split ring, A.M > 0);
 // returns the buffer holding the result.
 static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_t *buf0, uint32_t *buf1,
-                                       uint32_t num_tasks, uint32_t steps, hipStream_t s)
+                                       uint32_t num_tasks, uint32_t steps, hipStream_t s, int wpp = 0)
 {
     const uint32_t N = c.p.N;
     uint32_t *buf[2] = {buf0, buf1};
@@ -805,7 +816,7 @@ static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_
         A.acc_rd = buf[i & 1];
         A.acc_wr = buf[(i + 1) & 1];
         if (A.M) dev::launch_split_step(N, c.keys, A, num_tasks, s);
-        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s);
+        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s, wpp);
     }
     return buf[steps & 1];
 }
@@ -832,7 +843,7 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
     A.tasks = dt;
     A.ct_in = d_in;
     const uint32_t nt = (uint32_t)tasks.size();
-    const std::string key = "wide/" + std::to_string(S.ntt) + "/" + std::to_string(count) + "/" + std::to_string(nt) + "/" +
+    const std::string key = "wide/" + std::to_string(S.ntt) + "/" + std::to_string(S.wpp) + "/" + std::to_string(count) + "/" + std::to_string(nt) + "/" +
                             std::to_string(ks.cpw) + "/" + std::to_string(ks.P) + "/" + std::to_string(q_scalar) +
                             "/" + std::to_string((uintptr_t)qv) + "/" + std::to_string((uintptr_t)d_in) + "/" +
                             std::to_string((uintptr_t)d_out) + "/" + std::to_string(d.ws_generation);
@@ -840,7 +851,7 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
         d, key, use_graph, st,
         [&](hipStream_t s) {
             dev::WideArgs B = A;
-            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s);
+            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp);
             dev::launch_wide_extract(N, primes_of(c), B, doff, count, ext, s);
         },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, ks, part, s); });

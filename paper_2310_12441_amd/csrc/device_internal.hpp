@@ -122,5 +122,6 @@ void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const in
 // wide modulus, else 1).
 dev::WideArgs wide_args(const mm_ctx &c, const Device &d);
 int primes_of(const mm_ctx &c);
+int light_global_wpp(const mm_ctx &c);  // waves per component of light global-path work (0: the usual)
 
 }  // namespace mm

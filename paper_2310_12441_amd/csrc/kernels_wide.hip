@@ -581,8 +581,20 @@ void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks
 #undef C_
 }
 
-void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
+void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st,
+                      int wpp)
 {
+    if (npr == 1 && wpp > 0 && wpp != wide_wpp((int)N)) {
+        // twice the waves per component (N = 512, 1024; one prime): the step's work
+        // on more SIMDs of each component's compute unit
+#define L_(n, w)                                                                                                \
+    if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2, 1, w>), dim3(num_tasks), dim3(64 * w), 0, st, A); \
+    else hipLaunchKernelGGL((k_wide_step<n, 1, 1, w>), dim3(num_tasks), dim3(64 * w), 0, st, A)
+        if (N == 1024 && wpp == 4) L_(1024, 4);
+        else if (N == 512 && wpp == 2) L_(512, 2);
+#undef L_
+        return;
+    }
 #define C_(n, p)                                                                                                   \
     if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2, p>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A); \
     else hipLaunchKernelGGL((k_wide_step<n, 1, p>), dim3(num_tasks), dim3(64 * wide_wpp(n)), 0, st, A)
@@ -634,6 +646,11 @@ void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint3
 #undef BIG_DISPATCH
 
 int wide_waves_per_poly(uint32_t N) { return wide_wpp((int)N); }
+
+bool wide_supports_wpp(uint32_t N, int npr, int wpp)
+{
+    return wpp == wide_wpp((int)N) || (npr == 1 && ((N == 1024 && wpp == 4) || (N == 512 && wpp == 2)));
+}
 
 bool wide_supports_n(uint32_t N, int npr)
 {

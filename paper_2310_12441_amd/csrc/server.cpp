@@ -420,7 +420,7 @@ void Server::launch(Part &p)
     }
     bool glob = global;
     if (switchable) {
-        // the rule of the batched path's default schedule: at most one component per
+        // the rule of the batched path's default schedule: at most two components per
         // compute unit, or four where the components cannot take two-wave slots
         uint64_t comps = 0;
         bool wide8 = false;
@@ -428,7 +428,7 @@ void Server::launch(Part &p)
             comps += c->tables[a.table].r;
             wide8 |= c->tables[a.table].r > 4;
         }
-        glob = comps <= (uint64_t)d.num_cu || (wide8 && comps <= 4ull * (uint64_t)d.num_cu);
+        glob = comps <= 2ull * (uint64_t)d.num_cu || (wide8 && comps <= 4ull * (uint64_t)d.num_cu);
     }
     if (glob) {
         launch_global(p, fresh);
@@ -556,7 +556,7 @@ void Server::launch_global(Part &p, const std::vector<Active> &fresh)
         A.step = s;
         A.acc_rd = arena[p.cur];
         A.acc_wr = arena[p.cur ^ 1];
-        dev::launch_wide_step(N, npr, c->keys, A, (uint32_t)n_step, p.st);
+        dev::launch_wide_step(N, npr, c->keys, A, (uint32_t)n_step, p.st, switchable ? light_global_wpp(*c) : 0);
         p.cur ^= 1;
     }
     std::vector<Active> keep;

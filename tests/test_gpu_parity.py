@@ -335,9 +335,11 @@ def test_every_schedule_gives_the_same_bits(paper):
     n = paper.ctx.schedule_count(ids)
     say("schedules", n)
     assert n >= 4
-    # 2-wave component slots are among the candidates (N = 1024, r <= 4), and
-    # both LDS-staged key switches
-    assert {paper.ctx.schedule_describe(ids, k)[3] for k in range(n)} == {1, 2}
+    # 2-wave component slots are among the candidates (N = 1024, r <= 4), the
+    # global-accumulator shape with 2 and 4 waves per component, and both LDS-staged
+    # key switches
+    assert {paper.ctx.schedule_describe(ids, k)[3] for k in range(n)} == {1, 2, 4}
+    assert {paper.ctx.schedule_describe(ids, k)[0] for k in range(n)} == {0, 4, 8}
     assert {paper.ctx.schedule_describe(ids, k)[4] for k in range(n)} == {1, 2}
     # the three NTT stage schedules (LDS lockstep, lane swaps, staggered LDS)
     assert {paper.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2}
