@@ -30,13 +30,21 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # One wave64 VALU instruction per 4 clocks per SIMD, without dual issue: the
 # rate a stream of 64-bit multiply-adds can reach.
 SINGLE_ISSUE_LANE_OPS = 256 * 64 * 2.4e9
-# Issue rate of a register-only loop with the butterfly's instruction mix (64-bit
-# multiply-adds, low-word multiplies, adds, subtracts, mins) at 2 waves per SIMD,
-# measured on the MI355X: the ceiling this kernel's instruction mix can reach.
-MIX_CEILING_LANE_OPS = 35.0e12
+# Issue rate of a register-only loop of lazy Montgomery butterflies (64-bit
+# multiply-add, low-word multiply, multiply-add, subtract, min, add, subtract, add:
+# 8 instructions), 16 independent chains per thread, 4096 workgroups, measured on
+# the MI355X at the occupancy of each blind-rotation kernel: the ceiling that
+# instruction mix can reach (4.817e12 butterflies/s at 2 waves per SIMD, 4.957e12
+# at 5).
+MIX_CEILING_LANE_OPS = {2: 38.5e12, 5: 39.7e12}
 PEAK_HBM = 8.0e12
-KERNEL_SOURCES = ("paper_2310_12441_amd/csrc/kernels.hip", "paper_2310_12441_amd/csrc/device_common.hpp")
-COUNTERS = os.path.join(ROOT, "profiles", "k_blind_rotate_paper_shaped_4096_counters.txt")
+KERNEL_SOURCES = ("paper_2310_12441_amd/csrc/kernels.hip", "paper_2310_12441_amd/csrc/kernels_wide.hip",
+                  "paper_2310_12441_amd/csrc/device_common.hpp")
+# counter summaries of the two blind-rotation kernels the schedule can pick for the
+# paper-shaped batch: the fused persistent kernel, and the global-accumulator kernel
+# with four waves per component (one launch per CMux step)
+COUNTERS = {"fused": os.path.join(ROOT, "profiles", "k_blind_rotate_paper_shaped_4096_counters.txt"),
+            "global": os.path.join(ROOT, "profiles", "k_wide_step_paper_shaped_4096_counters.txt")}
 
 
 def ops_per_bootstrap(n, N, l, r):
@@ -91,13 +99,13 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the blind-rotation kernel from the committed
-    counter summary, or None when it is missing or the kernel changed since."""
-    if not os.path.exists(COUNTERS):
+def measured_traffic(path):
+    """HBM bytes per launch of a blind-rotation kernel from its committed counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -235,11 +243,23 @@ def main():
         plain_out = torch.cat(plain_outs).cpu().numpy().view(np.uint32)
         plain_same = bool(np.array_equal(plain_out, batched_out[:P]))
 
-    # ---- roofline of the blind-rotation kernel
+    # ---- roofline of the blind-rotation kernel the schedule picked: the fused
+    # persistent kernel (one launch per batch) or the global-accumulator kernel (one
+    # launch per CMux step, plus an initialisation and an extraction launch inside the
+    # same HIP-event bracket, so the per-launch time below is slightly conservative)
     br_avg = float(np.mean(br_ms)) * 1e-3
-    ops = ops_per_bootstrap(p.n, p.N, p.l, r) * B
-    achieved = ops / br_avg
-    hbm_alg = bsk_bytes(p.n, p.N, p.l) + B * (p.n + 1) * 4 + B * (p.N + 1) * 4
+    global_shape = sched[0] == 0
+    launches = p.n if global_shape else 1
+    per_launch = br_avg / launches
+    ops = ops_per_bootstrap(p.n, p.N, p.l, r) * B // launches
+    achieved = ops / per_launch
+    waves_per_simd = 5 if global_shape else 2  # VGPR-bound occupancy of each kernel (94 and 256 VGPRs)
+    mix = MIX_CEILING_LANE_OPS[waves_per_simd]
+    hbm_alg = (bsk_bytes(p.n, p.N, p.l) + B * (p.n + 1) * 4 + B * (p.N + 1) * 4) // launches
+    if global_shape:
+        kname = f"k_wide_step<{p.N},1,1,{sched[3]}>"
+    else:
+        kname = f"k_blind_rotate<{p.N},{sched[0]},1,{sched[3]}" + (",true" if sched[5] == 1 else "") + ">"
     roofline = {
         "bound": "alu",
         "achieved": round(achieved / 1e12, 3),
@@ -248,14 +268,17 @@ def main():
         "frac": round(achieved / PEAK_LANE_OPS, 4),
         "peak_single_issue": round(SINGLE_ISSUE_LANE_OPS / 1e12, 3),
         "frac_single_issue": round(achieved / SINGLE_ISSUE_LANE_OPS, 4),
-        "mix_ceiling": round(MIX_CEILING_LANE_OPS / 1e12, 3),
-        "frac_mix_ceiling": round(achieved / MIX_CEILING_LANE_OPS, 4),
-        "traffic": measured_traffic(),
-        "kernel": (f"k_blind_rotate<1024,{sched[0]},1,{sched[3]}" + (",true" if sched[5] == 1 else "") + ">"),
-        "kernel_ms": round(br_avg * 1e3, 3),
+        "mix_ceiling": round(mix / 1e12, 3),
+        "mix_ceiling_waves_per_simd": waves_per_simd,
+        "frac_mix_ceiling": round(achieved / mix, 4),
+        "traffic": measured_traffic(COUNTERS["global" if global_shape else "fused"]),
+        "kernel": kname,
+        "launches_per_batch": launches,
+        "kernel_ms": round(per_launch * 1e3, 4),
+        "blind_rotation_ms_per_batch": round(br_avg * 1e3, 3),
         "ops_per_launch": ops,
         "hbm_algorithmic_bytes": hbm_alg,
-        "hbm_frac": round(hbm_alg / br_avg / PEAK_HBM, 6),
+        "hbm_frac": round(hbm_alg / per_launch / PEAK_HBM, 6),
         "kernel_source_sha256_16": source_hash(),
     }
 

@@ -257,12 +257,13 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
  * workgroup slot packing, waves per component, NTT stage schedule, key-switch
  * kernel and tiling) on the device and remember the fastest for the shape (N,
  * sum of r, count).  mm_bootstrap uses the remembered schedule.  *choice
- * receives the chosen schedule index.  Untuned batches at N <= 1024 that leave
+ * receives the chosen schedule index.  Untuned batches at N = 1024 that leave
  * the device mostly idle (at most two components per compute unit, or four when
- * no two-wave slots fit) take the global-accumulator shape with twice its usual
- * waves per component (each component on a compute unit nearly of its own); that
- * shape, with the usual and with twice the waves, is a candidate for every batch
- * the fused kernel holds.  A batch on the global-accumulator path
+ * no two-wave slots fit), or that hold more than 16 components per compute unit,
+ * take the global-accumulator shape with four waves per component (each
+ * component a small workgroup of its own); that shape, with its usual and with
+ * twice the waves (N = 512, 1024), is a candidate for every batch the fused
+ * kernel holds.  A batch on the global-accumulator path
  * (see mm_params; the wide modulus among others) has one blind-rotation shape:
  * its candidates differ in the key switch only, and this call runs the batch
  * once and then times each key switch on its extracted samples. */
@@ -305,7 +306,7 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
  * components and one for wider ones, alternate launches; each launch advances
  * every resident ciphertext of its partition by chunk_steps CMux steps (2/3 of
  * that for the wider ones when a partition holds both kinds), so a request
- * admitted while others run joins them at the next launch.  At N <= 1024 a tick
+ * admitted while others run joins them at the next launch.  At N = 1024 a tick
  * whose partition holds at most two components per compute unit (four when it
  * holds r = 8 ciphertexts) runs the global-accumulator kernels instead, with the
  * waves per component of the batched path's light default.  Tables of general

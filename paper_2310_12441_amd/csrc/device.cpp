@@ -588,21 +588,23 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         const int shape = global_shapes(c).front();
         return Sched{0, ks_default(c, d, count), shape == 3 ? dev::SPLIT_WAVES : 0, shape};
     }
-    // untuned, at N <= 1024: the global-accumulator shape with twice its usual waves
-    // per component while the batch leaves the device mostly idle (at most two
-    // components per compute unit; four where the components cannot take two-wave
-    // slots): each component then has a compute unit nearly to itself, and one
-    // paper-shaped ciphertext takes 7.4 ms instead of 14.2 ms (r = 4) or 25.9 ms (r = 8)
-    if (global_ok(c) && c.p.N <= 1024) {
-        const uint64_t comps = sum_r(c, ids, count);
-        const bool two_wave = wide_slots_ok(c, ids, count);
-        if (comps <= 2ull * (uint64_t)d.num_cu || (!two_wave && comps <= 4ull * (uint64_t)d.num_cu))
-            return Sched{0, ks_default(c, d, count), light_global_wpp(c)};
-    }
-    // else 2-wave slots while the components fit half-full groups on every
-    // compute unit (the chip is not full), else the full-width default
-    const bool light = sum_r(c, ids, count) <= 4ull * (uint64_t)d.num_cu;
-    return Sched{8, ks_default(c, d, count), light && wide_slots_ok(c, ids, count) ? 2 : 0};
+    // untuned, at N = 1024 (the ring of the paper-shaped parameters, measured for
+    // r = 4 and 8 at 1024 to 16384 components; at N = 512 the fused kernel measured
+    // faster up to 8192 components): the global-accumulator shape with four
+    // waves per component (one component per workgroup: small workgroups, up to eight
+    // waves per SIMD) where it measured fastest -- batches that leave the device mostly
+    // idle (at most two components per compute unit, or four where the components
+    // cannot take two-wave slots: one ciphertext 7.4 ms instead of 14.2 ms, or 25.9 ms
+    // at r = 8) and batches of more than 16 components per compute unit (188.8 against
+    // 203.8 ms for 16,384); in between the fused kernel (two-wave slots up to four
+    // components per compute unit, 14.6 against 16.5 ms at 1024; one wave per component
+    // up to 16 per compute unit, 25.6 against 27.4 ms at 2048)
+    const uint64_t comps = sum_r(c, ids, count), cu = (uint64_t)d.num_cu;
+    const bool two_wave = wide_slots_ok(c, ids, count);
+    if (global_ok(c) && c.p.N == 1024 && light_global_wpp(c) &&
+        (comps <= 2 * cu || (!two_wave && comps <= 4 * cu) || comps > 16 * cu))
+        return Sched{0, ks_default(c, d, count), light_global_wpp(c)};
+    return Sched{8, ks_default(c, d, count), comps <= 4 * cu && two_wave ? 2 : 0};
 }
 
 static int br_grid(const Device &d, int groups, int gw) { return std::min(groups, d.num_cu * (gw == 4 ? 2 : 1)); }

@@ -240,9 +240,9 @@ Server *server_start(mm_ctx &c, size_t budget, uint32_t chunk)
     Device &d = ensure_device(c);
     const size_t N = c.p.N, W = c.p.n + 1;
     const bool global = c.wide || !dev::device_supports_n(c.p.N);
-    // at N <= 1024 a tick that leaves compute units idle runs the global-accumulator
+    // at N = 1024 a tick that leaves compute units idle runs the global-accumulator
     // kernels (each component on its own compute unit), a heavier one the fused kernel
-    const bool switchable = !global && N <= 1024 && dev::wide_supports_n((uint32_t)N, 1);
+    const bool switchable = !global && N == 1024 && dev::wide_supports_wpp((uint32_t)N, 1, 4);
     // per ciphertext slot: input, extracted sample, key-switch partial row; per unit:
     // one (a, b) pair (with every residue; in each of two arenas when ticks may take the
     // global path)

@@ -570,8 +570,8 @@ def test_empty_and_ragged_batches(paper):
 
 @pytest.mark.parametrize("N,ternary", [(1024, False), (1024, True), (512, False), (512, True)])
 def test_two_wave_slots_small_batches(N, ternary):
-    """Batches too small to fill the device: their default is the global-accumulator
-    shape (a compute unit per component), and the fused kernel's schedule with each
+    """Batches too small to fill the device: their default at N = 1024 is the
+    global-accumulator shape (a compute unit per component), and the fused kernel's schedule with each
     component on two waves (N = 512, 1024, r <= 4) is among the candidates; blind
     rotation and bootstrap against the oracle, and every schedule gives the same bits.
     r = 8 does not fit two-wave slots: its fused schedules run one wave per component."""
@@ -585,7 +585,10 @@ def test_two_wave_slots_small_batches(N, ternary):
     ct = c.encrypt(q, 2 * N, messages(2 * N, 3, 33), 34)
     ids = np.full(3, tid, np.int32)
     ids8 = np.full(3, tid8, np.int32)
-    assert c.ctx.schedule_describe(ids)[0] == 0 and c.ctx.schedule_describe(ids8)[0] == 0
+    if N == 1024:  # the default there: the global-accumulator shape, four waves per component
+        assert c.ctx.schedule_describe(ids)[0] == 0 and c.ctx.schedule_describe(ids8)[0] == 0
+    else:  # N = 512: the fused kernel, two-wave slots for r = 4
+        assert c.ctx.schedule_describe(ids)[:1] == (8,) and c.ctx.schedule_describe(ids)[3] == 2
     desc = [c.ctx.schedule_describe(ids, k) for k in range(c.ctx.schedule_count(ids))]
     assert any(d[0] == 8 and d[3] == 2 for d in desc)  # two-wave slots
     desc8 = [c.ctx.schedule_describe(ids8, k) for k in range(c.ctx.schedule_count(ids8))]
