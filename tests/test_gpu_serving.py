@@ -117,6 +117,25 @@ def test_admission_sheds_load_and_admitted_results_are_exact(setup):
     np.testing.assert_array_equal(out[~shed], ctx.bootstrap(ids[~shed], cts[~shed]))
 
 
+def test_ticks_switch_between_fused_and_global_kernels(setup):
+    """A burst of 1500 requests (ticks of many components per compute unit: the fused
+    kernel) followed by sparse arrivals (light ticks: the global-accumulator kernel with
+    four waves per component): ciphertexts change kernels between ticks, and every result
+    equals the same ciphertext bootstrapped alone."""
+    p, ctx, tabs, keys, b = setup
+    ids, cts, cls = _requests(p, keys, tabs, 1700, 11)
+    arrivals = np.concatenate([np.zeros(1500, np.int64),
+                               np.sort(np.random.default_rng(12).integers(0, 300_000_000, 200)) + 1000])
+    srv = ctx.server_start(1 << 30, chunk_steps=63)
+    out, lat = srv.replay(ids, cts, arrivals)
+    st = srv.stats()
+    srv.stop()
+    print("burst then sparse: p50 %.1f ms p99 %.1f ms; sparse part p50 %.1f ms" %
+          (np.percentile(lat, 50), np.percentile(lat, 99), np.percentile(lat[1500:], 50)))
+    assert st["completed"] == len(ids) and np.all(lat > 0)
+    np.testing.assert_array_equal(out, ctx.bootstrap(ids, cts))
+
+
 def test_server_errors(setup):
     p, ctx, tabs, keys, b = setup
     with pytest.raises(b.MMError):
