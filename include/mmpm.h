@@ -309,7 +309,9 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
  * admitted while others run joins them at the next launch.  At N = 1024 a tick
  * whose partition holds at most two components per compute unit (four when it
  * holds r = 8 ciphertexts) runs the global-accumulator kernels instead, with the
- * waves per component of the batched path's light default.  Tables of general
+ * four waves per component of the batched path's default (the accumulators then
+ * live in two arenas, so the budget counts 2 x 2 x N words per component at
+ * N = 1024, 2 x N elsewhere).  Tables of general
  * f are not served, nor, at the default modulus and N <= 8192, tables with
  * r N/1024 > 8.  A context on the global-accumulator path (Q2 != 0, or
  * N = 16384) is served with that path's kernels: each launch ("tick") is
