@@ -261,7 +261,9 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
  * the device mostly idle (at most two components per compute unit, or four when
  * no two-wave slots fit), or that hold more than 16 components per compute unit,
  * take the global-accumulator shape with four waves per component (each
- * component a small workgroup of its own); that shape, with its usual and with
+ * component a small workgroup of its own; up to two components per compute
+ * unit, with two digit groups of four waves: NTT schedule 4 below); that
+ * shape, with its usual and with
  * twice the waves (N = 512, 1024), is a candidate for every batch the fused
  * kernel holds.  A batch on the global-accumulator path
  * (see mm_params; the wide modulus among others) has one blind-rotation shape:
@@ -291,8 +293,10 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
  * (v_permlane16/32_swap), the others through LDS; 2: LDS exchanges with the two
  * polynomials staggered, one's relayout in flight while the other's
  * butterflies run; 3, global path only: the ring split into sub-rings of 8192,
- * the stages that mix them in separate launches).  Any output pointer may be
- * NULL. */
+ * the stages that mix them in separate launches; 4, the global-accumulator shape
+ * at N = 1024 with one prime: two groups of four waves per component, each
+ * taking every other gadget digit and one part's inverse NTT, for batches
+ * that leave compute units idle).  Any output pointer may be NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
                          int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
                          int *ntt_schedule);
@@ -309,7 +313,8 @@ int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int ch
  * admitted while others run joins them at the next launch.  At N = 1024 a tick
  * whose partition holds at most two components per compute unit (four when it
  * holds r = 8 ciphertexts) runs the global-accumulator kernels instead, with the
- * four waves per component of the batched path's default (the accumulators then
+ * four waves per component of the batched path's default, two digit groups of them
+ * up to two components per compute unit (the accumulators then
  * live in two arenas, so the budget counts 2 x 2 x N words per component at
  * N = 1024, 2 x N elsewhere).  Tables of general
  * f are not served, nor, at the default modulus and N <= 8192, tables with

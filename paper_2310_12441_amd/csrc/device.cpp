@@ -512,6 +512,15 @@ int light_global_wpp(const mm_ctx &c)
     return dev::wide_supports_wpp(c.p.N, 1, w2) ? w2 : 0;
 }
 
+// Digit groups per component of light global-path work: two (each group of
+// light_global_wpp waves taking every other digit) for batches of at most two
+// components per compute unit where that kernel exists, else one.
+int light_global_dg(const mm_ctx &c, const Device &d, uint64_t comps)
+{
+    const int w2 = light_global_wpp(c);
+    return w2 && dev::wide_supports_dg(c.p.N, primes_of(c), w2) && comps <= 2ull * (uint64_t)d.num_cu ? 2 : 1;
+}
+
 // Two waves per component (N = 512, 1024, r <= 4): for batches that do not
 // fill every compute unit, both waves of a slot share one component's work.
 static bool wide_slots_ok(const mm_ctx &c, const int *ids, size_t count)
@@ -571,8 +580,13 @@ static std::vector<Sched> candidates(const mm_ctx &c, const Device &d, const int
     // then run side by side instead of sharing one compute unit
     if (global_ok(c)) {
         for (auto &k : ks) out.push_back(Sched{0, k});
-        if (const int w2 = light_global_wpp(c))
+        if (const int w2 = light_global_wpp(c)) {
             for (auto &k : ks) out.push_back(Sched{0, k, w2});
+            // two digit groups per component (schedule 4): half a step's dependent
+            // chain per compute unit, for batches with compute units to spare
+            if (dev::wide_supports_dg(c.p.N, 1, w2))
+                for (auto &k : ks) out.push_back(Sched{0, k, w2, 4});
+        }
     }
     return out;
 }
@@ -598,12 +612,14 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
     // at r = 8) and batches of more than 16 components per compute unit (188.8 against
     // 203.8 ms for 16,384); in between the fused kernel (two-wave slots up to four
     // components per compute unit, 14.6 against 16.5 ms at 1024; one wave per component
-    // up to 16 per compute unit, 25.6 against 27.4 ms at 2048)
+    // up to 16 per compute unit, 25.6 against 27.4 ms at 2048).  Up to two components
+    // per compute unit, two digit groups per component (6.5 against 7.4 ms for one
+    // ciphertext, 12.2 against 12.7 ms for 512 components; 20.3 against 18.2 ms at 1024)
     const uint64_t comps = sum_r(c, ids, count), cu = (uint64_t)d.num_cu;
     const bool two_wave = wide_slots_ok(c, ids, count);
     if (global_ok(c) && c.p.N == 1024 && light_global_wpp(c) &&
         (comps <= 2 * cu || (!two_wave && comps <= 4 * cu) || comps > 16 * cu))
-        return Sched{0, ks_default(c, d, count), light_global_wpp(c)};
+        return Sched{0, ks_default(c, d, count), light_global_wpp(c), light_global_dg(c, d, comps) == 2 ? 4 : 0};
     return Sched{8, ks_default(c, d, count), comps <= 4 * cu && two_wave ? 2 : 0};
 }
 
@@ -807,7 +823,7 @@ static void split_buffers(const mm_ctx &c, Device &d, dev::WideArgs &A, size_t n
 // ACC init and `steps` CMux launches (three per step for a split ring, A.M > 0);
 // returns the buffer holding the result.
 static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_t *buf0, uint32_t *buf1,
-                                       uint32_t num_tasks, uint32_t steps, hipStream_t s, int wpp = 0)
+                                       uint32_t num_tasks, uint32_t steps, hipStream_t s, int wpp = 0, int dg = 1)
 {
     const uint32_t N = c.p.N;
     uint32_t *buf[2] = {buf0, buf1};
@@ -818,7 +834,7 @@ static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_
         A.acc_rd = buf[i & 1];
         A.acc_wr = buf[(i + 1) & 1];
         if (A.M) dev::launch_split_step(N, c.keys, A, num_tasks, s);
-        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s, wpp);
+        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s, wpp, dg);
     }
     return buf[steps & 1];
 }
@@ -853,7 +869,7 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
         d, key, use_graph, st,
         [&](hipStream_t s) {
             dev::WideArgs B = A;
-            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp);
+            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp, S.ntt == 4 ? 2 : 1);
             dev::launch_wide_extract(N, primes_of(c), B, doff, count, ext, s);
         },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, ks, part, s); });

@@ -123,5 +123,6 @@ void enqueue_keyswitch(const mm_ctx &c, Device &d, const uint32_t *ext, const in
 dev::WideArgs wide_args(const mm_ctx &c, const Device &d);
 int primes_of(const mm_ctx &c);
 int light_global_wpp(const mm_ctx &c);  // waves per component of light global-path work (0: the usual)
+int light_global_dg(const mm_ctx &c, const Device &d, uint64_t comps);  // digit groups of such work
 
 }  // namespace mm

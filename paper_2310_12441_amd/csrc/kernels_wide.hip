@@ -102,11 +102,17 @@ constexpr int wide_wpp(int N) { return N > 4096 ? N / 1024 : (N > 512 ? N / 512 
 // N = 2048), or what a workgroup of 16 waves leaves anyway.
 constexpr int wide_min_waves(int W) { return W >= 16 ? 4 : 3; }
 
-template <int N, int KEYS, int NPR, int W = wide_wpp(N)>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min_waves(W)))) void k_wide_step(WideArgs A)
+// DG = 2: two groups of W waves per workgroup share one component's step: group g
+// takes the digits u = g, g + 2, ... of the forward NTTs and products, the two
+// groups' products meet in LDS, and group g runs the inverse NTT of part g --
+// half the dependent chain of a step for a component on one compute unit, the
+// shape for batches that leave compute units idle.
+template <int N, int KEYS, int NPR, int W = wide_wpp(N), int DG = 1>
+__global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wide_min_waves(W)))) void k_wide_step(WideArgs A)
 {
     using G = Geo<N, W>;
     constexpr int E = G::E;
+    static_assert(DG == 1 || (DG == 2 && NPR == 1 && W < 16), "two digit groups: one prime, up to 8 waves each");
     // digit fields: l log2 B bits fit 32 with one prime (31-bit Q), up to 62 with two
     using Y = typename std::conditional<NPR == 1, uint32_t, uint64_t>::type;
     // a ternary secret keeps the first key's digit fields in LDS (each lane reads
@@ -124,13 +130,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
     constexpr bool DS = KEYS == 1 && W > 1 && 2 * G::SLOTW * 4 <= 160 * 1024;
     // 16 waves (N = 16384): the forward NTTs take one digit polynomial at a time
     constexpr bool ONE_AT_A_TIME = W >= 16;
-    __shared__ uint64_t lds64[G::SLOTW / 2 + (Y_LDS ? 2 * N : 0) + (DS ? G::SLOTW / 2 : 0)];
-    uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64);
-    uint64_t *const ylds = lds64 + G::SLOTW / 2;
+    constexpr int GS64 = G::SLOTW / 2 + (Y_LDS ? 2 * N : 0) + (DS ? G::SLOTW / 2 : 0);  // per group
+    __shared__ uint64_t lds64[GS64 * DG];
+    const int grp = DG > 1 ? (int)(threadIdx.x / (64 * W)) : 0;  // wave-uniform
+    uint32_t *const slot = reinterpret_cast<uint32_t *>(lds64 + grp * GS64);
+    uint64_t *const ylds = lds64 + grp * GS64 + G::SLOTW / 2;
     uint32_t *const slot2 = slot + G::SLOTW;  // DS only (ylds is ternary only)
     int par = 0;                              // relayouts so far: which slot the next one uses
     const WideTask T = A.tasks[blockIdx.x];
-    const int L = threadIdx.x;
+    const int L = DG > 1 ? (int)(threadIdx.x % (64 * W)) : (int)threadIdx.x;
     constexpr size_t CW = (size_t)2 * NPR * N, PW = (size_t)NPR * N;  // words per component, per part
     const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * CW;
     uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * CW;
@@ -182,15 +190,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
 #pragma unroll
         for (int part = 0; part < 2; part++)
 #pragma unroll
-            for (int k = 0; k < E; k++) out[part][k] = corr[part * N + k];
+            for (int k = 0; k < E; k++) out[part][k] = grp == 0 ? corr[part * N + k] : 0u;  // once per component
     };
     // out += the digits of y times BSK_{i,key} for one prime (eq. def:gsw)
     auto mac = [&](int pr, int key, uint32_t (&out)[2][E], bool from_lds = false) {
         const uint32_t *Kp = A.bsk + (((size_t)i * KEYS + key) * NPR + pr) * (2 * A.l * 2 * N);
-        for (uint32_t u = 0; u < A.l; u++) {
+        // with two digit groups both run the same number of NTTs (their relayouts meet at
+        // the same workgroup barriers): a group without a digit left transforms zeros
+        for (uint32_t u0 = 0; u0 < A.l; u0 += DG) {
             __asm__ volatile("" ::: "memory");
-            const uint32_t sh = u * A.log2B;
-            const Y mask = u + 1 == A.l ? ~(Y)0 : (Y)(((Y)1 << A.log2B) - 1);
+            const uint32_t u = u0 + (uint32_t)grp;
+            const bool real = DG == 1 || u < A.l;
+            const uint32_t sh = real ? u * A.log2B : 0u;
+            const Y mask = !real ? (Y)0 : (u + 1 == A.l ? ~(Y)0 : (Y)(((Y)1 << A.log2B) - 1));
             if constexpr (ONE_AT_A_TIME) {
                 // one digit polynomial at a time (16 waves leave 128 registers per lane):
                 // the digit of b meets rows u, then the digit of a rows l + u
@@ -224,6 +236,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
                 pd[1][k] = (uint32_t)((ya >> sh) & mask);  // digit of a meets rows l + u
             }
             ntt_fwd<N, 2, W, PRIO, DS>(pd, slot, pr ? A.twf1 : A.twf0, L, mod(pr), slot2, &par);
+            if (!real) continue;
             const uint32_t *kb_a = Kp + ((size_t)u * 2 + 0) * N + L * E;
             const uint32_t *kb_b = Kp + ((size_t)u * 2 + 1) * N + L * E;
             const uint32_t *ka_a = Kp + ((size_t)(A.l + u) * 2 + 0) * N + L * E;
@@ -240,6 +253,28 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(wide_min
     // inverse NTT, ACC_j + product, store to the other buffer
     auto finish = [&](int pr, uint32_t (&out)[2][E]) {
         __asm__ volatile("" ::: "memory");
+        if constexpr (DG == 2) {
+            // group g hands its product of part 1 - g to the other group through its
+            // own exchange slot and finishes part g
+            uint32_t *const theirs = reinterpret_cast<uint32_t *>(lds64 + (1 - grp) * GS64);
+            __syncthreads();  // every relayout of the forward NTTs is done
+#pragma unroll
+            for (int k = 0; k < E; k++) slot[k * G::LANES + L] = grp == 0 ? out[1][k] : out[0][k];
+            __syncthreads();
+            uint32_t o1[1][E];
+#pragma unroll
+            for (int k = 0; k < E; k++)
+                o1[0][k] = add_q(grp == 0 ? out[0][k] : out[1][k], theirs[k * G::LANES + L], mod(pr).Q);
+            __syncthreads();  // both slots read before the inverse relayouts reuse them
+            ntt_inv<N, 1, W, PRIO, DS>(o1, slot, pr ? A.twi1 : A.twi0, L, mod(pr), slot2, &par);
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const uint32_t idx = G::LANES * k + L;
+                const size_t at = (size_t)grp * PW + pr * N + idx;
+                wr[at] = add_q(o1[0][k], own[at], mod(pr).Q);
+            }
+            return;
+        }
         ntt_inv<N, 2, W, PRIO, DS>(out, slot, pr ? A.twi1 : A.twi0, L, mod(pr), slot2, &par);
 #pragma unroll
         for (int part = 0; part < 2; part++)
@@ -582,8 +617,13 @@ void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks
 }
 
 void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st,
-                      int wpp)
+                      int wpp, int dg)
 {
+    if (dg == 2 && npr == 1 && N == 1024 && wpp == 4) {
+        if (keys == 2) hipLaunchKernelGGL((k_wide_step<1024, 2, 1, 4, 2>), dim3(num_tasks), dim3(512), 0, st, A);
+        else hipLaunchKernelGGL((k_wide_step<1024, 1, 1, 4, 2>), dim3(num_tasks), dim3(512), 0, st, A);
+        return;
+    }
     if (npr == 1 && wpp > 0 && wpp != wide_wpp((int)N)) {
         // twice the waves per component (N = 512, 1024; one prime): the step's work
         // on more SIMDs of each component's compute unit
@@ -651,6 +691,8 @@ bool wide_supports_wpp(uint32_t N, int npr, int wpp)
 {
     return wpp == wide_wpp((int)N) || (npr == 1 && ((N == 1024 && wpp == 4) || (N == 512 && wpp == 2)));
 }
+
+bool wide_supports_dg(uint32_t N, int npr, int wpp) { return N == 1024 && npr == 1 && wpp == 4; }
 
 bool wide_supports_n(uint32_t N, int npr)
 {

@@ -341,8 +341,9 @@ def test_every_schedule_gives_the_same_bits(paper):
     assert {paper.ctx.schedule_describe(ids, k)[3] for k in range(n)} == {1, 2, 4}
     assert {paper.ctx.schedule_describe(ids, k)[0] for k in range(n)} == {0, 4, 8}
     assert {paper.ctx.schedule_describe(ids, k)[4] for k in range(n)} == {1, 2}
-    # the three NTT stage schedules (LDS lockstep, lane swaps, staggered LDS)
-    assert {paper.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2}
+    # the three NTT stage schedules (LDS lockstep, lane swaps, staggered LDS) and the
+    # global shape's two digit groups
+    assert {paper.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2, 4}
     ref = None
     for choice in range(n):
         paper.ctx.set_schedule(ids, choice)
@@ -431,7 +432,7 @@ def test_ternary_every_schedule():
     ids = np.full(40, tid, np.int32)
     want = oracle.bootstrap_many(case.p, 4, case.keys.bsk, case.keys.ksk, V, 8192, 8192, ct)
     n = case.ctx.schedule_count(ids)
-    assert {case.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2}
+    assert {case.ctx.schedule_describe(ids, k)[5] for k in range(n)} == {0, 1, 2, 4}
     for choice in range(n):
         case.ctx.set_schedule(ids, choice)
         np.testing.assert_array_equal(case.ctx.bootstrap(ids, ct), want, err_msg=f"schedule {choice}")
@@ -611,6 +612,44 @@ def test_two_wave_slots_small_batches(N, ternary):
     for k in range(c.ctx.schedule_count(ids8)):
         c.ctx.set_schedule(ids8, k)
         np.testing.assert_array_equal(c.ctx.bootstrap(ids8, ct8), want8, err_msg=f"r = 8, schedule {k}")
+    c.ctx.close()
+
+
+@pytest.mark.parametrize("l,log2_B,ternary", [(4, 7, False), (3, 10, False), (3, 10, True), (5, 6, True),
+                                               (1, 15, False)])
+def test_two_digit_groups(l, log2_B, ternary):
+    """NTT schedule 4 of the global-accumulator shape at N = 1024: two groups of four
+    waves per component, each taking every other gadget digit (odd l: the second
+    group transforms zeros on its last pass) and one part's inverse NTT.  One
+    ciphertext, a batch of mixed r and a batch spanning every compute unit several
+    times against the oracle."""
+    from dataclasses import replace
+    say("two digit groups l", l, "log2_B", log2_B, "ternary", ternary)
+    p = replace(Params(n=12, N=1024, log2_B=log2_B, l=l), ternary=ternary)
+    c = Case(p, 1700 + 10 * l + ternary)
+    tid, f, V = c.table(2048, 2048, 4, 41)
+    tid8, f8, V8 = c.table(64, 64, 8, 42)
+    for cnt, mixed in ((1, False), (7, True), (700, False)):
+        say("  count", cnt, "mixed", mixed)
+        r_of = [8 if mixed and j % 3 == 1 else 4 for j in range(cnt)]
+        ids = np.array([tid8 if r == 8 else tid for r in r_of], np.int32)
+        ct = np.array([c.encrypt(2 * 1024 * r, 64 if r == 8 else 2048,
+                                 messages(64 if r == 8 else 2048, 1, 43 + j), 44 + j)[0] for j, r in enumerate(r_of)])
+        n = c.ctx.schedule_count(ids)
+        dg = [k for k in range(n) if c.ctx.schedule_describe(ids, k)[5] == 4]
+        assert dg and all(c.ctx.schedule_describe(ids, k)[:1] == (0,) and c.ctx.schedule_describe(ids, k)[3] == 4
+                          for k in dg)
+        c.ctx.set_schedule(ids, dg[0])
+        out = c.ctx.bootstrap(ids, ct)
+        picks = range(cnt) if cnt < 10 else (0, 1, cnt // 2, cnt - 1)
+        for j in picks:
+            r = r_of[j]
+            q = 2 * 1024 * r
+            np.testing.assert_array_equal(out[j], oracle.bootstrap(p, r, c.keys.bsk, c.keys.ksk, V8 if r == 8 else V,
+                                                                   q, q, ct[j]), err_msg=f"ciphertext {j}")
+        if cnt >= 10:
+            c.ctx.set_schedule(ids, [k for k in range(n) if c.ctx.schedule_describe(ids, k)[5] != 4][0])
+            np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), out)
     c.ctx.close()
 
 
