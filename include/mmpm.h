@@ -266,9 +266,10 @@ int mm_last_timing(mm_ctx *ctx, float *blind_rotate_ms, float *keyswitch_ms);
  * shape, with its usual and with
  * twice the waves (N = 512, 1024), is a candidate for every batch the fused
  * kernel holds.  A batch on the global-accumulator path
- * (see mm_params; the wide modulus among others) has one blind-rotation shape:
- * its candidates differ in the key switch only, and this call runs the batch
- * once and then times each key switch on its extracted samples. */
+ * (see mm_params; the wide modulus among others) has one or two blind-rotation
+ * shapes (two primes: one workgroup per component, or per component and
+ * prime; N = 16384: one workgroup per component, or the split ring): this call
+ * times each shape once, then each key switch on the extracted samples. */
 int mm_autotune(mm_ctx *ctx, const int *table_ids, const uint32_t *ct_in, size_t count,
                 int *choice);
 
@@ -296,7 +297,9 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
  * the stages that mix them in separate launches; 4, the global-accumulator shape
  * at N = 1024 with one prime: two groups of four waves per component, each
  * taking every other gadget digit and one part's inverse NTT, for batches
- * that leave compute units idle).  Any output pointer may be NULL. */
+ * that leave compute units idle; 5, the global-accumulator path with two primes:
+ * one workgroup per component and prime, the default up to 16 components per
+ * compute unit).  Any output pointer may be NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
                          int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
                          int *ntt_schedule);

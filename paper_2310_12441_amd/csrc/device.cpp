@@ -495,7 +495,8 @@ int primes_of(const mm_ctx &c) { return c.wide ? 2 : 1; }
 // sub-rings of 8192 (schedule 3; one prime, rings of 16384 and more).
 static std::vector<int> global_shapes(const mm_ctx &c)
 {
-    if (c.wide || !dev::split_supports_n(c.p.N)) return {0};
+    if (c.wide) return dev::wide_supports_ps(c.p.N, 2) ? std::vector<int>{0, 5} : std::vector<int>{0};
+    if (!dev::split_supports_n(c.p.N)) return {0};
     if (c.p.N > 16384) return {3};
     return {0, 3};
 }
@@ -510,6 +511,16 @@ int light_global_wpp(const mm_ctx &c)
 {
     const int w2 = 2 * dev::wide_waves_per_poly(c.p.N);
     return dev::wide_supports_wpp(c.p.N, 1, w2) ? w2 : 0;
+}
+
+// One workgroup per component and prime (two primes) for batches of up to 16
+// components per compute unit.  Measured at the paper-margin parameters (N = 2048,
+// ternary, ms per bootstrap call, both shapes): one ciphertext 19.2 against 38.6,
+// 256 components 30.2 against 41.5, 1024 87.7 against 94.8, 4096 332.1 against
+// 335.3; 8192 669.2 against 663.2 (the shared digit fields computed twice).
+bool prime_split(const mm_ctx &c, const Device &d, uint64_t comps)
+{
+    return c.wide && dev::wide_supports_ps(c.p.N, 2) && comps <= 16ull * (uint64_t)d.num_cu;
 }
 
 // Digit groups per component of light global-path work: two (each group of
@@ -599,6 +610,7 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         if (it->second >= 0 && (size_t)it->second < cand.size()) return cand[it->second];
     }
     if (use_global(c, ids, count)) {
+        if (prime_split(c, d, sum_r(c, ids, count))) return Sched{0, ks_default(c, d, count), 0, 5};
         const int shape = global_shapes(c).front();
         return Sched{0, ks_default(c, d, count), shape == 3 ? dev::SPLIT_WAVES : 0, shape};
     }
@@ -823,7 +835,8 @@ static void split_buffers(const mm_ctx &c, Device &d, dev::WideArgs &A, size_t n
 // ACC init and `steps` CMux launches (three per step for a split ring, A.M > 0);
 // returns the buffer holding the result.
 static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_t *buf0, uint32_t *buf1,
-                                       uint32_t num_tasks, uint32_t steps, hipStream_t s, int wpp = 0, int dg = 1)
+                                       uint32_t num_tasks, uint32_t steps, hipStream_t s, int wpp = 0, int dg = 1,
+                                       bool ps = false)
 {
     const uint32_t N = c.p.N;
     uint32_t *buf[2] = {buf0, buf1};
@@ -834,7 +847,7 @@ static uint32_t *enqueue_wide_rotation(const mm_ctx &c, dev::WideArgs A, uint32_
         A.acc_rd = buf[i & 1];
         A.acc_wr = buf[(i + 1) & 1];
         if (A.M) dev::launch_split_step(N, c.keys, A, num_tasks, s);
-        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s, wpp, dg);
+        else dev::launch_wide_step(N, primes_of(c), c.keys, A, num_tasks, s, wpp, dg, ps);
     }
     return buf[steps & 1];
 }
@@ -869,7 +882,8 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
         d, key, use_graph, st,
         [&](hipStream_t s) {
             dev::WideArgs B = A;
-            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp, S.ntt == 4 ? 2 : 1);
+            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp, S.ntt == 4 ? 2 : 1,
+                                             S.ntt == 5);
             dev::launch_wide_extract(N, primes_of(c), B, doff, count, ext, s);
         },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, ks, part, s); });

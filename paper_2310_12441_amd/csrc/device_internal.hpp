@@ -124,5 +124,6 @@ dev::WideArgs wide_args(const mm_ctx &c, const Device &d);
 int primes_of(const mm_ctx &c);
 int light_global_wpp(const mm_ctx &c);  // waves per component of light global-path work (0: the usual)
 int light_global_dg(const mm_ctx &c, const Device &d, uint64_t comps);  // digit groups of such work
+bool prime_split(const mm_ctx &c, const Device &d, uint64_t comps);     // one workgroup per prime
 
 }  // namespace mm

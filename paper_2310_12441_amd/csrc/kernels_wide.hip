@@ -107,12 +107,18 @@ constexpr int wide_min_waves(int W) { return W >= 16 ? 4 : 3; }
 // groups' products meet in LDS, and group g runs the inverse NTT of part g --
 // half the dependent chain of a step for a component on one compute unit, the
 // shape for batches that leave compute units idle.
-template <int N, int KEYS, int NPR, int W = wide_wpp(N), int DG = 1>
+//
+// PS (two primes): two workgroups per component, one per prime (blockIdx.x = 2 task +
+// prime): both form the digit fields from both residues, each runs the NTTs, key
+// products and inverse NTT of its own prime and writes that prime's residues --
+// for batches with compute units to spare, half the dependent chain of a step.
+template <int N, int KEYS, int NPR, int W = wide_wpp(N), int DG = 1, bool PS = false>
 __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wide_min_waves(W)))) void k_wide_step(WideArgs A)
 {
     using G = Geo<N, W>;
     constexpr int E = G::E;
     static_assert(DG == 1 || (DG == 2 && NPR == 1 && W < 16), "two digit groups: one prime, up to 8 waves each");
+    static_assert(!PS || (NPR == 2 && DG == 1), "one workgroup per prime: two primes");
     // digit fields: l log2 B bits fit 32 with one prime (31-bit Q), up to 62 with two
     using Y = typename std::conditional<NPR == 1, uint32_t, uint64_t>::type;
     // a ternary secret keeps the first key's digit fields in LDS (each lane reads
@@ -137,16 +143,25 @@ __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wid
     uint64_t *const ylds = lds64 + grp * GS64 + G::SLOTW / 2;
     uint32_t *const slot2 = slot + G::SLOTW;  // DS only (ylds is ternary only)
     int par = 0;                              // relayouts so far: which slot the next one uses
-    const WideTask T = A.tasks[blockIdx.x];
+    const WideTask T = A.tasks[PS ? blockIdx.x / 2 : blockIdx.x];
     const int L = DG > 1 ? (int)(threadIdx.x % (64 * W)) : (int)threadIdx.x;
     constexpr size_t CW = (size_t)2 * NPR * N, PW = (size_t)NPR * N;  // words per component, per part
     const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * CW;
     uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * CW;
+    // the primes this workgroup computes: both, or its own with PS
+    const int pr_lo = PS ? (int)(blockIdx.x % 2) : 0, pr_hi = PS ? pr_lo + 1 : NPR;
     const uint32_t i = T.i0 + A.step;  // this task's CMux step
     if (i >= A.n) {
         // past step n - 1 (a ciphertext that finishes inside a sequence of launches):
         // carry the component over to the buffer the next launch reads
-        for (uint32_t w = threadIdx.x; w < (uint32_t)CW; w += blockDim.x) wr[w] = own[w];
+        if constexpr (PS) {
+            for (uint32_t w = threadIdx.x; w < 2u * N; w += blockDim.x) {
+                const size_t at = (size_t)(w / N) * PW + (size_t)pr_lo * N + w % N;
+                wr[at] = own[at];
+            }
+        } else {
+            for (uint32_t w = threadIdx.x; w < (uint32_t)CW; w += blockDim.x) wr[w] = own[w];
+        }
         return;
     }
     const uint32_t M = 2u * N * T.r;
@@ -289,7 +304,7 @@ __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wid
         // one prime at a time: only one prime's outputs are live
         digit_fields(0);
 #pragma unroll
-        for (int pr = 0; pr < NPR; pr++) {
+        for (int pr = pr_lo; pr < pr_hi; pr++) {
             uint32_t out[2][E];
             start(pr, out);
             mac(pr, 0, out);
@@ -304,7 +319,7 @@ __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wid
             for (int k = 0; k < E; k++) ylds[(part * E + k) * G::LANES + L] = y[part][k];
         digit_fields(1);
 #pragma unroll
-        for (int pr = 0; pr < NPR; pr++) {
+        for (int pr = pr_lo; pr < pr_hi; pr++) {
             uint32_t out[2][E];
             start(pr, out);
             mac(pr, 1, out);
@@ -315,7 +330,7 @@ __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wid
         // one prime at a time as well; each key's digit fields are formed again
         // for the second prime (cheaper than keeping both primes' outputs live)
 #pragma unroll
-        for (int pr = 0; pr < NPR; pr++) {
+        for (int pr = pr_lo; pr < pr_hi; pr++) {
             uint32_t out[2][E];
             start(pr, out);
             for (int key = 0; key < 2; key++) {
@@ -616,9 +631,26 @@ void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks
 #undef C_
 }
 
-void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st,
-                      int wpp, int dg)
+// One CMux-step launch with one workgroup per component and prime (two primes only).
+template <int n, int p>
+static void ps_launch(uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
 {
+    if constexpr (p == 2) {
+        const dim3 grid(2 * num_tasks), block(64 * wide_wpp(n));
+        if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2, 2, wide_wpp(n), 1, true>), grid, block, 0, st, A);
+        else hipLaunchKernelGGL((k_wide_step<n, 1, 2, wide_wpp(n), 1, true>), grid, block, 0, st, A);
+    }
+}
+
+void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st,
+                      int wpp, int dg, bool ps)
+{
+    if (ps && npr == 2) {
+#define P_(n, p) ps_launch<n, p>(keys, A, num_tasks, st)
+        WIDE_DISPATCH(N, 2, P_)
+#undef P_
+        return;
+    }
     if (dg == 2 && npr == 1 && N == 1024 && wpp == 4) {
         if (keys == 2) hipLaunchKernelGGL((k_wide_step<1024, 2, 1, 4, 2>), dim3(num_tasks), dim3(512), 0, st, A);
         else hipLaunchKernelGGL((k_wide_step<1024, 1, 1, 4, 2>), dim3(num_tasks), dim3(512), 0, st, A);
@@ -693,6 +725,8 @@ bool wide_supports_wpp(uint32_t N, int npr, int wpp)
 }
 
 bool wide_supports_dg(uint32_t N, int npr, int wpp) { return N == 1024 && npr == 1 && wpp == 4; }
+
+bool wide_supports_ps(uint32_t N, int npr) { return npr == 2 && wide_supports_n(N, 2); }
 
 bool wide_supports_n(uint32_t N, int npr)
 {

@@ -554,11 +554,12 @@ void Server::launch_global(Part &p, const std::vector<Active> &fresh)
     A.tasks = p.wtasks.d + n_init;
     const int wpp = switchable ? light_global_wpp(*c) : 0;
     const int dg = switchable ? light_global_dg(*c, d, n_step) : 1;
+    const bool ps = prime_split(*c, d, n_step);
     for (uint32_t s = 0; s < chunk; s++) {
         A.step = s;
         A.acc_rd = arena[p.cur];
         A.acc_wr = arena[p.cur ^ 1];
-        dev::launch_wide_step(N, npr, c->keys, A, (uint32_t)n_step, p.st, wpp, dg);
+        dev::launch_wide_step(N, npr, c->keys, A, (uint32_t)n_step, p.st, wpp, dg, ps);
         p.cur ^= 1;
     }
     std::vector<Active> keep;

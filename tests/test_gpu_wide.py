@@ -225,25 +225,35 @@ def test_wide_empty_and_rejected_calls():
         c.ctx.server_start(1 << 10)  # below one component's two accumulators
 
 
-def test_wide_schedules_give_the_same_bits_and_autotune():
-    """At the wide modulus the blind rotation has one shape (reported as 0 waves per
-    fused group, one workgroup of N / 512 waves per component); the schedules differ in
-    the key switch, every one gives the oracle's bits, and autotuning picks one of them."""
-    c = case(256, 8)
-    r, t = 2, 16
-    q = 2 * 256 * r
+@pytest.mark.parametrize("N,ternary,r,count", [(256, False, 2, 70), (2048, True, 1, 3), (512, True, 4, 80)])
+def test_wide_schedules_give_the_same_bits_and_autotune(N, ternary, r, count):
+    """At the wide modulus the blind rotation has two shapes (reported as 0 waves per
+    fused group, one workgroup of N / 512 waves per component): one workgroup per
+    component (NTT schedule 0) or one per component and prime (5, the default up to 16
+    components per compute unit); the schedules
+    also differ in the key switch, every one gives the oracle's bits, and autotuning
+    picks one of them."""
+    say("wide schedules N", N, "ternary", ternary, "r", r, "count", count)
+    c = case(N, 8, ternary)
+    t = 16
+    q = 2 * N * r
     tid, f, V = c.table(t, r, 31)
-    ct = c.encrypt(q, t, messages(t, 70, 32), 33)
+    ct = c.encrypt(q, t, messages(t, count, 32), 33)
     ids = np.full(len(ct), tid, np.int32)
     n = c.ctx.schedule_count(ids)
     desc = [c.ctx.schedule_describe(ids, k) for k in range(n)]
     say("wide schedules:", desc)
-    assert n >= 2 and all(d[0] == 0 and d[3] == 1 and d[5] == 0 for d in desc)
-    assert {d[4] for d in desc} >= {0, 1}  # i-split and LDS-tiled key switches
+    assert n >= 2 and all(d[0] == 0 and d[3] == max(1, N // 512) for d in desc)
+    assert {d[5] for d in desc} == {0, 5}
+    assert c.ctx.schedule_describe(ids)[5] == 5  # the default up to 16 components per compute unit
+    if count >= 64:
+        assert {d[4] for d in desc} >= {0, 1}  # i-split and LDS-tiled key switches
     want = oracle.w_bootstrap_many(c.p, r, c.keys.bsk, c.keys.ksk, V, q, q, ct)
     for k in range(n):
         c.ctx.set_schedule(ids, k)
         np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct), want, err_msg=f"schedule {k}")
+        if desc[k][5] == 5:
+            np.testing.assert_array_equal(c.ctx.bootstrap(ids, ct, plain=True), want, err_msg=f"plain, schedule {k}")
     choice = c.ctx.autotune(ids, ct)
     assert 0 <= choice < n
     assert c.ctx.schedule_describe(ids) == desc[choice]
