@@ -257,7 +257,7 @@ def main():
     mix = MIX_CEILING_LANE_OPS[waves_per_simd]
     hbm_alg = (bsk_bytes(p.n, p.N, p.l) + B * (p.n + 1) * 4 + B * (p.N + 1) * 4) // launches
     if global_shape:
-        kname = f"k_wide_step<{p.N},1,1,{sched[3]},{2 if sched[5] == 4 else 1}>"
+        kname = f"k_wide_step<{p.N},1,1,{sched[3]},{2 if sched[5] == 4 else 1},false>"
     else:
         kname = f"k_blind_rotate<{p.N},{sched[0]},1,{sched[3]}" + (",true" if sched[5] == 1 else "") + ">"
     roofline = {
