@@ -299,7 +299,8 @@ int mm_set_schedule(mm_ctx *ctx, const int *table_ids, size_t count, int choice)
  * taking every other gadget digit and one part's inverse NTT, for batches
  * that leave compute units idle; 5, the global-accumulator path with two primes:
  * one workgroup per component and prime, the default up to 16 components per
- * compute unit).  Any output pointer may be NULL. */
+ * compute unit; 6, those workgroups with two digit groups, N = 1024 and 2048,
+ * the default while all of them fit one per compute unit).  Any output pointer may be NULL. */
 int mm_schedule_describe(mm_ctx *ctx, const int *table_ids, size_t count, int choice, int *group_waves,
                          int *ks_cts_per_wave, int *ks_splits, int *waves_per_component, int *ks_kernel,
                          int *ntt_schedule);

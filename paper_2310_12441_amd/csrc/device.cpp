@@ -492,10 +492,17 @@ int primes_of(const mm_ctx &c) { return c.wide ? 2 : 1; }
 
 // Blind-rotation shapes of the global path: one workgroup per component and
 // CMux step (NTT schedule 0; rings up to 16384), or the ring split into
-// sub-rings of 8192 (schedule 3; one prime, rings of 16384 and more).
+// sub-rings of 8192 (schedule 3; one prime, rings of 16384 and more); with two
+// primes also one workgroup per component and prime (5), of two digit groups
+// (6, N = 1024 and 2048).
 static std::vector<int> global_shapes(const mm_ctx &c)
 {
-    if (c.wide) return dev::wide_supports_ps(c.p.N, 2) ? std::vector<int>{0, 5} : std::vector<int>{0};
+    if (c.wide) {
+        std::vector<int> v{0};
+        if (dev::wide_supports_ps(c.p.N, 2)) v.push_back(5);
+        if (dev::wide_supports_ps(c.p.N, 2, 2)) v.push_back(6);
+        return v;
+    }
     if (!dev::split_supports_n(c.p.N)) return {0};
     if (c.p.N > 16384) return {3};
     return {0, 3};
@@ -521,6 +528,15 @@ int light_global_wpp(const mm_ctx &c)
 bool prime_split(const mm_ctx &c, const Device &d, uint64_t comps)
 {
     return c.wide && dev::wide_supports_ps(c.p.N, 2) && comps <= 16ull * (uint64_t)d.num_cu;
+}
+
+// Digit groups of those workgroups: two (N = 1024, 2048) while both primes' workgroups
+// of every component fit one per compute unit (one ciphertext at N = 2048, t = 2^12:
+// 18.7 against 19.9 ms; 256 components 34.6 against 29.0 ms), else one.
+int prime_split_dg(const mm_ctx &c, const Device &d, uint64_t comps)
+{
+    return prime_split(c, d, comps) && dev::wide_supports_ps(c.p.N, 2, 2) && 2 * comps <= (uint64_t)d.num_cu ? 2
+                                                                                                            : 1;
 }
 
 // Digit groups per component of light global-path work: two (each group of
@@ -610,7 +626,9 @@ static Sched schedule_for(const mm_ctx &c, const Device &d, const int *ids, size
         if (it->second >= 0 && (size_t)it->second < cand.size()) return cand[it->second];
     }
     if (use_global(c, ids, count)) {
-        if (prime_split(c, d, sum_r(c, ids, count))) return Sched{0, ks_default(c, d, count), 0, 5};
+        const uint64_t comps = sum_r(c, ids, count);
+        if (prime_split(c, d, comps))
+            return Sched{0, ks_default(c, d, count), 0, prime_split_dg(c, d, comps) == 2 ? 6 : 5};
         const int shape = global_shapes(c).front();
         return Sched{0, ks_default(c, d, count), shape == 3 ? dev::SPLIT_WAVES : 0, shape};
     }
@@ -882,8 +900,8 @@ static void bootstrap_wide(mm_ctx &c, Device &d, const int *ids, const uint32_t 
         d, key, use_graph, st,
         [&](hipStream_t s) {
             dev::WideArgs B = A;
-            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp, S.ntt == 4 ? 2 : 1,
-                                             S.ntt == 5);
+            B.acc_rd = enqueue_wide_rotation(c, A, acc0, acc1, nt, c.p.n, s, S.ntt == 3 ? 0 : S.wpp,
+                                             S.ntt == 4 || S.ntt == 6 ? 2 : 1, S.ntt == 5 || S.ntt == 6);
             dev::launch_wide_extract(N, primes_of(c), B, doff, count, ext, s);
         },
         [&](hipStream_t s) { enqueue_keyswitch(c, d, ext, nullptr, count, d_out, qv, q_scalar, ks, part, s); });

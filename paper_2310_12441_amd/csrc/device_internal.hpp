@@ -125,5 +125,6 @@ int primes_of(const mm_ctx &c);
 int light_global_wpp(const mm_ctx &c);  // waves per component of light global-path work (0: the usual)
 int light_global_dg(const mm_ctx &c, const Device &d, uint64_t comps);  // digit groups of such work
 bool prime_split(const mm_ctx &c, const Device &d, uint64_t comps);     // one workgroup per prime
+int prime_split_dg(const mm_ctx &c, const Device &d, uint64_t comps);   // digit groups of those
 
 }  // namespace mm

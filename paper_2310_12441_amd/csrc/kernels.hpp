@@ -143,12 +143,12 @@ void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks
 // wpp: waves per component workgroup (0: wide_waves_per_poly(N)); with one prime
 // also twice that at N = 512 and 1024 (wide_supports_wpp).
 // dg = 2 (N = 1024, wpp = 4, one prime): two digit groups of wpp waves per component.
-// ps (two primes): one workgroup per component and prime.
+// ps (two primes): one workgroup per component and prime (dg = 2 too: N = 1024, 2048).
 void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st,
                       int wpp = 0, int dg = 1, bool ps = false);
 bool wide_supports_wpp(uint32_t N, int npr, int wpp);
 bool wide_supports_dg(uint32_t N, int npr, int wpp);  // two digit groups of wpp waves
-bool wide_supports_ps(uint32_t N, int npr);           // one workgroup per prime
+bool wide_supports_ps(uint32_t N, int npr, int dg = 1);  // one workgroup per prime (of dg digit groups)
 void launch_wide_extract(uint32_t N, int npr, const WideArgs &A, const uint64_t *acc_off, size_t count,
                          uint32_t *ext, hipStream_t st);
 void launch_wide_export(uint32_t N, const WideArgs &A, uint32_t num_tasks, uint32_t *out, hipStream_t st);

@@ -112,13 +112,15 @@ constexpr int wide_min_waves(int W) { return W >= 16 ? 4 : 3; }
 // prime): both form the digit fields from both residues, each runs the NTTs, key
 // products and inverse NTT of its own prime and writes that prime's residues --
 // for batches with compute units to spare, half the dependent chain of a step.
+// With DG = 2 as well, each such workgroup splits its prime's digits over two groups.
 template <int N, int KEYS, int NPR, int W = wide_wpp(N), int DG = 1, bool PS = false>
 __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wide_min_waves(W)))) void k_wide_step(WideArgs A)
 {
     using G = Geo<N, W>;
     constexpr int E = G::E;
-    static_assert(DG == 1 || (DG == 2 && NPR == 1 && W < 16), "two digit groups: one prime, up to 8 waves each");
-    static_assert(!PS || (NPR == 2 && DG == 1), "one workgroup per prime: two primes");
+    static_assert(DG == 1 || (DG == 2 && (NPR == 1 || PS) && W < 16),
+                  "two digit groups: one prime per workgroup, up to 8 waves each");
+    static_assert(!PS || NPR == 2, "one workgroup per prime: two primes");
     // digit fields: l log2 B bits fit 32 with one prime (31-bit Q), up to 62 with two
     using Y = typename std::conditional<NPR == 1, uint32_t, uint64_t>::type;
     // a ternary secret keeps the first key's digit fields in LDS (each lane reads
@@ -631,14 +633,15 @@ void launch_wide_init(uint32_t N, int npr, const WideArgs &A, uint32_t num_tasks
 #undef C_
 }
 
-// One CMux-step launch with one workgroup per component and prime (two primes only).
-template <int n, int p>
+// One CMux-step launch with one workgroup per component and prime (two primes only),
+// of dg digit groups (two: N = 1024 and 2048).
+template <int n, int p, int dg = 1>
 static void ps_launch(uint32_t keys, const WideArgs &A, uint32_t num_tasks, hipStream_t st)
 {
-    if constexpr (p == 2) {
-        const dim3 grid(2 * num_tasks), block(64 * wide_wpp(n));
-        if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2, 2, wide_wpp(n), 1, true>), grid, block, 0, st, A);
-        else hipLaunchKernelGGL((k_wide_step<n, 1, 2, wide_wpp(n), 1, true>), grid, block, 0, st, A);
+    if constexpr (p == 2 && (dg == 1 || n == 1024 || n == 2048)) {
+        const dim3 grid(2 * num_tasks), block(64 * wide_wpp(n) * dg);
+        if (keys == 2) hipLaunchKernelGGL((k_wide_step<n, 2, 2, wide_wpp(n), dg, true>), grid, block, 0, st, A);
+        else hipLaunchKernelGGL((k_wide_step<n, 1, 2, wide_wpp(n), dg, true>), grid, block, 0, st, A);
     }
 }
 
@@ -646,9 +649,13 @@ void launch_wide_step(uint32_t N, int npr, uint32_t keys, const WideArgs &A, uin
                       int wpp, int dg, bool ps)
 {
     if (ps && npr == 2) {
+        if (dg == 2 && N == 1024) ps_launch<1024, 2, 2>(keys, A, num_tasks, st);
+        else if (dg == 2 && N == 2048) ps_launch<2048, 2, 2>(keys, A, num_tasks, st);
+        else {
 #define P_(n, p) ps_launch<n, p>(keys, A, num_tasks, st)
-        WIDE_DISPATCH(N, 2, P_)
+            WIDE_DISPATCH(N, 2, P_)
 #undef P_
+        }
         return;
     }
     if (dg == 2 && npr == 1 && N == 1024 && wpp == 4) {
@@ -726,7 +733,7 @@ bool wide_supports_wpp(uint32_t N, int npr, int wpp)
 
 bool wide_supports_dg(uint32_t N, int npr, int wpp) { return N == 1024 && npr == 1 && wpp == 4; }
 
-bool wide_supports_ps(uint32_t N, int npr) { return npr == 2 && wide_supports_n(N, 2); }
+bool wide_supports_ps(uint32_t N, int npr, int dg) { return npr == 2 && wide_supports_n(N, 2) && (dg == 1 || N == 1024 || N == 2048); }
 
 bool wide_supports_n(uint32_t N, int npr)
 {

@@ -553,8 +553,8 @@ void Server::launch_global(Part &p, const std::vector<Active> &fresh)
     }
     A.tasks = p.wtasks.d + n_init;
     const int wpp = switchable ? light_global_wpp(*c) : 0;
-    const int dg = switchable ? light_global_dg(*c, d, n_step) : 1;
     const bool ps = prime_split(*c, d, n_step);
+    const int dg = switchable ? light_global_dg(*c, d, n_step) : ps ? prime_split_dg(*c, d, n_step) : 1;
     for (uint32_t s = 0; s < chunk; s++) {
         A.step = s;
         A.acc_rd = arena[p.cur];
