@@ -98,6 +98,16 @@ __global__ __launch_bounds__(256) void k_wide_init(WideArgs A)
 // at N = 16384, the most one workgroup holds.
 constexpr int wide_wpp(int N) { return N > 4096 ? N / 1024 : (N > 512 ? N / 512 : 1); }
 
+// Work item of workgroup b of a grid of g: the hardware deals workgroups to the eight
+// XCDs in turn (b mod 8), each with its own L2; this mapping gives each XCD a contiguous
+// eighth of the items (the rest, g mod 8, in order), so the components of one
+// ciphertext -- which read each other's accumulators through the rotation -- share an L2.
+__device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t g)
+{
+    const uint32_t full = g / 8 * 8;
+    return b < full ? (b % 8) * (full / 8) + b / 8 : b;
+}
+
 // Waves per EU the compiler is asked to leave room for: three (measured best at
 // N = 2048), or what a workgroup of 16 waves leaves anyway.
 constexpr int wide_min_waves(int W) { return W >= 16 ? 4 : 3; }
@@ -108,7 +118,7 @@ constexpr int wide_min_waves(int W) { return W >= 16 ? 4 : 3; }
 // half the dependent chain of a step for a component on one compute unit, the
 // shape for batches that leave compute units idle.
 //
-// PS (two primes): two workgroups per component, one per prime (blockIdx.x = 2 task +
+// PS (two primes): two workgroups per component, one per prime (work item = 2 task +
 // prime): both form the digit fields from both residues, each runs the NTTs, key
 // products and inverse NTT of its own prime and writes that prime's residues --
 // for batches with compute units to spare, half the dependent chain of a step.
@@ -145,13 +155,14 @@ __global__ __launch_bounds__(64 * W * DG) __attribute__((amdgpu_waves_per_eu(wid
     uint64_t *const ylds = lds64 + grp * GS64 + G::SLOTW / 2;
     uint32_t *const slot2 = slot + G::SLOTW;  // DS only (ylds is ternary only)
     int par = 0;                              // relayouts so far: which slot the next one uses
-    const WideTask T = A.tasks[PS ? blockIdx.x / 2 : blockIdx.x];
+    const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
+    const WideTask T = A.tasks[PS ? item / 2 : item];
     const int L = DG > 1 ? (int)(threadIdx.x % (64 * W)) : (int)threadIdx.x;
     constexpr size_t CW = (size_t)2 * NPR * N, PW = (size_t)NPR * N;  // words per component, per part
     const uint32_t *own = A.acc_rd + T.acc_off + (size_t)T.comp * CW;
     uint32_t *wr = A.acc_wr + T.acc_off + (size_t)T.comp * CW;
     // the primes this workgroup computes: both, or its own with PS
-    const int pr_lo = PS ? (int)(blockIdx.x % 2) : 0, pr_hi = PS ? pr_lo + 1 : NPR;
+    const int pr_lo = PS ? (int)(item % 2) : 0, pr_hi = PS ? pr_lo + 1 : NPR;
     const uint32_t i = T.i0 + A.step;  // this task's CMux step
     if (i >= A.n) {
         // past step n - 1 (a ciphertext that finishes inside a sequence of launches):
