@@ -353,11 +353,13 @@ int mm_server_stats(mm_server *s, double *p50_ms, double *p99_ms, double *boots_
                     uint64_t *completed);
 
 /* Admission by expected latency (load shedding): with max_latency_ms > 0,
- * mm_submit refuses a request with MM_EBUSY when the requests queued and in
- * flight, divided by the server's recent completion rate (its last 4096
- * completions, counted up to the time of the call), exceed max_latency_ms: by Little's law the time a request
- * admitted now can expect to wait for its result.  The check starts after 64
- * completions; 0 (the default) admits every request while the queue has room.
+ * mm_submit refuses a request with MM_EBUSY when the requests of its class (at
+ * most 4 components, or wider) queued and in flight, divided by that class's
+ * recent completion rate (its last 4096 completions, counted up to the time of
+ * the call), exceed max_latency_ms: by Little's law the time a request admitted
+ * now can expect to wait for its result.  The check starts after 64 completions
+ * (all classes' requests and completions count until the request's class has
+ * 64); 0 (the default) admits every request while the queue has room.
  * mm_server_refused reports how many requests admission has refused since the
  * server started. */
 int mm_server_set_admission(mm_server *s, double max_latency_ms);

@@ -98,6 +98,7 @@ struct Req {
     int table;
     std::vector<uint32_t> ct;
     clk::time_point t0;
+    int cls;  // 0: at most 4 components, 1: wider
 };
 
 struct Active {
@@ -105,6 +106,7 @@ struct Active {
     int table;
     uint32_t slot, unit, order, step;
     clk::time_point t0;
+    int cls;
 };
 
 struct Result {
@@ -182,12 +184,15 @@ struct Server {
     static constexpr size_t LAT_CAP = size_t(1) << 20;
     uint64_t next_ticket = 1, completed = 0, refused = 0;
     // admission by expected latency (0: off): a request is refused when the
-    // requests queued and in flight, over the recent completion rate (the last
-    // RECENT completions up to now), exceed max_latency_ms (Little's law: that quotient is
-    // the time a request admitted now can expect to wait for its result)
+    // requests of its class (at most 4 components, or wider: each class has a partition
+    // and a rate of its own) queued and in flight, over that class's recent completion
+    // rate (its last RECENT completions up to now), exceed max_latency_ms (Little's law:
+    // that quotient is the time a request admitted now can expect to wait for its
+    // result); until a class has 64 completions, all requests and all completions count
     double max_latency_ms = 0.0;
-    uint64_t in_flight = 0;  // admitted to device slots, result not harvested
-    std::deque<clk::time_point> recent;
+    uint64_t in_flight = 0;             // admitted to device slots, result not harvested
+    uint64_t in_flight_cls[2] = {0, 0};  // the same by class
+    std::deque<clk::time_point> recent, recent_cls[2];
     static constexpr size_t RECENT = 4096;
     bool have_first = false;
     clk::time_point t_first, t_last;
@@ -319,19 +324,26 @@ uint64_t Server::submit(int table, const uint32_t *ct, clk::time_point t0, int *
         *rc = MM_EBUSY;
         return 0;
     }
-    if (max_latency_ms > 0 && recent.size() >= 64) {
+    if (max_latency_ms > 0) {
         // completions arrive in bursts (a tick at a time): the rate is taken up to now,
         // not up to the last burst, over a window of several ticks
-        const double span = std::chrono::duration<double, std::milli>(clk::now() - recent.front()).count();
-        const double per_ms = span > 0 ? (double)recent.size() / span : 0.0;
-        const double backlog = (double)(pending[0].size() + pending[1].size() + in_flight);
-        if (per_ms > 0 && backlog / per_ms > max_latency_ms) {
+        const auto now = clk::now();
+        auto expected_ms = [&](const std::deque<clk::time_point> &rec, double backlog) {
+            const double span = std::chrono::duration<double, std::milli>(now - rec.front()).count();
+            return span > 0 ? backlog * span / (double)rec.size() : 0.0;
+        };
+        double e = 0.0;
+        if (recent_cls[cls].size() >= 64)
+            e = expected_ms(recent_cls[cls], (double)(pending[cls].size() + in_flight_cls[cls]));
+        else if (recent.size() >= 64)
+            e = expected_ms(recent, (double)(pending[0].size() + pending[1].size() + in_flight));
+        if (e > max_latency_ms) {
             refused++;
             *rc = MM_EBUSY;
             return 0;
         }
     }
-    Req r{next_ticket++, table, std::vector<uint32_t>(ct, ct + W), t0};
+    Req r{next_ticket++, table, std::vector<uint32_t>(ct, ct + W), t0, cls};
     live.insert(r.ticket);
     if (!have_first) {
         have_first = true;
@@ -365,8 +377,12 @@ bool Server::harvest(Part &p)
         buddy.release(a.unit, a.order);
         completed++;
         in_flight--;
+        const int cls = a.cls;
+        in_flight_cls[cls]--;
         recent.push_back(now);
         if (recent.size() > RECENT) recent.pop_front();
+        recent_cls[cls].push_back(now);
+        if (recent_cls[cls].size() > RECENT) recent_cls[cls].pop_front();
     }
     if (!p.finishing.empty()) t_last = now;
     p.finishing.clear();
@@ -395,9 +411,10 @@ void Server::launch(Part &p)
                 const uint32_t order = order_of(c->tables[q.table].r);
                 const int64_t unit = buddy.alloc(order);
                 if (unit < 0) break;  // no accumulator memory: wait for completions
-                Active a{q.ticket, q.table, free_slots.back(), (uint32_t)unit, order, 0, q.t0};
+                Active a{q.ticket, q.table, free_slots.back(), (uint32_t)unit, order, 0, q.t0, q.cls};
                 free_slots.pop_back();
                 in_flight++;
+                in_flight_cls[q.cls]++;
                 fresh.push_back(a);
                 fresh_req.push_back(std::move(queue.front()));
                 queue.pop_front();
