@@ -5,7 +5,7 @@
 // 1024 components), so it lives in device memory as [component][part][prime][N]
 // residues, double-buffered, and every CMux step is one launch over all
 // (ciphertext, component) pairs: the launch boundary is the barrier between
-// steps.  Workgroup k_wide_step (N / 512 waves) owns one pair for one step:
+// steps.  Workgroup k_wide_step (N / 512 waves by default) owns one pair for one step:
 //   1. reads its own component and the one that Phi(-a'_i) brings to it (index
 //      and sign remap of the source, eq. ex1:BPc), both primes, and forms
 //      D = Phi(-a'_i) ACC_j - ACC_j;
@@ -21,9 +21,13 @@
 // The same kernels, instantiated for one prime (NPR = 1), are the global-
 // accumulator path of the default 31-bit ring modulus: for tables whose r
 // components do not fit one workgroup's LDS (r N / 1024 > 8, e.g. r = 16 at
-// N = 1024) and for rings of degree 16384 (one polynomial over 16 waves), which
-// the fused persistent kernel cannot hold.  Layouts are the wide ones with the
+// N = 1024), for rings of 16384 and more (one polynomial over 16 waves, or the
+// split ring below), which the fused persistent kernel cannot hold, and, with
+// four waves per component at N = 1024, the faster shape for the largest and the
+// lightest batches the fused kernel could hold.  Layouts are the wide ones with the
 // prime index dropped: a component is [part][N], key blocks [n][keys][2l][2][N].
+// Variants: two digit groups per workgroup (DG), one workgroup per prime (PS), and
+// an XCD-aware order of work items (xcd_item).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
