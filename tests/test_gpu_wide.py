@@ -225,7 +225,8 @@ def test_wide_empty_and_rejected_calls():
         c.ctx.server_start(1 << 10)  # below one component's two accumulators
 
 
-@pytest.mark.parametrize("N,ternary,r,count", [(256, False, 2, 70), (2048, True, 1, 3), (512, True, 4, 80)])
+@pytest.mark.parametrize("N,ternary,r,count", [(256, False, 2, 70), (2048, True, 1, 3), (512, True, 4, 80),
+                                                (1024, False, 3, 12), (1024, True, 1, 2)])
 def test_wide_schedules_give_the_same_bits_and_autotune(N, ternary, r, count):
     """At the wide modulus the blind rotation has two shapes (reported as 0 waves per
     fused group, one workgroup of N / 512 waves per component): one workgroup per
